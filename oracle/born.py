@@ -1,0 +1,45 @@
+"""Born charges Z_A = d mu / d R_A (oracle).
+
+The nuclear force of the paper carries the dipole derivative d mu_n / d r_{n,j}
+(Theory: the forces F^m; Results: the Born charges are its bottleneck and are
+obtained by finite differences of the SCC dipole).  Two forms:
+
+  Mulliken replacement (Results, the cheap substitute):   Z_A = Q_A I_3
+  Exact by central finite differences of the converged SCC dipole:
+      Z_A[a][b] = (mu_a(R + h e_{A b}) - mu_a(R - h e_{A b})) / (2 h)
+
+Layout: Z[A][a][b] = d mu_a / d R_{A b}.  Displaced SCCs are warm-started from
+the undisplaced charges.
+
+Pinned by: acoustic sum rule sum_A Z_A = 0 for a neutral unit, the rotational
+sum rule sum_A Z_A (theta x R_A) = theta x mu, the C2v pattern of a symmetric
+monomer in its own frame (tests/test_oracle_born.py).
+"""
+import numpy as np
+
+from .scc import scc_unit
+
+
+def born_mulliken(charges):
+    charges = np.asarray(charges, dtype=np.float64)
+    return charges[:, None, None] * np.eye(3)[None, :, :]
+
+
+def born_fd(params, species, pos, h=1.0e-3, tol=1e-12, max_iter=200, dq_center=None):
+    """Returns (Z (Na,3,3), worst SCC status over the 6 Na displaced runs)."""
+    pos = np.asarray(pos, dtype=np.float64)
+    na = len(species)
+    Z = np.zeros((na, 3, 3))
+    worst = 0
+    for a in range(na):
+        for b in range(3):
+            mus = []
+            for sgn in (1.0, -1.0):
+                x = pos.copy()
+                x[a, b] += sgn * h
+                r = scc_unit(params, species, x, tol=tol, max_iter=max_iter, dq_start=dq_center,
+                             want_forces=False)
+                worst |= r["status"]
+                mus.append(r["dipole"])
+            Z[a, :, b] = (mus[0] - mus[1]) / (2.0 * h)
+    return Z, worst
