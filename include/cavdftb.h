@@ -1,0 +1,194 @@
+/*
+ * cavdftb: batched SCC-DFTB matter + multimode Fabry-Perot cavity dynamics on
+ * MI355X (gfx950).  C ABI over a HIP shared library (libcavdftb.so).
+ *
+ * The method is that of Wickramasinghe, Amini and Mandal, "On-the-Fly
+ * Cavity-Molecular Dynamics of Vibrational Polaritons" (arXiv 2512.03277):
+ * many independent molecular cells (Theory, Eq. hm), each described by
+ * second-order SCC-DFTB (Computational details), coupled through their
+ * projected dipoles to cavity modes whose mode functions depend on the cell
+ * position along the cavity axis (Theory, Eq. hlm_bigin and the mode function
+ * f_k(R_n)), propagated by the velocity-Verlet-like scheme with an exact free
+ * photon rotation (Theory, Step 1 Eq. pj1 and Step 3 Eq. qknk).
+ *
+ * Conventions shared by every call
+ *   - Atomic units throughout (bohr, hartree, a.u. of time, electron mass).
+ *   - All arrays are FP64 unless typed otherwise, owned by the caller.
+ *   - Pointers marked "device" are HIP device pointers (for instance torch
+ *     tensor data pointers on the same GPU); pointers marked "host" are read
+ *     during the call only.
+ *   - Every call is asynchronous on the HIP stream given at creation, except
+ *     cavdftb_create, cavdftb_destroy and cavdftb_sync, which synchronise.
+ *   - The library allocates all of its workspaces in cavdftb_create; no later
+ *     call allocates device memory.
+ *   - Return codes: CAVDFTB_OK or a negative CAVDFTB_E* value; no C++
+ *     exception crosses the ABI and the library never aborts.  Per-unit
+ *     failures are reported in unit_status bit masks (CAVDFTB_ST_*); they do
+ *     not make the call fail.  cavdftb_last_error returns a readable reason.
+ *   - Units are given in CSR form (unit_atom_off); atom order inside a unit is
+ *     free; species 0 = O (orbitals s, px, py, pz), 1 = H (s).  A unit may
+ *     hold at most 64 orbitals (32 water molecules need 192: see
+ *     CAVDFTB_MAX_ORBITALS) and its orbital count must be even.
+ */
+#ifndef CAVDFTB_H
+#define CAVDFTB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CAVDFTB_OK 0
+#define CAVDFTB_EINVAL (-1)
+#define CAVDFTB_ENOMEM (-2)
+#define CAVDFTB_EHIP (-3)
+
+/* unit_status bits */
+#define CAVDFTB_ST_NOT_CONVERGED 1 /* SCC hit max_iter before reaching tol */
+#define CAVDFTB_ST_NOT_PD 2        /* overlap matrix not positive definite */
+#define CAVDFTB_ST_DEGENERATE 4    /* HOMO-LUMO gap below 1e-6 hartree */
+#define CAVDFTB_ST_NAN 8           /* non-finite position or charge */
+
+/* Born-charge modes */
+#define CAVDFTB_BORN_MULLIKEN 0 /* Z_A = Q_A I (the paper's cheap replacement, Results) */
+#define CAVDFTB_BORN_FD 1       /* central finite differences of the SCC dipole (Results) */
+
+#define CAVDFTB_MAX_ORBITALS 64
+
+/* Synthetic SCC-DFTB parameter set.  Table index t (0..6): O-O ss sigma,
+ * O-O sp sigma, O-O pp sigma, O-O pp pi, O-H (s_H s_O) sigma,
+ * O-H (s_H p_O) sigma, H-H ss sigma; sk[t] = {a, b, c, d} with hopping
+ * a exp(-b r) and overlap c exp(-d r).  Pair types for repulsion
+ * A exp(-alpha r): 0 = O-O, 1 = O-H, 2 = H-H. */
+typedef struct cavdftb_params {
+  double sk[7][4];
+  double onsite[2][2]; /* [species][l]: O {eps_s, eps_p}, H {eps_s, unused} */
+  double hubbard_u[2]; /* U_O, U_H (hartree); gamma uses tau = 16 U / 5 */
+  double q0[2];        /* neutral valence populations: O 6, H 1 */
+  double rep_a[3];
+  double rep_alpha[3];
+  double mass[2]; /* nuclear masses (electron masses) */
+} cavdftb_params;
+
+/* Static description of the batch and of the cavity (all host pointers,
+ * copied to the device by cavdftb_create). */
+typedef struct cavdftb_layout {
+  int32_t n_units;
+  int32_t n_atoms;
+  int32_t n_modes;
+  const int32_t* unit_atom_off; /* [n_units+1] CSR offsets into the atom arrays */
+  const int8_t* species;        /* [n_atoms] */
+  const double* unit_x;         /* [n_units] cell position X_n along the cavity axis */
+  const double* omega;          /* [n_modes] mode frequencies omega_m */
+  const double* k;              /* [n_modes] wave numbers k_m */
+  const double* theta;          /* [n_modes] phases; phi_m(X) = sin(k_m X + theta_m) */
+  const double* lam;            /* [n_modes] couplings lambda_m (eta = lambda omega for one box) */
+  double pol[3];                /* cavity polarisation e (unit vector) */
+} cavdftb_layout;
+
+typedef struct cavdftb_ctx cavdftb_ctx;
+
+/* Create a context for a fixed batch layout.  hip_stream is a hipStream_t (or
+ * NULL for the null stream) on the current device.  Allocates every workspace
+ * (device memory ~ sum over units of 3 n_u^2 doubles plus O(atoms + modes)).
+ * Returns CAVDFTB_EINVAL for inconsistent layouts (non-monotone offsets,
+ * species outside {0,1}, an odd orbital count, more than 64 orbitals), and
+ * CAVDFTB_ENOMEM / CAVDFTB_EHIP on allocation failure. */
+int cavdftb_create(const cavdftb_params* params, const cavdftb_layout* layout, void* hip_stream,
+                   cavdftb_ctx** out);
+int cavdftb_destroy(cavdftb_ctx* ctx);
+
+/* SCC controls (defaults tol 1e-8, max_iter 200, mix_alpha 0.2): Johnson's
+ * modified Broyden mixing of the atomic charges with inverse-Jacobian weight
+ * w0 = 0.01 and at most 20 stored iterations; converged when
+ * max_A |Dq_out - Dq_in| < tol. */
+int cavdftb_set_scc(cavdftb_ctx* ctx, double tol, int32_t max_iter, double mix_alpha);
+
+/* Warm start: when enabled (default 1) each unit evaluation starts from the
+ * charges and the molecular-orbital basis its previous evaluation stored.
+ * cavdftb_reset_warm_start forgets them (the next evaluation starts cold). */
+int cavdftb_set_warm_start(cavdftb_ctx* ctx, int32_t enable);
+int cavdftb_reset_warm_start(cavdftb_ctx* ctx);
+
+/* SCC-DFTB of every unit at positions pos (device [n_atoms][3]): the matter
+ * potential V_n, its forces and the cell dipole (Theory: the -grad V_n term
+ * and mu_n of Eq. dpj; Computational details: second-order SCC-DFTB).
+ * Outputs (device, any may be NULL except unit_status):
+ *   energy [n_units]        E_n = Tr(P H0) + 1/2 Dq gamma Dq + E_rep
+ *   forces [n_atoms][3]     -dE_n/dR
+ *   charges [n_atoms]       Mulliken net charges Q_A = -(q_A - q0_A)
+ *   dipole [n_units][3]     mu_n = sum_A Q_A R_A
+ *   unit_status [n_units]   CAVDFTB_ST_* bits */
+int cavdftb_eval_units(cavdftb_ctx* ctx, const double* pos, double* energy, double* forces, double* charges,
+                       double* dipole, int32_t* unit_status);
+
+/* Born charges born[A][a][b] = d mu_a / d R_{A b} (device [n_atoms][3][3]) at
+ * positions pos (device).  mode CAVDFTB_BORN_MULLIKEN: Q_A delta_ab from one
+ * SCC per unit; CAVDFTB_BORN_FD: central differences with step h (bohr) of the
+ * converged SCC dipole, 6 n_atoms displaced SCCs per unit batched in one
+ * launch, warm-started from the undisplaced solution (Results: the Born
+ * charges are the bottleneck and are taken by finite differences).
+ * ens_std is reserved and must be NULL. */
+int cavdftb_born_charges(cavdftb_ctx* ctx, const double* pos, int32_t mode, double h, double* born,
+                         double* ens_std, int32_t* unit_status);
+
+/* Cavity coupling for given projected dipoles mu_pol[n_units] = e . mu_n and
+ * photon coordinates q[n_modes] (all device):
+ *   F[m]     = sum_n phi_m(X_n) mu_pol[n]                        (dipole sums)
+ *   field[n] = sum_m lambda_m omega_m phi_m(X_n) (q_m + lambda_m F_m / omega_m)
+ *   fq[m]    = -lambda_m omega_m F_m          (photon coupling force, Eq. dpj)
+ * Any output may be NULL.  (Theory: Eq. hlm_bigin with real standing-wave
+ * mode functions; the nuclear force is -field[n] (e . Z_A).) */
+int cavdftb_cavity_forces(cavdftb_ctx* ctx, const double* mu_pol, const double* q, double* F, double* field,
+                          double* fq);
+
+/* Photon start at frozen matter (Step 0 reading): q_m = -lambda_m F_m/omega_m,
+ * p_m = 0, with F from one SCC evaluation at r (device). */
+int cavdftb_init_photons(cavdftb_ctx* ctx, const double* r, double* qm, double* pm);
+
+/* Advance n_steps MD steps of length dt in place on device state r, p
+ * [n_atoms][3] (positions, momenta) and qm, pm [n_modes]:
+ *   p_m -= dt/2 lambda omega F(t); p += dt/2 (-dV/dr - E_n e.Z); r += dt p/m;
+ *   matter at r(t+dt); p += dt/2 (-dV/dr - E'_n e.Z) with E' from the old q;
+ *   p_m -= dt/2 lambda omega F(t+dt); exact rotation of (q_m, p_m) by omega dt
+ * (Theory, Step 1 Eq. pj1 and Step 3 Eq. qknk, in mode space).  born_mode as
+ * in cavdftb_born_charges, with fd step h_fd.  The forces at r(t) are those of
+ * the previous call on the same context, or are evaluated first when the
+ * context has not stepped yet (or after cavdftb_invalidate).
+ * obs (device [n_steps][CAVDFTB_N_OBS] or NULL) receives per step:
+ *   0 kinetic, 1 matter potential, 2 photon energy, 3 total, 4 mean per-unit
+ *   temperature (K, centre-of-mass motion removed), 5 units with a nonzero
+ *   status, 6 SCC iterations summed over units, 7 sum_n e.mu_n. */
+#define CAVDFTB_N_OBS 8
+int cavdftb_step(cavdftb_ctx* ctx, double* r, double* p, double* qm, double* pm, int32_t n_steps, double dt,
+                 int32_t born_mode, double h_fd, double* obs);
+int cavdftb_invalidate(cavdftb_ctx* ctx);
+
+/* Wait for the context stream; n_bad_units (host, may be NULL) receives the
+ * number of units whose last evaluation set a status bit. */
+int cavdftb_sync(cavdftb_ctx* ctx, int32_t* n_bad_units);
+
+/* Device-side counters since creation or the last reset: SCC evaluations
+ * (jobs), SCC iterations, and the algorithmic FP64 flop count of the SCC
+ * kernels (per iteration 10 n^3 + 2 n^2 n_occ, per geometry n^3/3 + 2 n^2 n_occ),
+ * plus the summed duration of SCC-kernel launches timed with HIP events on the
+ * context stream when timing is enabled.  Host outputs; synchronises. */
+typedef struct cavdftb_counters {
+  int64_t scc_jobs;
+  int64_t scc_iterations;
+  double scc_flops;
+  double scc_kernel_ms;
+  int64_t scc_launches;
+} cavdftb_counters;
+int cavdftb_enable_timing(cavdftb_ctx* ctx, int32_t enable);
+int cavdftb_read_counters(cavdftb_ctx* ctx, cavdftb_counters* out);
+int cavdftb_reset_counters(cavdftb_ctx* ctx);
+
+const char* cavdftb_last_error(const cavdftb_ctx* ctx);
+const char* cavdftb_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,11 @@
+"""MI355X-native batched SCC-DFTB + multimode cavity molecular dynamics.
+
+The compute path is libcavdftb.so (hand-written HIP kernels for gfx950, C ABI
+declared in include/cavdftb.h); `binding` is its thin ctypes wrapper.  There is
+no CPU fallback: using the binding without the built library raises.
+"""
+from .binding import (BORN_FD, BORN_MULLIKEN, N_OBS, OBS_NAMES, CavdftbError, Context, context_from_system,
+                      load_library, LIB_PATH, SYMBOLS)
+
+__all__ = ["BORN_FD", "BORN_MULLIKEN", "N_OBS", "OBS_NAMES", "CavdftbError", "Context", "context_from_system",
+           "load_library", "LIB_PATH", "SYMBOLS"]

@@ -1,0 +1,237 @@
+"""ctypes binding of libcavdftb (argument marshalling only).
+
+Every method forwards to the C function of the same name in include/cavdftb.h;
+torch CUDA (HIP) tensors supply device memory and the current stream.  No
+arithmetic of the method happens here.  The library must be built (see
+__graft_entry__.build); importing this module without it raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcavdftb.so")
+
+OK, EINVAL, ENOMEM, EHIP = 0, -1, -2, -3
+ST_NOT_CONVERGED, ST_NOT_PD, ST_DEGENERATE, ST_NAN = 1, 2, 4, 8
+BORN_MULLIKEN, BORN_FD = 0, 1
+N_OBS = 8
+OBS_NAMES = ("kinetic", "potential", "photon", "total", "temperature", "n_bad_units", "scc_iterations",
+             "sum_mu_pol")
+
+_c_d = ctypes.c_double
+_c_i32 = ctypes.c_int32
+_vp = ctypes.c_void_p
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("sk", (_c_d * 4) * 7), ("onsite", (_c_d * 2) * 2), ("hubbard_u", _c_d * 2), ("q0", _c_d * 2),
+                ("rep_a", _c_d * 3), ("rep_alpha", _c_d * 3), ("mass", _c_d * 2)]
+
+
+class Layout(ctypes.Structure):
+    _fields_ = [("n_units", _c_i32), ("n_atoms", _c_i32), ("n_modes", _c_i32), ("unit_atom_off", _vp),
+                ("species", _vp), ("unit_x", _vp), ("omega", _vp), ("k", _vp), ("theta", _vp), ("lam", _vp),
+                ("pol", _c_d * 3)]
+
+
+class Counters(ctypes.Structure):
+    _fields_ = [("scc_jobs", ctypes.c_int64), ("scc_iterations", ctypes.c_int64), ("scc_flops", _c_d),
+                ("scc_kernel_ms", _c_d), ("scc_launches", ctypes.c_int64)]
+
+
+SYMBOLS = {
+    "cavdftb_create": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.POINTER(Layout), _vp, ctypes.POINTER(_vp)]),
+    "cavdftb_destroy": (ctypes.c_int, [_vp]),
+    "cavdftb_set_scc": (ctypes.c_int, [_vp, _c_d, _c_i32, _c_d]),
+    "cavdftb_set_warm_start": (ctypes.c_int, [_vp, _c_i32]),
+    "cavdftb_reset_warm_start": (ctypes.c_int, [_vp]),
+    "cavdftb_eval_units": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "cavdftb_born_charges": (ctypes.c_int, [_vp, _vp, _c_i32, _c_d, _vp, _vp, _vp]),
+    "cavdftb_cavity_forces": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "cavdftb_init_photons": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "cavdftb_step": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _c_i32, _c_d, _c_i32, _c_d, _vp]),
+    "cavdftb_invalidate": (ctypes.c_int, [_vp]),
+    "cavdftb_sync": (ctypes.c_int, [_vp, ctypes.POINTER(_c_i32)]),
+    "cavdftb_enable_timing": (ctypes.c_int, [_vp, _c_i32]),
+    "cavdftb_read_counters": (ctypes.c_int, [_vp, ctypes.POINTER(Counters)]),
+    "cavdftb_reset_counters": (ctypes.c_int, [_vp]),
+    "cavdftb_last_error": (ctypes.c_char_p, [_vp]),
+    "cavdftb_version": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def load_library():
+    """Load libcavdftb.so from the package directory (raises if it is missing)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run `python -c 'import __graft_entry__ as g; g.build()'`")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SYMBOLS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+class CavdftbError(RuntimeError):
+    pass
+
+
+def _ptr(t, dtype=None, numel=None, name="tensor"):
+    """Device pointer of a contiguous CUDA tensor (or None -> NULL)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise CavdftbError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise CavdftbError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise CavdftbError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() != numel:
+        raise CavdftbError(f"{name} must have {numel} elements, got {t.numel()}")
+    return t.data_ptr()
+
+
+def params_struct(p):
+    s = Params()
+    for t in range(7):
+        for j in range(4):
+            s.sk[t][j] = float(p["sk"][t][j])
+    for a in range(2):
+        for b in range(2):
+            s.onsite[a][b] = float(p["onsite"][a][b])
+        s.hubbard_u[a] = float(p["hubbard_u"][a])
+        s.q0[a] = float(p["q0"][a])
+        s.mass[a] = float(p["mass"][a])
+    for t in range(3):
+        s.rep_a[t] = float(p["rep_a"][t])
+        s.rep_alpha[t] = float(p["rep_alpha"][t])
+    return s
+
+
+class Context:
+    """A library context for one batch layout (units, species, cavity modes)."""
+
+    def __init__(self, params, species, unit_off, unit_x, omega, k, theta, lam, pol, stream=None):
+        import torch
+        self.torch = torch
+        self.lib = load_library()
+        self._host = {
+            "unit_off": np.ascontiguousarray(unit_off, dtype=np.int32),
+            "species": np.ascontiguousarray(species, dtype=np.int8),
+            "unit_x": np.ascontiguousarray(unit_x, dtype=np.float64),
+            "omega": np.ascontiguousarray(omega, dtype=np.float64),
+            "k": np.ascontiguousarray(k, dtype=np.float64),
+            "theta": np.ascontiguousarray(theta, dtype=np.float64),
+            "lam": np.ascontiguousarray(lam, dtype=np.float64),
+        }
+        h = self._host
+        self.n_units = len(h["unit_off"]) - 1
+        self.n_atoms = int(h["unit_off"][-1])
+        self.n_modes = len(h["omega"])
+        L = Layout()
+        L.n_units, L.n_atoms, L.n_modes = self.n_units, self.n_atoms, self.n_modes
+        for key in ("unit_off", "species", "unit_x", "omega", "k", "theta", "lam"):
+            setattr(L, "unit_atom_off" if key == "unit_off" else key, h[key].ctypes.data)
+        for g in range(3):
+            L.pol[g] = float(pol[g])
+        self.stream = torch.cuda.current_stream() if stream is None else stream
+        P = params_struct(params)
+        out = _vp()
+        rc = self.lib.cavdftb_create(ctypes.byref(P), ctypes.byref(L), _vp(self.stream.cuda_stream), ctypes.byref(out))
+        if rc != OK:
+            raise CavdftbError(f"cavdftb_create failed with code {rc}")
+        self.ctx = out
+
+    def _check(self, rc, what):
+        if rc != OK:
+            msg = self.lib.cavdftb_last_error(self.ctx)
+            raise CavdftbError(f"{what} failed ({rc}): {msg.decode() if msg else ''}")
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.cavdftb_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- entry points (same names as the C ABI without the prefix)
+    def set_scc(self, tol, max_iter=200, mix_alpha=0.2):
+        self._check(self.lib.cavdftb_set_scc(self.ctx, float(tol), int(max_iter), float(mix_alpha)), "set_scc")
+
+    def set_warm_start(self, enable):
+        self._check(self.lib.cavdftb_set_warm_start(self.ctx, int(bool(enable))), "set_warm_start")
+
+    def reset_warm_start(self):
+        self._check(self.lib.cavdftb_reset_warm_start(self.ctx), "reset_warm_start")
+
+    def eval_units(self, pos, energy=None, forces=None, charges=None, dipole=None, unit_status=None):
+        t = self.torch
+        U, NA = self.n_units, self.n_atoms
+        self._check(self.lib.cavdftb_eval_units(
+            self.ctx, _ptr(pos, t.float64, NA * 3, "pos"), _ptr(energy, t.float64, U, "energy"),
+            _ptr(forces, t.float64, NA * 3, "forces"), _ptr(charges, t.float64, NA, "charges"),
+            _ptr(dipole, t.float64, U * 3, "dipole"), _ptr(unit_status, t.int32, U, "unit_status")), "eval_units")
+
+    def born_charges(self, pos, mode, h, born, unit_status=None):
+        t = self.torch
+        self._check(self.lib.cavdftb_born_charges(
+            self.ctx, _ptr(pos, t.float64, self.n_atoms * 3, "pos"), int(mode), float(h),
+            _ptr(born, t.float64, self.n_atoms * 9, "born"), None,
+            _ptr(unit_status, t.int32, self.n_units, "unit_status")), "born_charges")
+
+    def cavity_forces(self, mu_pol, q, F=None, field=None, fq=None):
+        t = self.torch
+        U, M = self.n_units, self.n_modes
+        self._check(self.lib.cavdftb_cavity_forces(
+            self.ctx, _ptr(mu_pol, t.float64, U, "mu_pol"), _ptr(q, t.float64, M, "q"), _ptr(F, t.float64, M, "F"),
+            _ptr(field, t.float64, U, "field"), _ptr(fq, t.float64, M, "fq")), "cavity_forces")
+
+    def init_photons(self, r, qm, pm):
+        t = self.torch
+        self._check(self.lib.cavdftb_init_photons(
+            self.ctx, _ptr(r, t.float64, self.n_atoms * 3, "r"), _ptr(qm, t.float64, self.n_modes, "qm"),
+            _ptr(pm, t.float64, self.n_modes, "pm")), "init_photons")
+
+    def step(self, r, p, qm, pm, n_steps, dt, born_mode=BORN_MULLIKEN, h_fd=1e-3, obs=None):
+        t = self.torch
+        NA, M = self.n_atoms, self.n_modes
+        self._check(self.lib.cavdftb_step(
+            self.ctx, _ptr(r, t.float64, NA * 3, "r"), _ptr(p, t.float64, NA * 3, "p"),
+            _ptr(qm, t.float64, M, "qm"), _ptr(pm, t.float64, M, "pm"), int(n_steps), float(dt), int(born_mode),
+            float(h_fd), _ptr(obs, t.float64, int(n_steps) * N_OBS, "obs")), "step")
+
+    def invalidate(self):
+        self._check(self.lib.cavdftb_invalidate(self.ctx), "invalidate")
+
+    def sync(self):
+        nb = _c_i32(0)
+        self._check(self.lib.cavdftb_sync(self.ctx, ctypes.byref(nb)), "sync")
+        return nb.value
+
+    def enable_timing(self, enable=True):
+        self._check(self.lib.cavdftb_enable_timing(self.ctx, int(bool(enable))), "enable_timing")
+
+    def read_counters(self):
+        c = Counters()
+        self._check(self.lib.cavdftb_read_counters(self.ctx, ctypes.byref(c)), "read_counters")
+        return {k: getattr(c, k) for k, _ in Counters._fields_}
+
+    def reset_counters(self):
+        self._check(self.lib.cavdftb_reset_counters(self.ctx), "reset_counters")
+
+
+def context_from_system(params, system, stream=None):
+    """Convenience constructor from a cavgen system dictionary."""
+    return Context(params, system["species"], system["unit_off"], system["unit_x"], system["omega"], system["k"],
+                   system["theta"], system["lam"], system["pol"], stream=stream)

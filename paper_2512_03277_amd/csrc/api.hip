@@ -1,0 +1,664 @@
+// Host side of the C ABI: context, workspaces, job lists, and the MD step
+// schedule.  Every computation is done by the kernels of scc_kernel.hip and
+// md_kernels.hip on the context stream; the host only sequences launches.
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "internal.h"
+
+using namespace cavdftb;
+
+namespace {
+
+__global__ void ws_identity_kernel(double* ws, const int64_t* ws_off, const int32_t* unit_off,
+                                   const int8_t* species, int n_units, int nmax_of_unit_stride_dummy) {
+  (void)nmax_of_unit_stride_dummy;
+  const int u = blockIdx.x;
+  if (u >= n_units) return;
+  int n = 0;
+  for (int a = unit_off[u]; a < unit_off[u + 1]; ++a) n += species[a] == 0 ? 4 : 1;
+  const int nmax = n <= 8 ? 8 : n <= 16 ? 16 : n <= 32 ? 32 : n <= 48 ? 48 : 64;
+  double* w = ws + ws_off[u];
+  for (int e = threadIdx.x; e < nmax * nmax; e += blockDim.x) w[e] = (e / nmax == e % nmax) ? 1.0 : 0.0;
+}
+
+int bucket_of(int n) { return n <= 8 ? 8 : n <= 16 ? 16 : n <= 32 ? 32 : n <= 48 ? 48 : 64; }
+
+struct Bucket {
+  int nmax = 0;
+  int n_units = 0;
+  int n_wg = 0;
+  int64_t scratch_per_wg = 0;
+  int32_t* d_units = nullptr;  // center jobs: unit list
+  int cjob0 = 0;               // offset of this bucket's center jobs in the center job arrays
+  // finite-difference Born jobs
+  int n_fd_jobs = 0;
+  int fjob0 = 0;               // offset in the fd job arrays
+  int32_t* d_fd_job_unit = nullptr;
+  int32_t* d_fd_job_disp = nullptr;
+  int32_t* d_fd_unit = nullptr;  // [n_units] unit of each fd block
+  int32_t* d_fd_job0 = nullptr;  // [n_units] first fd job (relative to this bucket's mu_job base)
+  double* d_scratch = nullptr;
+};
+
+}  // namespace
+
+struct cavdftb_ctx {
+  hipStream_t stream = nullptr;
+  DevParams prm{};
+  double mass[2] = {0, 0};
+  int U = 0, NA = 0, M = 0;
+  double pol[3] = {0, 0, 1};
+  std::vector<int32_t> h_unit_off;
+  int32_t* d_unit_off = nullptr;
+  int8_t* d_species = nullptr;
+  double *d_unit_x = nullptr, *d_omega = nullptr, *d_k = nullptr, *d_theta = nullptr, *d_lam = nullptr;
+  int32_t* d_atom_unit = nullptr;
+  double *d_mass = nullptr, *d_inv_mass = nullptr;
+  int64_t* d_ws_off = nullptr;
+  double* d_ws_C = nullptr;
+  double* d_ws_dq = nullptr;
+  std::vector<Bucket> buckets;
+  int n_fd_total = 0;
+  // work arrays
+  double *d_energy = nullptr, *d_forces = nullptr, *d_charges = nullptr, *d_dipole = nullptr;
+  double *d_mu_pol = nullptr, *d_F = nullptr, *d_fq = nullptr, *d_field = nullptr, *d_zpol = nullptr;
+  double* d_mu_job = nullptr;
+  int32_t *d_status = nullptr, *d_cjob_status = nullptr, *d_cjob_iters = nullptr;
+  int32_t *d_fjob_status = nullptr, *d_fjob_iters = nullptr;
+  unsigned long long* d_counters = nullptr;
+  std::vector<void*> allocs;
+  // controls
+  double tol = 1e-8;
+  int32_t max_iter = 200;
+  double alpha = 0.2;
+  double w0 = 0.01;
+  int warm_enabled = 1;
+  bool warm_valid = false;
+  bool primed = false;
+  // timing
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending, ev_free;
+  double t_ms = 0.0;
+  int64_t launches = 0;
+  std::string err;
+};
+
+namespace {
+
+int fail(cavdftb_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+int hip_fail(cavdftb_ctx* c, hipError_t e, const char* where) {
+  return fail(c, CAVDFTB_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+template <typename T>
+hipError_t dalloc(cavdftb_ctx* c, T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+  if (e == hipSuccess) c->allocs.push_back((void*)*p);
+  return e;
+}
+
+void release(cavdftb_ctx* c) {
+  if (c->stream) hipStreamSynchronize(c->stream);
+  for (void* p : c->allocs) hipFree(p);
+  c->allocs.clear();
+  for (auto& pr : c->ev_pending) {
+    hipEventDestroy(pr.first);
+    hipEventDestroy(pr.second);
+  }
+  for (auto& pr : c->ev_free) {
+    hipEventDestroy(pr.first);
+    hipEventDestroy(pr.second);
+  }
+  c->ev_pending.clear();
+  c->ev_free.clear();
+}
+
+void harvest_events(cavdftb_ctx* c) {
+  for (auto& pr : c->ev_pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(pr.second) == hipSuccess && hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess)
+      c->t_ms += ms;
+    c->ev_free.push_back(pr);
+  }
+  c->ev_pending.clear();
+}
+
+std::pair<hipEvent_t, hipEvent_t> get_events(cavdftb_ctx* c) {
+  if (c->ev_free.empty()) {
+    hipEvent_t a = nullptr, b = nullptr;
+    hipEventCreate(&a);
+    hipEventCreate(&b);
+    return {a, b};
+  }
+  auto pr = c->ev_free.back();
+  c->ev_free.pop_back();
+  return pr;
+}
+
+SccArgs base_args(cavdftb_ctx* c, const double* pos) {
+  SccArgs a{};
+  a.prm = c->prm;
+  a.pos = pos;
+  a.unit_off = c->d_unit_off;
+  a.species = c->d_species;
+  a.ws_off = c->d_ws_off;
+  a.ws_C = c->d_ws_C;
+  a.ws_dq = c->d_ws_dq;
+  a.counters = c->d_counters;
+  a.tol = c->tol;
+  a.max_iter = c->max_iter;
+  a.alpha = c->alpha;
+  a.w0 = c->w0;
+  return a;
+}
+
+int run_scc(cavdftb_ctx* c, const Bucket& b, SccArgs& a) {
+  if (a.n_jobs <= 0) return CAVDFTB_OK;
+  a.scratch = b.d_scratch;
+  a.scratch_per_wg = b.scratch_per_wg;
+  const int n_wg = a.n_jobs < b.n_wg ? a.n_jobs : b.n_wg;
+  std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+  if (c->timing) {
+    if (c->ev_pending.size() > 4096) harvest_events(c);
+    ev = get_events(c);
+    hipEventRecord(ev.first, c->stream);
+  }
+  hipError_t e = launch_scc(b.nmax, n_wg, a, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "scc kernel launch");
+  if (c->timing) {
+    hipEventRecord(ev.second, c->stream);
+    c->ev_pending.push_back(ev);
+  }
+  c->launches += 1;
+  return CAVDFTB_OK;
+}
+
+// SCC of every unit at pos (center jobs); writes the context work arrays
+int eval_center(cavdftb_ctx* c, const double* pos, bool forces) {
+  int32_t flags = JF_STORE | (forces ? JF_FORCES : 0);
+  if (c->warm_enabled && c->warm_valid) flags |= JF_WARM_C | JF_WARM_DQ;
+  for (const Bucket& b : c->buckets) {
+    SccArgs a = base_args(c, pos);
+    a.job_unit = b.d_units;
+    a.job_disp = nullptr;
+    a.n_jobs = b.n_units;
+    a.energy = c->d_energy;
+    a.forces = c->d_forces;
+    a.charges = c->d_charges;
+    a.dipole = c->d_dipole;
+    a.status = c->d_status;
+    a.job_status = c->d_cjob_status + b.cjob0;
+    a.job_iters = c->d_cjob_iters + b.cjob0;
+    a.flags = flags;
+    int rc = run_scc(c, b, a);
+    if (rc) return rc;
+  }
+  c->warm_valid = c->warm_enabled != 0;
+  return CAVDFTB_OK;
+}
+
+// displaced SCCs for the central-difference Born charges; needs eval_center first
+int eval_fd(cavdftb_ctx* c, const double* pos, double h, double* born) {
+  for (const Bucket& b : c->buckets) {
+    SccArgs a = base_args(c, pos);
+    a.job_unit = b.d_fd_job_unit;
+    a.job_disp = b.d_fd_job_disp;
+    a.n_jobs = b.n_fd_jobs;
+    a.fd_h = h;
+    a.mu_job = c->d_mu_job + (int64_t)b.fjob0 * 3;
+    a.job_status = c->d_fjob_status + b.fjob0;
+    a.job_iters = c->d_fjob_iters + b.fjob0;
+    a.flags = JF_WARM_C | JF_WARM_DQ;
+    int rc = run_scc(c, b, a);
+    if (rc) return rc;
+    hipError_t e = launch_born_fd_assemble(c->d_unit_off, b.d_fd_unit, b.d_fd_job0, b.n_units,
+                                           c->d_mu_job + (int64_t)b.fjob0 * 3, h, c->pol,
+                                           c->d_fjob_status + b.fjob0, born, c->d_zpol, c->d_status, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "born fd assemble");
+  }
+  return CAVDFTB_OK;
+}
+
+CavArgs cav_args(cavdftb_ctx* c) {
+  CavArgs a{};
+  a.n_units = c->U;
+  a.n_atoms = c->NA;
+  a.n_modes = c->M;
+  a.unit_x = c->d_unit_x;
+  a.k = c->d_k;
+  a.theta = c->d_theta;
+  a.omega = c->d_omega;
+  a.lam = c->d_lam;
+  for (int g = 0; g < 3; ++g) a.pol[g] = c->pol[g];
+  return a;
+}
+
+// matter + Born stage at r: forces, energy, dipole, e.Z into the work arrays
+int matter_stage(cavdftb_ctx* c, const double* r, int born_mode, double h) {
+  int rc = eval_center(c, r, true);
+  if (rc) return rc;
+  hipError_t e;
+  if (born_mode == CAVDFTB_BORN_FD) {
+    rc = eval_fd(c, r, h, nullptr);
+    if (rc) return rc;
+  } else {
+    e = launch_zpol_mulliken(c->d_charges, c->pol, c->NA, c->d_zpol, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "zpol");
+  }
+  e = launch_mu_pol(c->d_dipole, c->pol, c->U, c->d_mu_pol, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "mu_pol");
+  return CAVDFTB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* cavdftb_version(void) { return "cavdftb 0.1 (gfx950)"; }
+
+const char* cavdftb_last_error(const cavdftb_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int cavdftb_create(const cavdftb_params* params, const cavdftb_layout* L, void* hip_stream, cavdftb_ctx** out) {
+  if (!params || !L || !out) return CAVDFTB_EINVAL;
+  *out = nullptr;
+  if (L->n_units <= 0 || L->n_atoms <= 0 || L->n_modes < 0 || !L->unit_atom_off || !L->species || !L->unit_x)
+    return CAVDFTB_EINVAL;
+  if (L->n_modes > 0 && (!L->omega || !L->k || !L->theta || !L->lam)) return CAVDFTB_EINVAL;
+  cavdftb_ctx* c = new (std::nothrow) cavdftb_ctx();
+  if (!c) return CAVDFTB_ENOMEM;
+  c->stream = (hipStream_t)hip_stream;
+  c->U = L->n_units;
+  c->NA = L->n_atoms;
+  c->M = L->n_modes;
+  for (int g = 0; g < 3; ++g) c->pol[g] = L->pol[g];
+  memcpy(c->prm.sk, params->sk, sizeof(c->prm.sk));
+  memcpy(c->prm.onsite, params->onsite, sizeof(c->prm.onsite));
+  memcpy(c->prm.U, params->hubbard_u, sizeof(c->prm.U));
+  memcpy(c->prm.q0, params->q0, sizeof(c->prm.q0));
+  memcpy(c->prm.rep_a, params->rep_a, sizeof(c->prm.rep_a));
+  memcpy(c->prm.rep_alpha, params->rep_alpha, sizeof(c->prm.rep_alpha));
+  c->mass[0] = params->mass[0];
+  c->mass[1] = params->mass[1];
+
+  // ---- validate the layout and size buckets (host)
+  const int U = c->U, NA = c->NA;
+  c->h_unit_off.assign(L->unit_atom_off, L->unit_atom_off + U + 1);
+  if (c->h_unit_off[0] != 0 || c->h_unit_off[U] != NA) {
+    delete c;
+    return CAVDFTB_EINVAL;
+  }
+  std::vector<int> n_orb(U);
+  std::vector<int32_t> atom_unit(NA);
+  std::vector<double> mass(NA), inv_mass(NA);
+  for (int u = 0; u < U; ++u) {
+    const int a0 = c->h_unit_off[u], a1 = c->h_unit_off[u + 1];
+    if (a1 <= a0) {
+      delete c;
+      return CAVDFTB_EINVAL;
+    }
+    int n = 0;
+    for (int a = a0; a < a1; ++a) {
+      const int s = L->species[a];
+      if (s != 0 && s != 1) {
+        delete c;
+        return CAVDFTB_EINVAL;
+      }
+      n += s == 0 ? 4 : 1;
+      atom_unit[a] = u;
+      mass[a] = params->mass[s];
+      inv_mass[a] = 1.0 / params->mass[s];
+    }
+    if (n > CAVDFTB_MAX_ORBITALS || (n & 1)) {
+      delete c;
+      return CAVDFTB_EINVAL;
+    }
+    n_orb[u] = n;
+  }
+  int dev = 0, n_cu = 256;
+  hipGetDevice(&dev);
+  hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (n_cu <= 0) n_cu = 256;
+
+  const int nmaxs[5] = {8, 16, 32, 48, 64};
+  std::vector<int64_t> ws_off(U);
+  int64_t ws_total = 0;
+  std::vector<std::vector<int32_t>> bunits(5);
+  for (int u = 0; u < U; ++u) {
+    const int nm = bucket_of(n_orb[u]);
+    for (int k = 0; k < 5; ++k)
+      if (nmaxs[k] == nm) bunits[k].push_back(u);
+    ws_off[u] = ws_total;
+    ws_total += (int64_t)nm * nm;
+  }
+  hipError_t e = hipSuccess;
+#define CK(x)                                  \
+  do {                                         \
+    e = (x);                                   \
+    if (e != hipSuccess) {                     \
+      release(c);                              \
+      delete c;                                \
+      return e == hipErrorOutOfMemory ? CAVDFTB_ENOMEM : CAVDFTB_EHIP; \
+    }                                          \
+  } while (0)
+  const int M = c->M > 0 ? c->M : 1;
+  CK(dalloc(c, &c->d_unit_off, U + 1));
+  CK(dalloc(c, &c->d_species, NA));
+  CK(dalloc(c, &c->d_unit_x, U));
+  CK(dalloc(c, &c->d_omega, M));
+  CK(dalloc(c, &c->d_k, M));
+  CK(dalloc(c, &c->d_theta, M));
+  CK(dalloc(c, &c->d_lam, M));
+  CK(dalloc(c, &c->d_atom_unit, NA));
+  CK(dalloc(c, &c->d_mass, NA));
+  CK(dalloc(c, &c->d_inv_mass, NA));
+  CK(dalloc(c, &c->d_ws_off, U));
+  CK(dalloc(c, &c->d_ws_C, ws_total));
+  CK(dalloc(c, &c->d_ws_dq, NA));
+  CK(dalloc(c, &c->d_energy, U));
+  CK(dalloc(c, &c->d_forces, (size_t)NA * 3));
+  CK(dalloc(c, &c->d_charges, NA));
+  CK(dalloc(c, &c->d_dipole, (size_t)U * 3));
+  CK(dalloc(c, &c->d_mu_pol, U));
+  CK(dalloc(c, &c->d_F, M));
+  CK(dalloc(c, &c->d_fq, M));
+  CK(dalloc(c, &c->d_field, U));
+  CK(dalloc(c, &c->d_zpol, (size_t)NA * 3));
+  CK(dalloc(c, &c->d_status, U));
+  CK(dalloc(c, &c->d_cjob_status, U));
+  CK(dalloc(c, &c->d_cjob_iters, U));
+  CK(dalloc(c, &c->d_counters, 4));
+  CK(hipMemcpy(c->d_unit_off, c->h_unit_off.data(), (U + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
+  CK(hipMemcpy(c->d_species, L->species, NA, hipMemcpyHostToDevice));
+  CK(hipMemcpy(c->d_unit_x, L->unit_x, U * sizeof(double), hipMemcpyHostToDevice));
+  if (c->M > 0) {
+    CK(hipMemcpy(c->d_omega, L->omega, c->M * sizeof(double), hipMemcpyHostToDevice));
+    CK(hipMemcpy(c->d_k, L->k, c->M * sizeof(double), hipMemcpyHostToDevice));
+    CK(hipMemcpy(c->d_theta, L->theta, c->M * sizeof(double), hipMemcpyHostToDevice));
+    CK(hipMemcpy(c->d_lam, L->lam, c->M * sizeof(double), hipMemcpyHostToDevice));
+  }
+  CK(hipMemcpy(c->d_atom_unit, atom_unit.data(), NA * sizeof(int32_t), hipMemcpyHostToDevice));
+  CK(hipMemcpy(c->d_mass, mass.data(), NA * sizeof(double), hipMemcpyHostToDevice));
+  CK(hipMemcpy(c->d_inv_mass, inv_mass.data(), NA * sizeof(double), hipMemcpyHostToDevice));
+  CK(hipMemcpy(c->d_ws_off, ws_off.data(), U * sizeof(int64_t), hipMemcpyHostToDevice));
+  CK(hipMemset(c->d_ws_dq, 0, NA * sizeof(double)));
+  CK(hipMemset(c->d_counters, 0, 4 * sizeof(unsigned long long)));
+  CK(hipMemset(c->d_status, 0, U * sizeof(int32_t)));
+  CK(hipMemset(c->d_cjob_iters, 0, U * sizeof(int32_t)));
+  CK(hipMemset(c->d_energy, 0, U * sizeof(double)));
+
+  // ---- buckets: unit lists, scratch, finite-difference job lists
+  int cj = 0, fj = 0;
+  for (int k = 0; k < 5; ++k) {
+    if (bunits[k].empty()) continue;
+    Bucket b;
+    b.nmax = nmaxs[k];
+    b.n_units = (int)bunits[k].size();
+    b.cjob0 = cj;
+    cj += b.n_units;
+    b.scratch_per_wg = scc_scratch_per_wg(b.nmax);
+    const int per_cu = scc_blocks_per_cu(b.nmax);
+    b.n_wg = n_cu * per_cu;
+    CK(dalloc(c, &b.d_units, b.n_units));
+    CK(hipMemcpy(b.d_units, bunits[k].data(), b.n_units * sizeof(int32_t), hipMemcpyHostToDevice));
+    CK(dalloc(c, &b.d_scratch, (size_t)b.n_wg * b.scratch_per_wg));
+    std::vector<int32_t> jun, jdisp, fdu, fdj0;
+    for (int u : bunits[k]) {
+      const int na = c->h_unit_off[u + 1] - c->h_unit_off[u];
+      fdu.push_back(u);
+      fdj0.push_back((int32_t)jun.size());
+      for (int a = 0; a < na; ++a)
+        for (int dir = 0; dir < 3; ++dir)
+          for (int sg = 0; sg < 2; ++sg) {
+            jun.push_back(u);
+            jdisp.push_back((a * 3 + dir) * 2 + sg);
+          }
+    }
+    b.n_fd_jobs = (int)jun.size();
+    b.fjob0 = fj;
+    fj += b.n_fd_jobs;
+    CK(dalloc(c, &b.d_fd_job_unit, b.n_fd_jobs));
+    CK(dalloc(c, &b.d_fd_job_disp, b.n_fd_jobs));
+    CK(dalloc(c, &b.d_fd_unit, b.n_units));
+    CK(dalloc(c, &b.d_fd_job0, b.n_units));
+    CK(hipMemcpy(b.d_fd_job_unit, jun.data(), jun.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    CK(hipMemcpy(b.d_fd_job_disp, jdisp.data(), jdisp.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    CK(hipMemcpy(b.d_fd_unit, fdu.data(), fdu.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    CK(hipMemcpy(b.d_fd_job0, fdj0.data(), fdj0.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    c->buckets.push_back(b);
+  }
+  c->n_fd_total = fj;
+  CK(dalloc(c, &c->d_mu_job, (size_t)fj * 3));
+  CK(dalloc(c, &c->d_fjob_status, fj));
+  CK(dalloc(c, &c->d_fjob_iters, fj));
+  hipLaunchKernelGGL(ws_identity_kernel, dim3(U), dim3(256), 0, c->stream, c->d_ws_C, c->d_ws_off, c->d_unit_off,
+                     c->d_species, U, 0);
+  CK(hipGetLastError());
+  CK(hipStreamSynchronize(c->stream));
+#undef CK
+  *out = c;
+  return CAVDFTB_OK;
+}
+
+int cavdftb_destroy(cavdftb_ctx* ctx) {
+  if (!ctx) return CAVDFTB_EINVAL;
+  release(ctx);
+  delete ctx;
+  return CAVDFTB_OK;
+}
+
+int cavdftb_set_scc(cavdftb_ctx* ctx, double tol, int32_t max_iter, double mix_alpha) {
+  if (!ctx) return CAVDFTB_EINVAL;
+  if (!(tol > 0.0) || max_iter < 1 || !(mix_alpha > 0.0) || mix_alpha > 1.0)
+    return fail(ctx, CAVDFTB_EINVAL, "set_scc: need tol > 0, max_iter >= 1, 0 < alpha <= 1");
+  ctx->tol = tol;
+  ctx->max_iter = max_iter;
+  ctx->alpha = mix_alpha;
+  return CAVDFTB_OK;
+}
+
+int cavdftb_set_warm_start(cavdftb_ctx* ctx, int32_t enable) {
+  if (!ctx) return CAVDFTB_EINVAL;
+  ctx->warm_enabled = enable ? 1 : 0;
+  if (!enable) ctx->warm_valid = false;
+  return CAVDFTB_OK;
+}
+
+int cavdftb_reset_warm_start(cavdftb_ctx* ctx) {
+  if (!ctx) return CAVDFTB_EINVAL;
+  ctx->warm_valid = false;
+  return CAVDFTB_OK;
+}
+
+int cavdftb_eval_units(cavdftb_ctx* ctx, const double* pos, double* energy, double* forces, double* charges,
+                       double* dipole, int32_t* unit_status) {
+  if (!ctx || !pos || !unit_status) return ctx ? fail(ctx, CAVDFTB_EINVAL, "eval_units: null pointer")
+                                               : CAVDFTB_EINVAL;
+  const bool want_f = energy || forces;
+  int32_t flags = JF_STORE | (want_f ? JF_FORCES : 0);
+  if (ctx->warm_enabled && ctx->warm_valid) flags |= JF_WARM_C | JF_WARM_DQ;
+  for (const Bucket& b : ctx->buckets) {
+    SccArgs a = base_args(ctx, pos);
+    a.job_unit = b.d_units;
+    a.n_jobs = b.n_units;
+    a.energy = energy;
+    a.forces = forces;
+    a.charges = charges;
+    a.dipole = dipole;
+    a.status = unit_status;
+    a.job_status = ctx->d_cjob_status + b.cjob0;
+    a.job_iters = ctx->d_cjob_iters + b.cjob0;
+    a.flags = flags;
+    int rc = run_scc(ctx, b, a);
+    if (rc) return rc;
+  }
+  ctx->warm_valid = ctx->warm_enabled != 0;
+  ctx->primed = false;
+  return CAVDFTB_OK;
+}
+
+int cavdftb_born_charges(cavdftb_ctx* ctx, const double* pos, int32_t mode, double h, double* born,
+                         double* ens_std, int32_t* unit_status) {
+  if (!ctx) return CAVDFTB_EINVAL;
+  if (!pos || !born || ens_std) return fail(ctx, CAVDFTB_EINVAL, "born_charges: bad pointer arguments");
+  if (mode != CAVDFTB_BORN_MULLIKEN && mode != CAVDFTB_BORN_FD)
+    return fail(ctx, CAVDFTB_EINVAL, "born_charges: unknown mode");
+  if (mode == CAVDFTB_BORN_FD && !(h > 0.0)) return fail(ctx, CAVDFTB_EINVAL, "born_charges: need h > 0");
+  int rc = eval_center(ctx, pos, false);
+  if (rc) return rc;
+  ctx->primed = false;
+  if (mode == CAVDFTB_BORN_MULLIKEN) {
+    hipError_t e = launch_born_mulliken(ctx->d_charges, ctx->NA, born, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "born mulliken");
+  } else {
+    rc = eval_fd(ctx, pos, h, born);
+    if (rc) return rc;
+  }
+  if (unit_status) {
+    hipError_t e = hipMemcpyAsync(unit_status, ctx->d_status, ctx->U * sizeof(int32_t), hipMemcpyDeviceToDevice,
+                                  ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "status copy");
+  }
+  return CAVDFTB_OK;
+}
+
+int cavdftb_cavity_forces(cavdftb_ctx* ctx, const double* mu_pol, const double* q, double* F, double* field,
+                          double* fq) {
+  if (!ctx) return CAVDFTB_EINVAL;
+  if (!mu_pol || (field && !q)) return fail(ctx, CAVDFTB_EINVAL, "cavity_forces: null input");
+  CavArgs ca = cav_args(ctx);
+  double* Fd = F ? F : ctx->d_F;
+  hipError_t e = launch_cav_scatter(ca, mu_pol, Fd, fq, ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "cavity scatter");
+  if (field) {
+    e = launch_cav_gather(ca, q, Fd, field, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "cavity gather");
+  }
+  return CAVDFTB_OK;
+}
+
+int cavdftb_init_photons(cavdftb_ctx* ctx, const double* r, double* qm, double* pm) {
+  if (!ctx) return CAVDFTB_EINVAL;
+  if (!r || !qm || !pm) return fail(ctx, CAVDFTB_EINVAL, "init_photons: null pointer");
+  int rc = eval_center(ctx, r, false);
+  if (rc) return rc;
+  ctx->primed = false;
+  CavArgs ca = cav_args(ctx);
+  hipError_t e = launch_mu_pol(ctx->d_dipole, ctx->pol, ctx->U, ctx->d_mu_pol, ctx->stream);
+  if (e == hipSuccess) e = launch_cav_scatter(ca, ctx->d_mu_pol, ctx->d_F, nullptr, ctx->stream);
+  if (e == hipSuccess) e = launch_init_photons(ca, ctx->d_F, qm, pm, ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "init_photons");
+  return CAVDFTB_OK;
+}
+
+int cavdftb_invalidate(cavdftb_ctx* ctx) {
+  if (!ctx) return CAVDFTB_EINVAL;
+  ctx->primed = false;
+  return CAVDFTB_OK;
+}
+
+int cavdftb_step(cavdftb_ctx* ctx, double* r, double* p, double* qm, double* pm, int32_t n_steps, double dt,
+                 int32_t born_mode, double h_fd, double* obs) {
+  if (!ctx) return CAVDFTB_EINVAL;
+  if (!r || !p || (ctx->M > 0 && (!qm || !pm)) || n_steps < 0 || !(dt > 0.0))
+    return fail(ctx, CAVDFTB_EINVAL, "step: bad arguments");
+  if (born_mode != CAVDFTB_BORN_MULLIKEN && born_mode != CAVDFTB_BORN_FD)
+    return fail(ctx, CAVDFTB_EINVAL, "step: unknown born mode");
+  if (born_mode == CAVDFTB_BORN_FD && !(h_fd > 0.0)) return fail(ctx, CAVDFTB_EINVAL, "step: need h_fd > 0");
+  hipStream_t s = ctx->stream;
+  CavArgs ca = cav_args(ctx);
+  hipError_t e;
+  int rc;
+  if (!ctx->primed) {
+    rc = matter_stage(ctx, r, born_mode, h_fd);
+    if (rc) return rc;
+    e = launch_cav_scatter(ca, ctx->d_mu_pol, ctx->d_F, nullptr, s);
+    if (e == hipSuccess) e = launch_cav_gather(ca, qm, ctx->d_F, ctx->d_field, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "step prime");
+    ctx->primed = true;
+  }
+  for (int st = 0; st < n_steps; ++st) {
+    e = launch_photon_kick(ctx->M, ctx->d_omega, ctx->d_lam, ctx->d_F, dt, pm, 0, qm, s);
+    if (e == hipSuccess)
+      e = launch_kick_drift(ctx->NA, ctx->d_atom_unit, ctx->d_inv_mass, ctx->d_forces, ctx->d_zpol, ctx->d_field,
+                            dt, r, p, 1, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "step kick/drift");
+    rc = matter_stage(ctx, r, born_mode, h_fd);
+    if (rc) return rc;
+    e = launch_cav_scatter(ca, ctx->d_mu_pol, ctx->d_F, nullptr, s);
+    if (e == hipSuccess) e = launch_cav_gather(ca, qm, ctx->d_F, ctx->d_field, s);  // old q
+    if (e == hipSuccess)
+      e = launch_kick_drift(ctx->NA, ctx->d_atom_unit, ctx->d_inv_mass, ctx->d_forces, ctx->d_zpol, ctx->d_field,
+                            dt, r, p, 0, s);
+    if (e == hipSuccess) e = launch_photon_kick(ctx->M, ctx->d_omega, ctx->d_lam, ctx->d_F, dt, pm, 1, qm, s);
+    if (e == hipSuccess) e = launch_cav_gather(ca, qm, ctx->d_F, ctx->d_field, s);  // rotated q
+    if (e == hipSuccess && obs)
+      e = launch_observables(ctx->U, ctx->NA, ctx->M, ctx->d_unit_off, ctx->d_mass, p, ctx->d_energy, qm, pm,
+                             ctx->d_omega, ctx->d_lam, ctx->d_F, ctx->d_mu_pol, ctx->d_status, ctx->d_cjob_iters,
+                             ctx->U, obs + (int64_t)st * CAVDFTB_N_OBS, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "step cavity/kick");
+  }
+  return CAVDFTB_OK;
+}
+
+int cavdftb_sync(cavdftb_ctx* ctx, int32_t* n_bad_units) {
+  if (!ctx) return CAVDFTB_EINVAL;
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "sync");
+  if (n_bad_units) {
+    std::vector<int32_t> st(ctx->U);
+    e = hipMemcpy(st.data(), ctx->d_status, ctx->U * sizeof(int32_t), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(ctx, e, "sync status");
+    int32_t nb = 0;
+    for (int32_t v : st) nb += v != 0;
+    *n_bad_units = nb;
+  }
+  return CAVDFTB_OK;
+}
+
+int cavdftb_enable_timing(cavdftb_ctx* ctx, int32_t enable) {
+  if (!ctx) return CAVDFTB_EINVAL;
+  ctx->timing = enable != 0;
+  return CAVDFTB_OK;
+}
+
+int cavdftb_read_counters(cavdftb_ctx* ctx, cavdftb_counters* out) {
+  if (!ctx || !out) return CAVDFTB_EINVAL;
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "counters sync");
+  harvest_events(ctx);
+  unsigned long long h[4] = {0, 0, 0, 0};
+  e = hipMemcpy(h, ctx->d_counters, sizeof(h), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(ctx, e, "counters copy");
+  out->scc_jobs = (int64_t)h[0];
+  out->scc_iterations = (int64_t)h[1];
+  out->scc_flops = (double)h[2];
+  out->scc_kernel_ms = ctx->t_ms;
+  out->scc_launches = ctx->launches;
+  return CAVDFTB_OK;
+}
+
+int cavdftb_reset_counters(cavdftb_ctx* ctx) {
+  if (!ctx) return CAVDFTB_EINVAL;
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(ctx->d_counters, 0, 4 * sizeof(unsigned long long), ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "reset counters");
+  harvest_events(ctx);
+  ctx->t_ms = 0.0;
+  ctx->launches = 0;
+  return CAVDFTB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,99 @@
+// Internal declarations shared by the HIP translation units of libcavdftb.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "cavdftb.h"
+
+namespace cavdftb {
+
+struct DevParams {
+  double sk[7][4];
+  double onsite[2][2];
+  double U[2];
+  double q0[2];
+  double rep_a[3];
+  double rep_alpha[3];
+};
+
+// job flags
+enum : int32_t {
+  JF_FORCES = 1,   // energy and forces
+  JF_WARM_C = 2,   // start from the stored MO basis of the unit
+  JF_WARM_DQ = 4,  // start from the stored charges of the unit
+  JF_STORE = 8,    // store basis and charges after convergence
+};
+
+constexpr int kMaxHist = 20;  // Broyden window
+
+struct SccArgs {
+  DevParams prm;
+  const double* pos;        // [n_atoms][3]
+  const int32_t* unit_off;  // [n_units+1]
+  const int8_t* species;    // [n_atoms]
+  const int32_t* job_unit;  // [n_jobs]
+  const int32_t* job_disp;  // [n_jobs] or nullptr; -1 = none, else (atom*3+dir)*2 + (step<0)
+  int32_t n_jobs;
+  double fd_h;
+  const int64_t* ws_off;    // [n_units] offset of the unit's stored basis in ws_C (doubles)
+  double* ws_C;             // stored MO bases, NMAX x NMAX per unit of the bucket
+  double* ws_dq;            // [n_atoms] stored charges (electron excess)
+  double* scratch;          // [gridDim.x][scratch_per_wg]
+  int64_t scratch_per_wg;
+  double* energy;           // [n_units] or nullptr
+  double* forces;           // [n_atoms][3] or nullptr
+  double* charges;          // [n_atoms] or nullptr
+  double* dipole;           // [n_units][3] or nullptr (written for undisplaced jobs)
+  double* mu_job;           // [n_jobs][3] or nullptr (written for displaced jobs)
+  int32_t* status;          // [n_units] (undisplaced jobs) or nullptr
+  int32_t* job_status;      // [n_jobs] or nullptr
+  int32_t* job_iters;       // [n_jobs] or nullptr
+  unsigned long long* counters;  // [3]: jobs, iterations, algorithmic flops
+  double tol;
+  int32_t max_iter;
+  double alpha;
+  double w0;
+  int32_t flags;
+};
+
+// scratch doubles needed per workgroup for a bucket
+int64_t scc_scratch_per_wg(int nmax);
+// launch the SCC kernel of the bucket nmax over args.n_jobs jobs with n_wg workgroups
+hipError_t launch_scc(int nmax, int n_wg, const SccArgs& args, hipStream_t stream);
+// workgroups per CU the SCC kernel of a bucket can keep resident
+int scc_blocks_per_cu(int nmax);
+
+// ---- cavity / integrator kernels (md_kernels.hip) ----
+struct CavArgs {
+  int32_t n_units, n_atoms, n_modes;
+  const double* unit_x;
+  const double* k;
+  const double* theta;
+  const double* omega;
+  const double* lam;
+  double pol[3];
+};
+
+hipError_t launch_mu_pol(const double* dipole, const double pol[3], int n_units, double* mu_pol, hipStream_t s);
+hipError_t launch_cav_scatter(const CavArgs& c, const double* mu_pol, double* F, double* fq, hipStream_t s);
+hipError_t launch_cav_gather(const CavArgs& c, const double* q, const double* F, double* field, hipStream_t s);
+hipError_t launch_init_photons(const CavArgs& c, const double* F, double* qm, double* pm, hipStream_t s);
+hipError_t launch_born_mulliken(const double* charges, int n_atoms, double* born, hipStream_t s);
+hipError_t launch_zpol_mulliken(const double* charges, const double pol[3], int n_atoms, double* zpol,
+                                hipStream_t s);
+hipError_t launch_born_fd_assemble(const int32_t* unit_off, const int32_t* fd_unit, const int32_t* fd_job0,
+                                   int n_fd_units, const double* mu_job, double h, const double pol[3],
+                                   const int32_t* job_status, double* born, double* zpol, int32_t* status,
+                                   hipStream_t s);
+hipError_t launch_kick_drift(int n_atoms, const int32_t* atom_unit, const double* inv_mass, const double* forces,
+                             const double* zpol, const double* field, double dt, double* r, double* p,
+                             int do_drift, hipStream_t s);
+hipError_t launch_photon_kick(int n_modes, const double* omega, const double* lam, const double* F, double dt,
+                              double* pm, int rotate, double* qm, hipStream_t s);
+hipError_t launch_observables(int n_units, int n_atoms, int n_modes, const int32_t* unit_off,
+                              const double* mass, const double* p, const double* energy,
+                              const double* qm, const double* pm, const double* omega, const double* lam,
+                              const double* F, const double* mu_pol, const int32_t* status,
+                              const int32_t* job_iters, int n_jobs, double* obs, hipStream_t s);
+
+}  // namespace cavdftb

@@ -1,0 +1,328 @@
+// Cavity coupling and integrator kernels (gfx950).
+//
+// Mode-space form of the paper's light-matter Hamiltonian (Theory, Eq.
+// hlm_bigin with real standing-wave mode functions phi_m(X) = sin(k_m X +
+// theta_m)):  F_m = sum_n phi_m(X_n) e.mu_n ;  the field felt by cell n is
+// E_n = sum_m lambda_m omega_m phi_m(X_n) (q_m + lambda_m F_m / omega_m); the
+// nuclear coupling force is -E_n e.Z_A and the photon coupling force
+// -lambda_m omega_m F_m (Eq. dpj).  The integrator follows Step 1 (Eq. pj1) and
+// the exact free rotation of Step 3 (Eq. qknk).  Mode functions are recomputed
+// with sin() rather than streamed (M x U table is up to 1 GB), and every sum
+// runs in a fixed order (no floating-point atomics).
+#include <math.h>
+
+#include "internal.h"
+
+namespace cavdftb {
+namespace {
+
+constexpr int kNT = 256;
+
+__device__ double wg_sum(double v, double* red) {
+  const int t = threadIdx.x;
+  red[t] = v;
+  __syncthreads();
+  for (int s = kNT / 2; s > 0; s >>= 1) {
+    if (t < s) red[t] += red[t + s];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(kNT) void mu_pol_kernel(const double* __restrict__ dip, double e0, double e1, double e2,
+                                                     int n, double* __restrict__ out) {
+  const int i = blockIdx.x * kNT + threadIdx.x;
+  if (i < n) out[i] = e0 * dip[i * 3] + e1 * dip[i * 3 + 1] + e2 * dip[i * 3 + 2];
+}
+
+// one workgroup per mode: F_m = sum_n phi_m(X_n) mu_n ; fq_m = -lambda omega F_m
+__global__ __launch_bounds__(kNT) void scatter_kernel(const CavArgs c, const double* __restrict__ mu_pol,
+                                                      double* __restrict__ F, double* __restrict__ fq) {
+  __shared__ double red[kNT];
+  const int m = blockIdx.x;
+  const double km = c.k[m], th = c.theta[m];
+  double acc = 0.0;
+  for (int n = threadIdx.x; n < c.n_units; n += kNT) acc += sin(km * c.unit_x[n] + th) * mu_pol[n];
+  const double f = wg_sum(acc, red);
+  if (threadIdx.x == 0) {
+    if (F) F[m] = f;
+    if (fq) fq[m] = -c.lam[m] * c.omega[m] * f;
+  }
+}
+
+// E_n = sum_m phi_m(X_n) g_m with g_m = lambda omega (q + lambda F / omega);
+// one thread per cell, modes staged through LDS in chunks.
+__global__ __launch_bounds__(kNT) void gather_kernel(const CavArgs c, const double* __restrict__ q,
+                                                     const double* __restrict__ F, double* __restrict__ field) {
+  __shared__ double sg[kNT], sk[kNT], sth[kNT];
+  const int n = blockIdx.x * kNT + threadIdx.x;
+  const double x = n < c.n_units ? c.unit_x[n] : 0.0;
+  double acc = 0.0;
+  for (int m0 = 0; m0 < c.n_modes; m0 += kNT) {
+    const int m = m0 + threadIdx.x;
+    if (m < c.n_modes) {
+      const double lw = c.lam[m] * c.omega[m];
+      sg[threadIdx.x] = lw * (q[m] + c.lam[m] * F[m] / c.omega[m]);
+      sk[threadIdx.x] = c.k[m];
+      sth[threadIdx.x] = c.theta[m];
+    }
+    __syncthreads();
+    const int cnt = min(kNT, c.n_modes - m0);
+    for (int j = 0; j < cnt; ++j) acc += sin(sk[j] * x + sth[j]) * sg[j];
+    __syncthreads();
+  }
+  if (n < c.n_units) field[n] = acc;
+}
+
+__global__ __launch_bounds__(kNT) void init_photons_kernel(const CavArgs c, const double* __restrict__ F,
+                                                           double* __restrict__ qm, double* __restrict__ pm) {
+  const int m = blockIdx.x * kNT + threadIdx.x;
+  if (m < c.n_modes) {
+    qm[m] = -c.lam[m] * F[m] / c.omega[m];
+    pm[m] = 0.0;
+  }
+}
+
+__global__ __launch_bounds__(kNT) void born_mulliken_kernel(const double* __restrict__ q, int n,
+                                                            double* __restrict__ born) {
+  const int i = blockIdx.x * kNT + threadIdx.x;
+  if (i < n)
+    for (int e = 0; e < 9; ++e) born[(int64_t)i * 9 + e] = (e % 4 == 0) ? q[i] : 0.0;
+}
+
+__global__ __launch_bounds__(kNT) void zpol_mulliken_kernel(const double* __restrict__ q, double e0, double e1,
+                                                            double e2, int n, double* __restrict__ zp) {
+  const int i = blockIdx.x * kNT + threadIdx.x;
+  if (i < n) {
+    zp[i * 3] = q[i] * e0;
+    zp[i * 3 + 1] = q[i] * e1;
+    zp[i * 3 + 2] = q[i] * e2;
+  }
+}
+
+// one thread per (unit, atom): Z[a][al][b] = (mu+_al - mu-_al) / 2h from the
+// displaced jobs of the unit (job order (atom*3 + dir)*2 + (minus)).
+__global__ __launch_bounds__(64) void born_fd_kernel(const int32_t* __restrict__ unit_off,
+                                                      const int32_t* __restrict__ fd_unit,
+                                                      const int32_t* __restrict__ fd_job0, int n_fd_units,
+                                                      const double* __restrict__ mu_job, double h, double e0,
+                                                      double e1, double e2, double* __restrict__ born,
+                                                      double* __restrict__ zpol) {
+  const int w = blockIdx.x;
+  if (w >= n_fd_units) return;
+  const int u = fd_unit[w];
+  const int a0 = unit_off[u], na = unit_off[u + 1] - a0;
+  const int loc = threadIdx.x;
+  if (loc >= na) return;
+  const int64_t j0 = fd_job0[w];
+  double Z[3][3];
+  for (int b = 0; b < 3; ++b) {
+    const int64_t jp = j0 + (int64_t)((loc * 3 + b) * 2);
+    for (int al = 0; al < 3; ++al) Z[al][b] = (mu_job[jp * 3 + al] - mu_job[(jp + 1) * 3 + al]) / (2.0 * h);
+  }
+  const int64_t A = a0 + loc;
+  if (born)
+    for (int al = 0; al < 3; ++al)
+      for (int b = 0; b < 3; ++b) born[A * 9 + al * 3 + b] = Z[al][b];
+  if (zpol)
+    for (int b = 0; b < 3; ++b) zpol[A * 3 + b] = e0 * Z[0][b] + e1 * Z[1][b] + e2 * Z[2][b];
+}
+
+// OR the displaced-job status into the unit status, one thread per fd unit
+__global__ __launch_bounds__(kNT) void born_fd_status_kernel(const int32_t* __restrict__ unit_off,
+                                                             const int32_t* __restrict__ fd_unit,
+                                                             const int32_t* __restrict__ fd_job0, int n_fd_units,
+                                                             const int32_t* __restrict__ job_status,
+                                                             int32_t* __restrict__ status) {
+  const int w = blockIdx.x * kNT + threadIdx.x;
+  if (w >= n_fd_units) return;
+  const int u = fd_unit[w];
+  const int na = unit_off[u + 1] - unit_off[u];
+  int st = status[u];
+  for (int j = 0; j < 6 * na; ++j) st |= job_status[fd_job0[w] + j];
+  status[u] = st;
+}
+
+// p += dt/2 (F - E_n e.Z) ; optionally r += dt p / m
+__global__ __launch_bounds__(kNT) void kick_drift_kernel(int n, const int32_t* __restrict__ atom_unit,
+                                                         const double* __restrict__ inv_mass,
+                                                         const double* __restrict__ f,
+                                                         const double* __restrict__ zp,
+                                                         const double* __restrict__ field, double dt,
+                                                         double* __restrict__ r, double* __restrict__ p,
+                                                         int drift) {
+  const int i = blockIdx.x * kNT + threadIdx.x;
+  if (i >= n) return;
+  const double e = field[atom_unit[i]];
+  for (int g = 0; g < 3; ++g) {
+    const double pn = p[i * 3 + g] + 0.5 * dt * (f[i * 3 + g] - e * zp[i * 3 + g]);
+    p[i * 3 + g] = pn;
+    if (drift) r[i * 3 + g] += dt * pn * inv_mass[i];
+  }
+}
+
+// p_m -= dt/2 lambda omega F_m ; optionally exact rotation by omega dt
+__global__ __launch_bounds__(kNT) void photon_kernel(int nm, const double* __restrict__ omega,
+                                                     const double* __restrict__ lam, const double* __restrict__ F,
+                                                     double dt, double* __restrict__ pm, int rotate,
+                                                     double* __restrict__ qm) {
+  const int m = blockIdx.x * kNT + threadIdx.x;
+  if (m >= nm) return;
+  const double w = omega[m];
+  double p = pm[m] - 0.5 * dt * lam[m] * w * F[m];
+  if (rotate) {
+    const double q = qm[m];
+    const double c = cos(w * dt), s = sin(w * dt);
+    qm[m] = q * c + p * s / w;
+    p = p * c - w * q * s;
+  }
+  pm[m] = p;
+}
+
+// one workgroup: fixed-order totals for the observables of one step
+__global__ __launch_bounds__(kNT) void observables_kernel(int nu, int na, int nm, const int32_t* __restrict__ uoff,
+                                                          const double* __restrict__ mass,
+                                                          const double* __restrict__ p,
+                                                          const double* __restrict__ energy,
+                                                          const double* __restrict__ qm,
+                                                          const double* __restrict__ pm,
+                                                          const double* __restrict__ omega,
+                                                          const double* __restrict__ lam,
+                                                          const double* __restrict__ F,
+                                                          const double* __restrict__ mu_pol,
+                                                          const int32_t* __restrict__ status,
+                                                          const int32_t* __restrict__ iters, int n_jobs,
+                                                          double* __restrict__ obs) {
+  __shared__ double red[kNT];
+  double ke = 0.0, v = 0.0, eph = 0.0, tsum = 0.0, nbad = 0.0, its = 0.0, mus = 0.0;
+  for (int u = threadIdx.x; u < nu; u += kNT) {
+    const int a0 = uoff[u], a1 = uoff[u + 1];
+    double pc[3] = {0.0, 0.0, 0.0}, mt = 0.0, k2 = 0.0;
+    for (int a = a0; a < a1; ++a) {
+      mt += mass[a];
+      for (int g = 0; g < 3; ++g) {
+        pc[g] += p[a * 3 + g];
+        k2 += p[a * 3 + g] * p[a * 3 + g] / (2.0 * mass[a]);
+      }
+    }
+    ke += k2;
+    const double kcm = (pc[0] * pc[0] + pc[1] * pc[1] + pc[2] * pc[2]) / (2.0 * mt);
+    const int dof = 3 * (a1 - a0) - 3;
+    if (dof > 0) tsum += 2.0 * (k2 - kcm) / (dof * 3.166811563e-6);
+    v += energy[u];
+    nbad += status[u] != 0 ? 1.0 : 0.0;
+    mus += mu_pol[u];
+  }
+  for (int m = threadIdx.x; m < nm; m += kNT) {
+    const double x = qm[m] + lam[m] * F[m] / omega[m];
+    eph += 0.5 * pm[m] * pm[m] + 0.5 * omega[m] * omega[m] * x * x;
+  }
+  for (int j = threadIdx.x; j < n_jobs; j += kNT) its += iters[j];
+  ke = wg_sum(ke, red);
+  v = wg_sum(v, red);
+  eph = wg_sum(eph, red);
+  tsum = wg_sum(tsum, red);
+  nbad = wg_sum(nbad, red);
+  its = wg_sum(its, red);
+  mus = wg_sum(mus, red);
+  if (threadIdx.x == 0) {
+    obs[0] = ke;
+    obs[1] = v;
+    obs[2] = eph;
+    obs[3] = ke + v + eph;
+    obs[4] = tsum / nu;
+    obs[5] = nbad;
+    obs[6] = its;
+    obs[7] = mus;
+  }
+  (void)na;
+}
+
+inline int nblk(int n) { return (n + kNT - 1) / kNT; }
+
+}  // namespace
+
+hipError_t launch_mu_pol(const double* dipole, const double pol[3], int n_units, double* mu_pol, hipStream_t s) {
+  if (n_units <= 0) return hipSuccess;
+  hipLaunchKernelGGL(mu_pol_kernel, dim3(nblk(n_units)), dim3(kNT), 0, s, dipole, pol[0], pol[1], pol[2], n_units,
+                     mu_pol);
+  return hipGetLastError();
+}
+
+hipError_t launch_cav_scatter(const CavArgs& c, const double* mu_pol, double* F, double* fq, hipStream_t s) {
+  if (c.n_modes <= 0) return hipSuccess;
+  hipLaunchKernelGGL(scatter_kernel, dim3(c.n_modes), dim3(kNT), 0, s, c, mu_pol, F, fq);
+  return hipGetLastError();
+}
+
+hipError_t launch_cav_gather(const CavArgs& c, const double* q, const double* F, double* field, hipStream_t s) {
+  if (c.n_units <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gather_kernel, dim3(nblk(c.n_units)), dim3(kNT), 0, s, c, q, F, field);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_photons(const CavArgs& c, const double* F, double* qm, double* pm, hipStream_t s) {
+  if (c.n_modes <= 0) return hipSuccess;
+  hipLaunchKernelGGL(init_photons_kernel, dim3(nblk(c.n_modes)), dim3(kNT), 0, s, c, F, qm, pm);
+  return hipGetLastError();
+}
+
+hipError_t launch_born_mulliken(const double* charges, int n_atoms, double* born, hipStream_t s) {
+  hipLaunchKernelGGL(born_mulliken_kernel, dim3(nblk(n_atoms)), dim3(kNT), 0, s, charges, n_atoms, born);
+  return hipGetLastError();
+}
+
+hipError_t launch_zpol_mulliken(const double* charges, const double pol[3], int n_atoms, double* zpol,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(zpol_mulliken_kernel, dim3(nblk(n_atoms)), dim3(kNT), 0, s, charges, pol[0], pol[1], pol[2],
+                     n_atoms, zpol);
+  return hipGetLastError();
+}
+
+hipError_t launch_born_fd_assemble(const int32_t* unit_off, const int32_t* fd_unit, const int32_t* fd_job0,
+                                   int n_fd_units, const double* mu_job, double h, const double pol[3],
+                                   const int32_t* job_status, double* born, double* zpol, int32_t* status,
+                                   hipStream_t s) {
+  if (n_fd_units <= 0) return hipSuccess;
+  // at most 64 orbitals per unit -> at most 64 atoms: one 64-thread block per unit
+  hipLaunchKernelGGL(born_fd_kernel, dim3(n_fd_units), dim3(64), 0, s, unit_off, fd_unit, fd_job0, n_fd_units,
+                     mu_job, h, pol[0], pol[1], pol[2], born, zpol);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (status && job_status) {
+    hipLaunchKernelGGL(born_fd_status_kernel, dim3(nblk(n_fd_units)), dim3(kNT), 0, s, unit_off, fd_unit, fd_job0,
+                       n_fd_units, job_status, status);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+hipError_t launch_kick_drift(int n_atoms, const int32_t* atom_unit, const double* inv_mass, const double* forces,
+                             const double* zpol, const double* field, double dt, double* r, double* p,
+                             int do_drift, hipStream_t s) {
+  hipLaunchKernelGGL(kick_drift_kernel, dim3(nblk(n_atoms)), dim3(kNT), 0, s, n_atoms, atom_unit, inv_mass, forces,
+                     zpol, field, dt, r, p, do_drift);
+  return hipGetLastError();
+}
+
+hipError_t launch_photon_kick(int n_modes, const double* omega, const double* lam, const double* F, double dt,
+                              double* pm, int rotate, double* qm, hipStream_t s) {
+  if (n_modes <= 0) return hipSuccess;
+  hipLaunchKernelGGL(photon_kernel, dim3(nblk(n_modes)), dim3(kNT), 0, s, n_modes, omega, lam, F, dt, pm, rotate,
+                     qm);
+  return hipGetLastError();
+}
+
+hipError_t launch_observables(int n_units, int n_atoms, int n_modes, const int32_t* unit_off, const double* mass,
+                              const double* p, const double* energy, const double* qm, const double* pm,
+                              const double* omega, const double* lam, const double* F, const double* mu_pol,
+                              const int32_t* status, const int32_t* job_iters, int n_jobs, double* obs,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(observables_kernel, dim3(1), dim3(kNT), 0, s, n_units, n_atoms, n_modes, unit_off, mass, p,
+                     energy, qm, pm, omega, lam, F, mu_pol, status, job_iters, n_jobs, obs);
+  return hipGetLastError();
+}
+
+}  // namespace cavdftb

@@ -1,0 +1,848 @@
+// Batched SCC-DFTB unit evaluation on CDNA4 (gfx950).
+//
+// One workgroup evaluates one unit geometry ("job") at a time and loops over
+// jobs persistently (job = blockIdx.x + k * gridDim.x), so per-workgroup
+// scratch can be preallocated and the job order is fixed (deterministic).
+//
+// Per job (second-order SCC-DFTB, Elstner et al. 1998, which the paper uses
+// for every cell - Computational details):
+//   H0, S from the Slater-Koster rules (Slater & Koster 1954, Table I) with the
+//   exponential radial tables; gamma from Elstner's kernel (tau = 16U/5).
+//   An S-orthonormal basis X (X^T S X = I) is built by Cholesky
+//   orthonormalisation of the identity (cold) or of the stored MO basis of the
+//   unit (warm).  Each SCC iteration forms H = H0 + 1/2 S o (V_a + V_b),
+//   A = X^T H X, and diagonalises A by cyclic parallel Jacobi whose rotations
+//   are applied straight to X, so X becomes the MO coefficient matrix C and
+//   stays the (near-diagonalising) basis of the next iteration.  Aufbau
+//   occupation of the n_occ lowest levels, P = 2 C_occ C_occ^T, Mulliken
+//   charges, Johnson's modified Broyden mixing.  After convergence:
+//   W = 2 C_occ eps C_occ^T, E = Tr(P H0) + 1/2 Dq gamma Dq + E_rep and the
+//   pair-wise force contraction, all with fixed-order reductions.
+//
+// LDS holds the three n x n working matrices (X, A, T); H0, S and gamma live
+// in per-workgroup global scratch (L2 resident).
+#include <math.h>
+
+#include "internal.h"
+
+namespace cavdftb {
+namespace {
+
+constexpr int kMaxSweeps = 30;
+constexpr double kJacobiThr = 1.0e-14;  // off-diagonal threshold (hartree)
+constexpr double kGapMin = 1.0e-6;
+
+// ---------------------------------------------------------------- SK rules
+__device__ __forceinline__ void radial(const DevParams& P, int t, double r, double& h, double& s, double& hp,
+                                       double& sp) {
+  h = P.sk[t][0] * exp(-P.sk[t][1] * r);
+  s = P.sk[t][2] * exp(-P.sk[t][3] * r);
+  hp = -P.sk[t][1] * h;
+  sp = -P.sk[t][3] * s;
+}
+
+// Two-centre block <i on A | . | j on B> for d = R_B - R_A (nA x nB, row-major
+// with leading dimension 4).
+__device__ void sk_block(const DevParams& P, int spA, int spB, const double d[3], double H[16], double S[16]) {
+  const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+  const double ir = 1.0 / r;
+  const double u[3] = {d[0] * ir, d[1] * ir, d[2] * ir};
+  int t_ss, t_sp, t_ps;
+  if (spA == 0 && spB == 0) {
+    t_ss = 0; t_sp = 1; t_ps = 1;
+  } else if (spA == 0) {  // O-H
+    t_ss = 4; t_sp = -1; t_ps = 5;
+  } else if (spB == 0) {  // H-O
+    t_ss = 4; t_sp = 5; t_ps = -1;
+  } else {
+    t_ss = 6; t_sp = -1; t_ps = -1;
+  }
+  const int nA = spA == 0 ? 4 : 1, nB = spB == 0 ? 4 : 1;
+  double h, s, hp, spr;
+  radial(P, t_ss, r, h, s, hp, spr);
+  H[0] = h;
+  S[0] = s;
+  if (nB == 4) {  // s on A, p on B:  u_b V
+    radial(P, t_sp, r, h, s, hp, spr);
+    for (int b = 0; b < 3; ++b) {
+      H[1 + b] = u[b] * h;
+      S[1 + b] = u[b] * s;
+    }
+  }
+  if (nA == 4) {  // p on A, s on B:  -u_a V
+    radial(P, t_ps, r, h, s, hp, spr);
+    for (int a = 0; a < 3; ++a) {
+      H[(1 + a) * 4] = -u[a] * h;
+      S[(1 + a) * 4] = -u[a] * s;
+    }
+  }
+  if (nA == 4 && nB == 4) {  // p-p
+    double hs, ss, hsp, ssp, hpi, spi, hpip, spip;
+    radial(P, 2, r, hs, ss, hsp, ssp);
+    radial(P, 3, r, hpi, spi, hpip, spip);
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        const double dl = a == b ? 1.0 : 0.0;
+        const int e = (1 + a) * 4 + 1 + b;
+        H[e] = u[a] * u[b] * (hs - hpi) + dl * hpi;
+        S[e] = u[a] * u[b] * (ss - spi) + dl * spi;
+      }
+  }
+}
+
+// Gradient contribution of the pair (A, B) with respect to d = R_B - R_A:
+// g += 2 sum_ij [ P_ij dH0_ij - (W_ij - 1/2 P_ij (V_A + V_B)) dS_ij ], streaming
+// over the block elements so no derivative block is kept in registers.
+__device__ void pair_band_grad(const DevParams& P, int spA, int spB, const double d[3], const double* Pm,
+                               const double* Wm, int ld, int oA, int oB, double vab, double g[3]) {
+  const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+  const double ir = 1.0 / r;
+  const double u[3] = {d[0] * ir, d[1] * ir, d[2] * ir};
+  int t_ss, t_sp, t_ps;
+  if (spA == 0 && spB == 0) {
+    t_ss = 0; t_sp = 1; t_ps = 1;
+  } else if (spA == 0) {
+    t_ss = 4; t_sp = -1; t_ps = 5;
+  } else if (spB == 0) {
+    t_ss = 4; t_sp = 5; t_ps = -1;
+  } else {
+    t_ss = 6; t_sp = -1; t_ps = -1;
+  }
+  const int nA = spA == 0 ? 4 : 1, nB = spB == 0 ? 4 : 1;
+  double h, s, hp, sp;
+  // s-s: weight on dH and dS
+  {
+    radial(P, t_ss, r, h, s, hp, sp);
+    const double pij = Pm[oA * ld + oB];
+    const double wij = Wm[oA * ld + oB] - 0.5 * pij * vab;
+    const double rad = 2.0 * (pij * hp - wij * sp);
+    for (int k = 0; k < 3; ++k) g[k] += rad * u[k];
+  }
+  if (nB == 4) {  // <s_A | p_B,b> = u_b V
+    radial(P, t_sp, r, h, s, hp, sp);
+    for (int b = 0; b < 3; ++b) {
+      const double pij = Pm[oA * ld + oB + 1 + b];
+      const double wij = Wm[oA * ld + oB + 1 + b] - 0.5 * pij * vab;
+      const double ch = 2.0 * pij, cs = -2.0 * wij;
+      for (int k = 0; k < 3; ++k) {
+        const double du = ((b == k ? 1.0 : 0.0) - u[b] * u[k]) * ir;
+        g[k] += ch * (du * h + u[b] * hp * u[k]) + cs * (du * s + u[b] * sp * u[k]);
+      }
+    }
+  }
+  if (nA == 4) {  // <p_A,a | s_B> = -u_a V
+    radial(P, t_ps, r, h, s, hp, sp);
+    for (int a = 0; a < 3; ++a) {
+      const double pij = Pm[(oA + 1 + a) * ld + oB];
+      const double wij = Wm[(oA + 1 + a) * ld + oB] - 0.5 * pij * vab;
+      const double ch = 2.0 * pij, cs = -2.0 * wij;
+      for (int k = 0; k < 3; ++k) {
+        const double du = ((a == k ? 1.0 : 0.0) - u[a] * u[k]) * ir;
+        g[k] -= ch * (du * h + u[a] * hp * u[k]) + cs * (du * s + u[a] * sp * u[k]);
+      }
+    }
+  }
+  if (nA == 4 && nB == 4) {  // p-p
+    double hs, ss, hsp, ssp, hpi, spi, hpip, spip;
+    radial(P, 2, r, hs, ss, hsp, ssp);
+    radial(P, 3, r, hpi, spi, hpip, spip);
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        const double pij = Pm[(oA + 1 + a) * ld + oB + 1 + b];
+        const double wij = Wm[(oA + 1 + a) * ld + oB + 1 + b] - 0.5 * pij * vab;
+        const double ch = 2.0 * pij, cs = -2.0 * wij;
+        const double dl = a == b ? 1.0 : 0.0;
+        for (int k = 0; k < 3; ++k) {
+          const double dua = ((a == k ? 1.0 : 0.0) - u[a] * u[k]) * ir;
+          const double dub = ((b == k ? 1.0 : 0.0) - u[b] * u[k]) * ir;
+          const double duu = dua * u[b] + u[a] * dub;
+          const double dH = duu * (hs - hpi) + u[a] * u[b] * (hsp - hpip) * u[k] + dl * hpip * u[k];
+          const double dS = duu * (ss - spi) + u[a] * u[b] * (ssp - spip) * u[k] + dl * spip * u[k];
+          g[k] += ch * dH + cs * dS;
+        }
+      }
+  }
+}
+
+// Elstner gamma and d gamma / dR for distinct sites.
+__device__ void gamma_pair(double ua, double ub, double r, double& g, double& dg) {
+  const double ta = 3.2 * ua, tb = 3.2 * ub;  // 16 U / 5
+  double s, ds;
+  if (fabs(ta - tb) < 1e-10 * fmax(ta, tb)) {
+    const double t = 0.5 * (ta + tb);
+    const double e = exp(-t * r);
+    const double poly = 1.0 / r + 11.0 * t / 16.0 + 3.0 * t * t * r / 16.0 + t * t * t * r * r / 48.0;
+    const double dpoly = -1.0 / (r * r) + 3.0 * t * t / 16.0 + t * t * t * r / 24.0;
+    s = e * poly;
+    ds = -t * s + e * dpoly;
+  } else {
+    s = 0.0;
+    ds = 0.0;
+    for (int k = 0; k < 2; ++k) {
+      const double a = k == 0 ? ta : tb, b = k == 0 ? tb : ta;
+      const double d2 = a * a - b * b;
+      const double k1 = b * b * b * b * a / (2.0 * d2 * d2);
+      const double k2 = (b * b * b * b * b * b - 3.0 * a * a * b * b * b * b) / (d2 * d2 * d2);
+      const double e = exp(-a * r);
+      const double v = e * (k1 - k2 / r);
+      s += v;
+      ds += -a * v + e * (k2 / (r * r));
+    }
+  }
+  g = 1.0 / r - s;
+  dg = -1.0 / (r * r) - ds;
+}
+
+// ---------------------------------------------------------------- block helpers
+template <int NT>
+__device__ double block_sum(double v, double* red) {
+  const int t = threadIdx.x;
+  red[t] = v;
+  __syncthreads();
+#pragma unroll
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if (t < s) red[t] += red[t + s];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+template <int NT>
+__device__ double block_max(double v, double* red) {
+  const int t = threadIdx.x;
+  red[t] = v;
+  __syncthreads();
+#pragma unroll
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if (t < s) red[t] = fmax(red[t], red[t + s]);
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+template <int NMAX, int NT>
+struct Tile {
+  static constexpr int G = (NT == 256) ? 16 : 8;
+  static constexpr int TM = NMAX / G;
+  static_assert(TM * G == NMAX, "tile mismatch");
+};
+
+// C = A B over the leading n x n block (LD = NMAX); padding of A, B is zero.
+template <int NMAX, int NT>
+__device__ void gemm_nn(const double* __restrict__ A, const double* __restrict__ B, double* __restrict__ C,
+                        int n) {
+  constexpr int G = Tile<NMAX, NT>::G, TM = Tile<NMAX, NT>::TM;
+  const int tx = threadIdx.x % G, ty = threadIdx.x / G;
+  double acc[TM][TM];
+#pragma unroll
+  for (int r = 0; r < TM; ++r)
+#pragma unroll
+    for (int c = 0; c < TM; ++c) acc[r][c] = 0.0;
+  for (int k = 0; k < n; ++k) {
+    double av[TM], bv[TM];
+#pragma unroll
+    for (int r = 0; r < TM; ++r) av[r] = A[(ty + G * r) * NMAX + k];
+#pragma unroll
+    for (int c = 0; c < TM; ++c) bv[c] = B[k * NMAX + tx + G * c];
+#pragma unroll
+    for (int r = 0; r < TM; ++r)
+#pragma unroll
+      for (int c = 0; c < TM; ++c) acc[r][c] = fma(av[r], bv[c], acc[r][c]);
+  }
+#pragma unroll
+  for (int r = 0; r < TM; ++r)
+#pragma unroll
+    for (int c = 0; c < TM; ++c) C[(ty + G * r) * NMAX + tx + G * c] = acc[r][c];
+}
+
+// C = A^T B
+template <int NMAX, int NT>
+__device__ void gemm_tn(const double* __restrict__ A, const double* __restrict__ B, double* __restrict__ C,
+                        int n) {
+  constexpr int G = Tile<NMAX, NT>::G, TM = Tile<NMAX, NT>::TM;
+  const int tx = threadIdx.x % G, ty = threadIdx.x / G;
+  double acc[TM][TM];
+#pragma unroll
+  for (int r = 0; r < TM; ++r)
+#pragma unroll
+    for (int c = 0; c < TM; ++c) acc[r][c] = 0.0;
+  for (int k = 0; k < n; ++k) {
+    double av[TM], bv[TM];
+#pragma unroll
+    for (int r = 0; r < TM; ++r) av[r] = A[k * NMAX + ty + G * r];
+#pragma unroll
+    for (int c = 0; c < TM; ++c) bv[c] = B[k * NMAX + tx + G * c];
+#pragma unroll
+    for (int r = 0; r < TM; ++r)
+#pragma unroll
+      for (int c = 0; c < TM; ++c) acc[r][c] = fma(av[r], bv[c], acc[r][c]);
+  }
+#pragma unroll
+  for (int r = 0; r < TM; ++r)
+#pragma unroll
+    for (int c = 0; c < TM; ++c) C[(ty + G * r) * NMAX + tx + G * c] = acc[r][c];
+}
+
+// C = X diag(w) X^T restricted to the columns listed in idx[0..m)
+template <int NMAX, int NT>
+__device__ void gemm_xwxt(const double* __restrict__ X, const double* __restrict__ w, const int* __restrict__ idx,
+                          int m, double* __restrict__ C) {
+  constexpr int G = Tile<NMAX, NT>::G, TM = Tile<NMAX, NT>::TM;
+  const int tx = threadIdx.x % G, ty = threadIdx.x / G;
+  double acc[TM][TM];
+#pragma unroll
+  for (int r = 0; r < TM; ++r)
+#pragma unroll
+    for (int c = 0; c < TM; ++c) acc[r][c] = 0.0;
+  for (int kk = 0; kk < m; ++kk) {
+    const int k = idx[kk];
+    const double wk = w[k];
+    double av[TM], bv[TM];
+#pragma unroll
+    for (int r = 0; r < TM; ++r) av[r] = X[(ty + G * r) * NMAX + k] * wk;
+#pragma unroll
+    for (int c = 0; c < TM; ++c) bv[c] = X[(tx + G * c) * NMAX + k];
+#pragma unroll
+    for (int r = 0; r < TM; ++r)
+#pragma unroll
+      for (int c = 0; c < TM; ++c) acc[r][c] = fma(av[r], bv[c], acc[r][c]);
+  }
+#pragma unroll
+  for (int r = 0; r < TM; ++r)
+#pragma unroll
+    for (int c = 0; c < TM; ++c) C[(ty + G * r) * NMAX + tx + G * c] = acc[r][c];
+}
+
+// index held by slot s in round r of the circle (round-robin) ordering of m indices
+__device__ __forceinline__ int rr_index(int s, int r, int m) { return s == 0 ? 0 : 1 + (s - 1 + r) % (m - 1); }
+
+struct Shared {
+  int n, nocc, na, notpd;
+  int bcount, bhead, converged, n_iter;
+  double homo, lumo;
+};
+
+template <int NMAX, int NT>
+__global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
+  constexpr int HALF = NMAX / 2;
+  __shared__ double sX[NMAX * NMAX];
+  __shared__ double sA[NMAX * NMAX];
+  __shared__ double sT[NMAX * NMAX];
+  __shared__ double sPos[NMAX * 3];
+  __shared__ double sDqIn[NMAX], sDqOut[NMAX], sV[NMAX], sQ0[NMAX], sEig[NMAX], sW[NMAX], sQorb[NMAX];
+  __shared__ int sOrbAtom[NMAX], sAtomOff[NMAX + 1], sSp[NMAX], sOcc[NMAX];
+  __shared__ double sRed[NT];
+  __shared__ double sF[NT * 3];
+  __shared__ int sRp[HALF], sRq[HALF];
+  __shared__ double sRc[HALF], sRs[HALF], sRt[HALF];
+  __shared__ double sBa[kMaxHist * kMaxHist], sBc[kMaxHist], sBg[kMaxHist];
+  __shared__ Shared sh;
+
+  const int tid = threadIdx.x;
+  const DevParams& P = a.prm;
+  double* scr = a.scratch + (int64_t)blockIdx.x * a.scratch_per_wg;
+  double* gH0 = scr;
+  double* gS = scr + NMAX * NMAX;
+  double* gG = scr + 2 * NMAX * NMAX;
+  double* bXp = scr + 3 * NMAX * NMAX;
+  double* bFp = bXp + NMAX;
+  double* bDF = bFp + NMAX;
+  double* bU = bDF + kMaxHist * NMAX;
+
+  for (int job = blockIdx.x; job < a.n_jobs; job += gridDim.x) {
+    const int u = a.job_unit[job];
+    const int disp = a.job_disp ? a.job_disp[job] : -1;
+    const int a0 = a.unit_off[u];
+    const int na = a.unit_off[u + 1] - a0;
+    const int d_atom = disp >= 0 ? (disp >> 1) / 3 : -1;
+    const int d_dir = disp >= 0 ? (disp >> 1) % 3 : 0;
+    const double d_step = disp >= 0 ? ((disp & 1) ? -a.fd_h : a.fd_h) : 0.0;
+
+    // ---- load atoms
+    for (int t = tid; t < na; t += NT) {
+      sSp[t] = a.species[a0 + t];
+      for (int g = 0; g < 3; ++g) sPos[t * 3 + g] = a.pos[(int64_t)(a0 + t) * 3 + g];
+      if (t == d_atom) sPos[t * 3 + d_dir] += d_step;
+    }
+    for (int e = tid; e < NMAX * NMAX; e += NT) {
+      sX[e] = 0.0;
+      sA[e] = 0.0;
+      sT[e] = 0.0;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int o = 0;
+      double nel = 0.0;
+      bool bad = false;
+      for (int t = 0; t < na; ++t) {
+        sAtomOff[t] = o;
+        o += sSp[t] == 0 ? 4 : 1;
+        nel += P.q0[sSp[t]];
+        for (int g = 0; g < 3; ++g) bad |= !isfinite(sPos[t * 3 + g]);
+      }
+      sAtomOff[na] = o;
+      sh.n = o;
+      sh.nocc = (int)(nel + 0.5) / 2;
+      sh.na = na;
+      sh.notpd = bad ? 2 : 0;  // 2 marks a non-finite position
+      sh.bcount = 0;
+      sh.bhead = 0;
+      sh.converged = 0;
+    }
+    __syncthreads();
+    const int n = sh.n, nocc = sh.nocc;
+    for (int t = tid; t < na; t += NT) {
+      for (int o = sAtomOff[t]; o < sAtomOff[t + 1]; ++o) sOrbAtom[o] = t;
+      sQ0[t] = P.q0[sSp[t]];
+      sDqIn[t] = (a.flags & JF_WARM_DQ) ? a.ws_dq[a0 + t] : 0.0;
+    }
+
+    // ---- H0, S (global scratch) and gamma
+    for (int task = tid; task < na * na; task += NT) {
+      const int A = task / na, B = task % na;
+      if (B < A) continue;
+      const int oA = sAtomOff[A], oB = sAtomOff[B];
+      const int nA = sSp[A] == 0 ? 4 : 1, nB = sSp[B] == 0 ? 4 : 1;
+      if (A == B) {
+        for (int i = 0; i < nA; ++i)
+          for (int j = 0; j < nA; ++j) {
+            const double h = (i == j) ? P.onsite[sSp[A]][i == 0 ? 0 : 1] : 0.0;
+            gH0[(oA + i) * NMAX + oA + j] = h;
+            gS[(oA + i) * NMAX + oA + j] = (i == j) ? 1.0 : 0.0;
+          }
+        gG[A * NMAX + A] = P.U[sSp[A]];
+      } else {
+        double d[3], H[16], S[16];
+        for (int g = 0; g < 3; ++g) d[g] = sPos[B * 3 + g] - sPos[A * 3 + g];
+        sk_block(P, sSp[A], sSp[B], d, H, S);
+        for (int i = 0; i < nA; ++i)
+          for (int j = 0; j < nB; ++j) {
+            gH0[(oA + i) * NMAX + oB + j] = H[i * 4 + j];
+            gS[(oA + i) * NMAX + oB + j] = S[i * 4 + j];
+            gH0[(oB + j) * NMAX + oA + i] = H[i * 4 + j];
+            gS[(oB + j) * NMAX + oA + i] = S[i * 4 + j];
+          }
+        const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        double g, dg;
+        gamma_pair(P.U[sSp[A]], P.U[sSp[B]], r, g, dg);
+        gG[A * NMAX + B] = g;
+        gG[B * NMAX + A] = g;
+      }
+    }
+    __syncthreads();
+
+    // ---- S-orthonormal starting basis X: Cholesky of M = C0^T S C0
+    const bool warm = (a.flags & JF_WARM_C) != 0;
+    if (warm) {
+      const double* wc = a.ws_C + a.ws_off[u];
+      for (int e = tid; e < n * n; e += NT) {
+        const int i = e / n, j = e % n;
+        sX[i * NMAX + j] = wc[i * NMAX + j];
+        sA[i * NMAX + j] = gS[i * NMAX + j];
+      }
+      __syncthreads();
+      gemm_nn<NMAX, NT>(sA, sX, sT, n);  // T = S C0
+      __syncthreads();
+      gemm_tn<NMAX, NT>(sX, sT, sA, n);  // M = C0^T S C0
+      __syncthreads();
+    } else {
+      for (int e = tid; e < n * n; e += NT) {
+        const int i = e / n, j = e % n;
+        sX[i * NMAX + j] = (i == j) ? 1.0 : 0.0;
+        sA[i * NMAX + j] = gS[i * NMAX + j];
+      }
+      __syncthreads();
+    }
+    // in-place upper Cholesky M = R^T R in sA
+    for (int k = 0; k < n; ++k) {
+      if (tid == 0) {
+        double dkk = sA[k * NMAX + k];
+        if (!(dkk > 0.0)) {
+          sh.notpd |= 1;
+          dkk = 1.0;
+        }
+        sA[k * NMAX + k] = sqrt(dkk);
+      }
+      __syncthreads();
+      const double rkk = sA[k * NMAX + k];
+      for (int j = k + 1 + tid; j < n; j += NT) sA[k * NMAX + j] /= rkk;
+      __syncthreads();
+      const int m = n - k - 1;
+      for (int idx = tid; idx < m * m; idx += NT) {
+        const int i = k + 1 + idx / m, j = k + 1 + idx % m;
+        if (j >= i) sA[i * NMAX + j] -= sA[k * NMAX + i] * sA[k * NMAX + j];
+      }
+      __syncthreads();
+    }
+    // X <- C0 R^{-1}, row by row
+    for (int i = tid; i < n; i += NT) {
+      for (int j = 0; j < n; ++j) {
+        double s = sX[i * NMAX + j];
+        for (int l = 0; l < j; ++l) s -= sX[i * NMAX + l] * sA[l * NMAX + j];
+        sX[i * NMAX + j] = s / sA[j * NMAX + j];
+      }
+    }
+    __syncthreads();
+    int status = 0;
+    if (sh.notpd) status |= (sh.notpd & 2) ? CAVDFTB_ST_NAN : CAVDFTB_ST_NOT_PD;
+
+    int it = 0;
+    if (status == 0) {
+      for (it = 1; it <= a.max_iter; ++it) {
+        // V = gamma Dq_in ; H = H0 + 1/2 S o (V_a + V_b) into sA
+        for (int t = tid; t < na; t += NT) {
+          double v = 0.0;
+          for (int c = 0; c < na; ++c) v += gG[t * NMAX + c] * sDqIn[c];
+          sV[t] = v;
+        }
+        __syncthreads();
+        for (int e = tid; e < n * n; e += NT) {
+          const int i = e / n, j = e % n;
+          sA[i * NMAX + j] =
+              gH0[i * NMAX + j] + 0.5 * gS[i * NMAX + j] * (sV[sOrbAtom[i]] + sV[sOrbAtom[j]]);
+        }
+        __syncthreads();
+        gemm_nn<NMAX, NT>(sA, sX, sT, n);  // T = H X
+        __syncthreads();
+        gemm_tn<NMAX, NT>(sX, sT, sA, n);  // A = X^T H X
+        __syncthreads();
+        for (int e = tid; e < n * n; e += NT) {
+          const int i = e / n, j = e % n;
+          if (j > i) {
+            const double v = 0.5 * (sA[i * NMAX + j] + sA[j * NMAX + i]);
+            sA[i * NMAX + j] = v;
+            sA[j * NMAX + i] = v;
+          }
+        }
+        __syncthreads();
+
+        // ---- cyclic parallel Jacobi on A, rotations accumulated into X
+        const int half = n / 2;
+        for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
+          double off = 0.0;
+          for (int e = tid; e < n * n; e += NT) {
+            const int i = e / n, j = e % n;
+            if (j > i) off = fmax(off, fabs(sA[i * NMAX + j]));
+          }
+          if (block_max<NT>(off, sRed) < kJacobiThr) break;
+          for (int r = 0; r < n - 1; ++r) {
+            if (tid < half) {
+              int p = rr_index(tid, r, n), q = rr_index(n - 1 - tid, r, n);
+              if (p > q) {
+                const int tmp = p;
+                p = q;
+                q = tmp;
+              }
+              const double apq = sA[p * NMAX + q];
+              double c = 1.0, s = 0.0, t = 0.0;
+              if (fabs(apq) > 1.0e-300) {
+                const double theta = (sA[q * NMAX + q] - sA[p * NMAX + p]) / (2.0 * apq);
+                t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                c = 1.0 / sqrt(t * t + 1.0);
+                s = t * c;
+              }
+              sRp[tid] = p;
+              sRq[tid] = q;
+              sRc[tid] = c;
+              sRs[tid] = s;
+              sRt[tid] = t;
+            }
+            __syncthreads();
+            for (int task = tid; task < half * half; task += NT) {
+              const int k = task / half, l = task % half;
+              const int p = sRp[k], q = sRq[k];
+              if (k == l) {
+                const double apq = sA[p * NMAX + q], t = sRt[k];
+                sA[p * NMAX + p] -= t * apq;
+                sA[q * NMAX + q] += t * apq;
+                if (t != 0.0) {
+                  sA[p * NMAX + q] = 0.0;
+                  sA[q * NMAX + p] = 0.0;
+                }
+              } else {
+                const int pl = sRp[l], ql = sRq[l];
+                const double ck = sRc[k], sk = sRs[k], cl = sRc[l], sl = sRs[l];
+                const double b00 = sA[p * NMAX + pl], b01 = sA[p * NMAX + ql];
+                const double b10 = sA[q * NMAX + pl], b11 = sA[q * NMAX + ql];
+                const double r00 = ck * b00 - sk * b10, r01 = ck * b01 - sk * b11;
+                const double r10 = sk * b00 + ck * b10, r11 = sk * b01 + ck * b11;
+                sA[p * NMAX + pl] = cl * r00 - sl * r01;
+                sA[p * NMAX + ql] = sl * r00 + cl * r01;
+                sA[q * NMAX + pl] = cl * r10 - sl * r11;
+                sA[q * NMAX + ql] = sl * r10 + cl * r11;
+              }
+            }
+            for (int task = tid; task < half * n; task += NT) {
+              const int k = task / n, i = task % n;
+              const int p = sRp[k], q = sRq[k];
+              const double c = sRc[k], s = sRs[k];
+              const double xp = sX[i * NMAX + p], xq = sX[i * NMAX + q];
+              sX[i * NMAX + p] = c * xp - s * xq;
+              sX[i * NMAX + q] = s * xp + c * xq;
+            }
+            __syncthreads();
+          }
+        }
+
+        // ---- aufbau occupation from the eigenvalues on the diagonal
+        for (int i = tid; i < n; i += NT) sEig[i] = sA[i * NMAX + i];
+        __syncthreads();
+        for (int i = tid; i < n; i += NT) {
+          const double li = sEig[i];
+          int rank = 0;
+          for (int j = 0; j < n; ++j) {
+            const double lj = sEig[j];
+            rank += (lj < li || (lj == li && j < i)) ? 1 : 0;
+          }
+          sW[i] = rank < nocc ? 2.0 : 0.0;
+          if (rank < nocc) sOcc[rank] = i;
+          if (rank == nocc - 1) sh.homo = li;
+          if (rank == nocc) sh.lumo = li;
+        }
+        __syncthreads();
+        // ---- P = 2 C_occ C_occ^T into sT ; Mulliken charges
+        gemm_xwxt<NMAX, NT>(sX, sW, sOcc, nocc, sT);
+        __syncthreads();
+        for (int i = tid; i < n; i += NT) {
+          double q = 0.0;
+          for (int j = 0; j < n; ++j) q += sT[i * NMAX + j] * gS[i * NMAX + j];
+          sQorb[i] = q;
+        }
+        __syncthreads();
+        double res = 0.0;
+        for (int t = tid; t < na; t += NT) {
+          double q = 0.0;
+          for (int o = sAtomOff[t]; o < sAtomOff[t + 1]; ++o) q += sQorb[o];
+          sDqOut[t] = q - sQ0[t];
+          const double dlt = fabs(sDqOut[t] - sDqIn[t]);
+          res = (dlt == dlt) ? fmax(res, dlt) : INFINITY;
+        }
+        res = block_max<NT>(res, sRed);
+        if (res < a.tol) break;  // block-uniform
+        if (!(res < INFINITY)) {
+          status |= CAVDFTB_ST_NAN;
+          break;
+        }
+
+        // ---- Johnson's modified Broyden mixing
+        if (it > 1) {
+          double part = 0.0;
+          for (int t = tid; t < na; t += NT) {
+            const double df = (sDqOut[t] - sDqIn[t]) - bFp[t];
+            part += df * df;
+          }
+          const double nrm = sqrt(block_sum<NT>(part, sRed));
+          if (nrm > 1.0e-300) {
+            const int slot = sh.bcount < kMaxHist ? sh.bcount : sh.bhead;
+            for (int t = tid; t < na; t += NT) {
+              const double df = ((sDqOut[t] - sDqIn[t]) - bFp[t]) / nrm;
+              bDF[slot * NMAX + t] = df;
+              bU[slot * NMAX + t] = a.alpha * df + (sDqIn[t] - bXp[t]) / nrm;
+            }
+            __syncthreads();
+            if (tid == 0) {
+              if (sh.bcount < kMaxHist)
+                sh.bcount += 1;
+              else
+                sh.bhead = (sh.bhead + 1) % kMaxHist;
+            }
+          }
+        }
+        for (int t = tid; t < na; t += NT) {
+          bXp[t] = sDqIn[t];
+          bFp[t] = sDqOut[t] - sDqIn[t];
+        }
+        __syncthreads();
+        const int m = sh.bcount;
+        if (m > 0) {
+          for (int task = tid; task < m * m + m; task += NT) {
+            const int i = task / (m + 1), j = task % (m + 1);
+            double s = 0.0;
+            if (j < m) {
+              for (int t = 0; t < na; ++t) s += bDF[i * NMAX + t] * bDF[j * NMAX + t];
+              sBa[i * kMaxHist + j] = s + (i == j ? a.w0 * a.w0 : 0.0);
+            } else {
+              for (int t = 0; t < na; ++t) s += bDF[i * NMAX + t] * bFp[t];
+              sBc[i] = s;
+            }
+          }
+          __syncthreads();
+          if (tid == 0) {  // solve (w0^2 I + a) g = c by Cholesky (m <= 20)
+            for (int k = 0; k < m; ++k) {
+              double d = sBa[k * kMaxHist + k];
+              for (int l = 0; l < k; ++l) d -= sBa[k * kMaxHist + l] * sBa[k * kMaxHist + l];
+              d = sqrt(d);
+              sBa[k * kMaxHist + k] = d;
+              for (int i = k + 1; i < m; ++i) {
+                double v = sBa[i * kMaxHist + k];
+                for (int l = 0; l < k; ++l) v -= sBa[i * kMaxHist + l] * sBa[k * kMaxHist + l];
+                sBa[i * kMaxHist + k] = v / d;
+              }
+            }
+            for (int i = 0; i < m; ++i) {
+              double v = sBc[i];
+              for (int l = 0; l < i; ++l) v -= sBa[i * kMaxHist + l] * sBg[l];
+              sBg[i] = v / sBa[i * kMaxHist + i];
+            }
+            for (int i = m - 1; i >= 0; --i) {
+              double v = sBg[i];
+              for (int l = i + 1; l < m; ++l) v -= sBa[l * kMaxHist + i] * sBg[l];
+              sBg[i] = v / sBa[i * kMaxHist + i];
+            }
+          }
+          __syncthreads();
+        }
+        for (int t = tid; t < na; t += NT) {
+          double x = sDqIn[t] + a.alpha * bFp[t];
+          for (int k = 0; k < m; ++k) x -= sBg[k] * bU[k * NMAX + t];
+          sDqIn[t] = x;
+        }
+        __syncthreads();
+      }
+      if (it > a.max_iter) {
+        status |= CAVDFTB_ST_NOT_CONVERGED;
+        it = a.max_iter;
+      }
+      if (nocc < n && sh.lumo - sh.homo < kGapMin) status |= CAVDFTB_ST_DEGENERATE;
+    }
+
+    // ---- outputs
+    if (status == 0 && (a.flags & JF_STORE)) {
+      double* wc = a.ws_C + a.ws_off[u];
+      for (int e = tid; e < n * n; e += NT) {
+        const int i = e / n, j = e % n;
+        wc[i * NMAX + j] = sX[i * NMAX + j];
+      }
+      for (int t = tid; t < na; t += NT) a.ws_dq[a0 + t] = sDqOut[t];
+    }
+    if (status & (CAVDFTB_ST_NOT_PD | CAVDFTB_ST_NAN)) {
+      for (int t = tid; t < na; t += NT) sDqOut[t] = 0.0;
+    }
+    __syncthreads();
+    // dipole mu = sum_A Q_A R_A with Q = -Dq
+    if (tid < 3) {
+      double m = 0.0;
+      for (int t = 0; t < na; ++t) m -= sDqOut[t] * sPos[t * 3 + tid];
+      if (disp >= 0) {
+        if (a.mu_job) a.mu_job[(int64_t)job * 3 + tid] = m;
+      } else if (a.dipole) {
+        a.dipole[(int64_t)u * 3 + tid] = m;
+      }
+    }
+    if (disp < 0) {
+      for (int t = tid; t < na; t += NT)
+        if (a.charges) a.charges[a0 + t] = -sDqOut[t];
+    }
+    if ((a.flags & JF_FORCES) && disp < 0) {
+      // V from the output charges, W = 2 C_occ eps C_occ^T into sA
+      for (int t = tid; t < na; t += NT) {
+        double v = 0.0;
+        for (int c = 0; c < na; ++c) v += gG[t * NMAX + c] * sDqOut[c];
+        sV[t] = v;
+      }
+      for (int i = tid; i < n; i += NT) sQorb[i] = sW[i] * sEig[i];  // occupation x eigenvalue
+      __syncthreads();
+      gemm_xwxt<NMAX, NT>(sX, sQorb, sOcc, nocc, sA);
+      __syncthreads();
+      double ebp = 0.0;
+      for (int e = tid; e < n * n; e += NT) {
+        const int i = e / n, j = e % n;
+        ebp += sT[i * NMAX + j] * gH0[i * NMAX + j];
+      }
+      double ecp = 0.0;
+      for (int t = tid; t < na; t += NT) ecp += 0.5 * sDqOut[t] * sV[t];
+      // pair forces: task (A, part) sums g(A,B) over its B's
+      constexpr int SPLIT = (NT / NMAX) > 0 ? NT / NMAX : 1;
+      double erp = 0.0;
+      double fa[3] = {0.0, 0.0, 0.0};
+      const int A = tid / SPLIT, part = tid % SPLIT;
+      if (A < na && (status & (CAVDFTB_ST_NOT_PD | CAVDFTB_ST_NAN)) == 0) {
+        const int oA = sAtomOff[A];
+        for (int B = part; B < na; B += SPLIT) {
+          if (B == A) continue;
+          const int oB = sAtomOff[B];
+          double d[3];
+          for (int g = 0; g < 3; ++g) d[g] = sPos[B * 3 + g] - sPos[A * 3 + g];
+          const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+          pair_band_grad(P, sSp[A], sSp[B], d, sT, sA, NMAX, oA, oB, sV[A] + sV[B], fa);
+          double gm, dgm;
+          gamma_pair(P.U[sSp[A]], P.U[sSp[B]], r, gm, dgm);
+          const int pt = sSp[A] + sSp[B];
+          const double vrep = P.rep_a[pt] * exp(-P.rep_alpha[pt] * r);
+          erp += 0.5 * vrep;
+          const double radial_g = sDqOut[A] * sDqOut[B] * dgm - P.rep_alpha[pt] * vrep;
+          for (int g = 0; g < 3; ++g) fa[g] += radial_g * d[g] / r;
+        }
+      }
+      for (int g = 0; g < 3; ++g) sF[tid * 3 + g] = fa[g];
+      const double etot = block_sum<NT>(ebp + ecp + erp, sRed);  // contains the barrier for sF
+      for (int t = tid; t < na; t += NT) {
+        for (int g = 0; g < 3; ++g) {
+          double f = 0.0;
+          for (int pp = 0; pp < SPLIT; ++pp) f += sF[(t * SPLIT + pp) * 3 + g];
+          if (a.forces) a.forces[(int64_t)(a0 + t) * 3 + g] = f;
+        }
+      }
+      if (tid == 0 && a.energy) a.energy[u] = etot;
+    }
+    if (tid == 0) {
+      if (disp < 0 && a.status) a.status[u] = status;
+      if (a.job_status) a.job_status[job] = status;
+      if (a.job_iters) a.job_iters[job] = it;
+      if (a.counters) {
+        const unsigned long long nn = n, no = nocc;
+        const unsigned long long per_it = 10ull * nn * nn * nn + 2ull * nn * nn * no;
+        const unsigned long long per_geo = nn * nn * nn / 3ull + 2ull * nn * nn * no;
+        atomicAdd(&a.counters[0], 1ull);
+        atomicAdd(&a.counters[1], (unsigned long long)it);
+        atomicAdd(&a.counters[2], per_it * (unsigned long long)it + per_geo);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+int64_t scc_scratch_per_wg(int nmax) { return 3LL * nmax * nmax + (2LL + 2LL * kMaxHist) * nmax; }
+
+template <int NMAX, int NT>
+static hipError_t launch_t(int n_wg, const SccArgs& args, hipStream_t stream) {
+  hipLaunchKernelGGL((scc_kernel<NMAX, NT>), dim3(n_wg), dim3(NT), 0, stream, args);
+  return hipGetLastError();
+}
+
+template <int NMAX, int NT>
+static int occ_t() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, scc_kernel<NMAX, NT>, NT, 0) != hipSuccess) return 1;
+  return nb > 0 ? nb : 1;
+}
+
+hipError_t launch_scc(int nmax, int n_wg, const SccArgs& args, hipStream_t stream) {
+  switch (nmax) {
+    case 8: return launch_t<8, 64>(n_wg, args, stream);
+    case 16: return launch_t<16, 64>(n_wg, args, stream);
+    case 32: return launch_t<32, 256>(n_wg, args, stream);
+    case 48: return launch_t<48, 256>(n_wg, args, stream);
+    case 64: return launch_t<64, 256>(n_wg, args, stream);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+int scc_blocks_per_cu(int nmax) {
+  switch (nmax) {
+    case 8: return occ_t<8, 64>();
+    case 16: return occ_t<16, 64>();
+    case 32: return occ_t<32, 256>();
+    case 48: return occ_t<48, 256>();
+    case 64: return occ_t<64, 256>();
+    default: return 1;
+  }
+}
+
+}  // namespace cavdftb
