@@ -105,9 +105,20 @@ int cavdftb_destroy(cavdftb_ctx* ctx);
  * max_A |Dq_out - Dq_in| < tol. */
 int cavdftb_set_scc(cavdftb_ctx* ctx, double tol, int32_t max_iter, double mix_alpha);
 
+/* Solver tuning (results are unchanged to within the SCC tolerance):
+ *   jacobi_res_factor (default 1e-3): inside the SCC loop the Jacobi
+ *     eigensolver stops once every off-diagonal element of the rotated
+ *     Hamiltonian is below max(1e-14, jacobi_res_factor x previous charge
+ *     residual); 0 means always 1e-14 (hartree).
+ *   keep_mixer_history (default 1): a unit's Broyden history survives between
+ *     its evaluations (MD steps) and seeds its displaced finite-difference SCCs.
+ * Returns CAVDFTB_EINVAL outside 0 <= jacobi_res_factor <= 1. */
+int cavdftb_set_tuning(cavdftb_ctx* ctx, double jacobi_res_factor, int32_t keep_mixer_history);
+
 /* Warm start: when enabled (default 1) each unit evaluation starts from the
- * charges and the molecular-orbital basis its previous evaluation stored.
- * cavdftb_reset_warm_start forgets them (the next evaluation starts cold). */
+ * charges, the molecular-orbital basis and the mixer history its previous
+ * evaluation stored.  cavdftb_reset_warm_start forgets them (the next
+ * evaluation starts cold). */
 int cavdftb_set_warm_start(cavdftb_ctx* ctx, int32_t enable);
 int cavdftb_reset_warm_start(cavdftb_ctx* ctx);
 
@@ -180,6 +191,7 @@ typedef struct cavdftb_counters {
   double scc_flops;
   double scc_kernel_ms;
   int64_t scc_launches;
+  int64_t jacobi_sweeps; /* Jacobi sweeps summed over all SCC iterations of all jobs */
 } cavdftb_counters;
 int cavdftb_enable_timing(cavdftb_ctx* ctx, int32_t enable);
 int cavdftb_read_counters(cavdftb_ctx* ctx, cavdftb_counters* out);

@@ -38,13 +38,14 @@ class Layout(ctypes.Structure):
 
 class Counters(ctypes.Structure):
     _fields_ = [("scc_jobs", ctypes.c_int64), ("scc_iterations", ctypes.c_int64), ("scc_flops", _c_d),
-                ("scc_kernel_ms", _c_d), ("scc_launches", ctypes.c_int64)]
+                ("scc_kernel_ms", _c_d), ("scc_launches", ctypes.c_int64), ("jacobi_sweeps", ctypes.c_int64)]
 
 
 SYMBOLS = {
     "cavdftb_create": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.POINTER(Layout), _vp, ctypes.POINTER(_vp)]),
     "cavdftb_destroy": (ctypes.c_int, [_vp]),
     "cavdftb_set_scc": (ctypes.c_int, [_vp, _c_d, _c_i32, _c_d]),
+    "cavdftb_set_tuning": (ctypes.c_int, [_vp, _c_d, _c_i32]),
     "cavdftb_set_warm_start": (ctypes.c_int, [_vp, _c_i32]),
     "cavdftb_reset_warm_start": (ctypes.c_int, [_vp]),
     "cavdftb_eval_units": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
@@ -168,6 +169,10 @@ class Context:
     # ---- entry points (same names as the C ABI without the prefix)
     def set_scc(self, tol, max_iter=200, mix_alpha=0.2):
         self._check(self.lib.cavdftb_set_scc(self.ctx, float(tol), int(max_iter), float(mix_alpha)), "set_scc")
+
+    def set_tuning(self, jacobi_res_factor=1e-3, keep_mixer_history=True):
+        self._check(self.lib.cavdftb_set_tuning(self.ctx, float(jacobi_res_factor), int(bool(keep_mixer_history))),
+                    "set_tuning")
 
     def set_warm_start(self, enable):
         self._check(self.lib.cavdftb_set_warm_start(self.ctx, int(bool(enable))), "set_warm_start")

@@ -63,6 +63,10 @@ struct cavdftb_ctx {
   int64_t* d_ws_off = nullptr;
   double* d_ws_C = nullptr;
   double* d_ws_dq = nullptr;
+  double* d_ws_dq_hist = nullptr;
+  int md_hist = 0;  // consecutive MD evaluations whose charges are stored
+  int64_t* d_hist_off = nullptr;
+  double* d_hist = nullptr;
   std::vector<Bucket> buckets;
   int n_fd_total = 0;
   // work arrays
@@ -78,6 +82,8 @@ struct cavdftb_ctx {
   int32_t max_iter = 200;
   double alpha = 0.2;
   double w0 = 0.01;
+  double jac_factor = 1.0e-3;
+  int keep_hist = 1;
   int warm_enabled = 1;
   bool warm_valid = false;
   bool primed = false;
@@ -156,6 +162,10 @@ SccArgs base_args(cavdftb_ctx* c, const double* pos) {
   a.ws_off = c->d_ws_off;
   a.ws_C = c->d_ws_C;
   a.ws_dq = c->d_ws_dq;
+  a.n_atoms = c->NA;
+  a.hist = c->d_hist;
+  a.hist_off = c->d_hist_off;
+  a.jac_factor = c->jac_factor;
   a.counters = c->d_counters;
   a.tol = c->tol;
   a.max_iter = c->max_iter;
@@ -186,11 +196,21 @@ int run_scc(cavdftb_ctx* c, const Bucket& b, SccArgs& a) {
 }
 
 // SCC of every unit at pos (center jobs); writes the context work arrays
-int eval_center(cavdftb_ctx* c, const double* pos, bool forces) {
-  int32_t flags = JF_STORE | (forces ? JF_FORCES : 0);
-  if (c->warm_enabled && c->warm_valid) flags |= JF_WARM_C | JF_WARM_DQ;
+int32_t center_flags(cavdftb_ctx* c, bool forces) {
+  int32_t flags = JF_STORE | JF_STORE_HIST | (forces ? JF_FORCES : 0);
+  if (c->warm_enabled && c->warm_valid) flags |= JF_WARM_C | JF_WARM_DQ | (c->keep_hist ? JF_WARM_HIST : 0);
+  return flags;
+}
+
+int eval_center(cavdftb_ctx* c, const double* pos, bool forces, bool md = false) {
+  const int32_t flags = center_flags(c, forces);
+  const bool extrap = md && c->warm_enabled && c->warm_valid;
   for (const Bucket& b : c->buckets) {
     SccArgs a = base_args(c, pos);
+    if (md) {
+      a.ws_dq_hist = c->d_ws_dq_hist;
+      a.n_extrap = extrap ? (c->md_hist < 3 ? c->md_hist : 3) : 0;
+    }
     a.job_unit = b.d_units;
     a.job_disp = nullptr;
     a.n_jobs = b.n_units;
@@ -205,6 +225,7 @@ int eval_center(cavdftb_ctx* c, const double* pos, bool forces) {
     int rc = run_scc(c, b, a);
     if (rc) return rc;
   }
+  c->md_hist = (md && extrap) ? c->md_hist + 1 : (md && c->warm_enabled ? 1 : 0);
   c->warm_valid = c->warm_enabled != 0;
   return CAVDFTB_OK;
 }
@@ -220,7 +241,7 @@ int eval_fd(cavdftb_ctx* c, const double* pos, double h, double* born) {
     a.mu_job = c->d_mu_job + (int64_t)b.fjob0 * 3;
     a.job_status = c->d_fjob_status + b.fjob0;
     a.job_iters = c->d_fjob_iters + b.fjob0;
-    a.flags = JF_WARM_C | JF_WARM_DQ;
+    a.flags = JF_WARM_C | JF_WARM_DQ | (c->keep_hist ? JF_WARM_HIST : 0);
     int rc = run_scc(c, b, a);
     if (rc) return rc;
     hipError_t e = launch_born_fd_assemble(c->d_unit_off, b.d_fd_unit, b.d_fd_job0, b.n_units,
@@ -247,7 +268,7 @@ CavArgs cav_args(cavdftb_ctx* c) {
 
 // matter + Born stage at r: forces, energy, dipole, e.Z into the work arrays
 int matter_stage(cavdftb_ctx* c, const double* r, int born_mode, double h) {
-  int rc = eval_center(c, r, true);
+  int rc = eval_center(c, r, true, true);
   if (rc) return rc;
   hipError_t e;
   if (born_mode == CAVDFTB_BORN_FD) {
@@ -332,8 +353,8 @@ int cavdftb_create(const cavdftb_params* params, const cavdftb_layout* L, void* 
   if (n_cu <= 0) n_cu = 256;
 
   const int nmaxs[5] = {8, 16, 32, 48, 64};
-  std::vector<int64_t> ws_off(U);
-  int64_t ws_total = 0;
+  std::vector<int64_t> ws_off(U), hist_off(U);
+  int64_t ws_total = 0, hist_total = 0;
   std::vector<std::vector<int32_t>> bunits(5);
   for (int u = 0; u < U; ++u) {
     const int nm = bucket_of(n_orb[u]);
@@ -341,6 +362,8 @@ int cavdftb_create(const cavdftb_params* params, const cavdftb_layout* L, void* 
       if (nmaxs[k] == nm) bunits[k].push_back(u);
     ws_off[u] = ws_total;
     ws_total += (int64_t)nm * nm;
+    hist_off[u] = hist_total;
+    hist_total += hist_doubles(nm);
   }
   hipError_t e = hipSuccess;
 #define CK(x)                                  \
@@ -366,6 +389,9 @@ int cavdftb_create(const cavdftb_params* params, const cavdftb_layout* L, void* 
   CK(dalloc(c, &c->d_ws_off, U));
   CK(dalloc(c, &c->d_ws_C, ws_total));
   CK(dalloc(c, &c->d_ws_dq, NA));
+  CK(dalloc(c, &c->d_ws_dq_hist, 2 * (size_t)NA));
+  CK(dalloc(c, &c->d_hist_off, U));
+  CK(dalloc(c, &c->d_hist, hist_total));
   CK(dalloc(c, &c->d_energy, U));
   CK(dalloc(c, &c->d_forces, (size_t)NA * 3));
   CK(dalloc(c, &c->d_charges, NA));
@@ -393,6 +419,8 @@ int cavdftb_create(const cavdftb_params* params, const cavdftb_layout* L, void* 
   CK(hipMemcpy(c->d_inv_mass, inv_mass.data(), NA * sizeof(double), hipMemcpyHostToDevice));
   CK(hipMemcpy(c->d_ws_off, ws_off.data(), U * sizeof(int64_t), hipMemcpyHostToDevice));
   CK(hipMemset(c->d_ws_dq, 0, NA * sizeof(double)));
+  CK(hipMemcpy(c->d_hist_off, hist_off.data(), U * sizeof(int64_t), hipMemcpyHostToDevice));
+  CK(hipMemset(c->d_hist, 0, hist_total * sizeof(double)));
   CK(hipMemset(c->d_counters, 0, 4 * sizeof(unsigned long long)));
   CK(hipMemset(c->d_status, 0, U * sizeof(int32_t)));
   CK(hipMemset(c->d_cjob_iters, 0, U * sizeof(int32_t)));
@@ -468,6 +496,15 @@ int cavdftb_set_scc(cavdftb_ctx* ctx, double tol, int32_t max_iter, double mix_a
   return CAVDFTB_OK;
 }
 
+int cavdftb_set_tuning(cavdftb_ctx* ctx, double jacobi_res_factor, int32_t keep_mixer_history) {
+  if (!ctx) return CAVDFTB_EINVAL;
+  if (!(jacobi_res_factor >= 0.0) || jacobi_res_factor > 1.0)
+    return fail(ctx, CAVDFTB_EINVAL, "set_tuning: need 0 <= jacobi_res_factor <= 1");
+  ctx->jac_factor = jacobi_res_factor;
+  ctx->keep_hist = keep_mixer_history ? 1 : 0;
+  return CAVDFTB_OK;
+}
+
 int cavdftb_set_warm_start(cavdftb_ctx* ctx, int32_t enable) {
   if (!ctx) return CAVDFTB_EINVAL;
   ctx->warm_enabled = enable ? 1 : 0;
@@ -478,6 +515,7 @@ int cavdftb_set_warm_start(cavdftb_ctx* ctx, int32_t enable) {
 int cavdftb_reset_warm_start(cavdftb_ctx* ctx) {
   if (!ctx) return CAVDFTB_EINVAL;
   ctx->warm_valid = false;
+  ctx->md_hist = 0;
   return CAVDFTB_OK;
 }
 
@@ -486,8 +524,7 @@ int cavdftb_eval_units(cavdftb_ctx* ctx, const double* pos, double* energy, doub
   if (!ctx || !pos || !unit_status) return ctx ? fail(ctx, CAVDFTB_EINVAL, "eval_units: null pointer")
                                                : CAVDFTB_EINVAL;
   const bool want_f = energy || forces;
-  int32_t flags = JF_STORE | (want_f ? JF_FORCES : 0);
-  if (ctx->warm_enabled && ctx->warm_valid) flags |= JF_WARM_C | JF_WARM_DQ;
+  const int32_t flags = center_flags(ctx, want_f);
   for (const Bucket& b : ctx->buckets) {
     SccArgs a = base_args(ctx, pos);
     a.job_unit = b.d_units;
@@ -505,6 +542,7 @@ int cavdftb_eval_units(cavdftb_ctx* ctx, const double* pos, double* energy, doub
   }
   ctx->warm_valid = ctx->warm_enabled != 0;
   ctx->primed = false;
+  ctx->md_hist = 0;
   return CAVDFTB_OK;
 }
 
@@ -646,6 +684,7 @@ int cavdftb_read_counters(cavdftb_ctx* ctx, cavdftb_counters* out) {
   out->scc_flops = (double)h[2];
   out->scc_kernel_ms = ctx->t_ms;
   out->scc_launches = ctx->launches;
+  out->jacobi_sweeps = (int64_t)h[3];
   return CAVDFTB_OK;
 }
 

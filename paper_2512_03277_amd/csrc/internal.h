@@ -22,6 +22,8 @@ enum : int32_t {
   JF_WARM_C = 2,   // start from the stored MO basis of the unit
   JF_WARM_DQ = 4,  // start from the stored charges of the unit
   JF_STORE = 8,    // store basis and charges after convergence
+  JF_WARM_HIST = 16,   // start the mixer from the unit's stored Broyden history
+  JF_STORE_HIST = 32,  // keep the Broyden history in the unit's store afterwards
 };
 
 constexpr int kMaxHist = 20;  // Broyden window
@@ -38,6 +40,11 @@ struct SccArgs {
   const int64_t* ws_off;    // [n_units] offset of the unit's stored basis in ws_C (doubles)
   double* ws_C;             // stored MO bases, NMAX x NMAX per unit of the bucket
   double* ws_dq;            // [n_atoms] stored charges (electron excess)
+  double* ws_dq_hist;       // [2][n_atoms] charges of the two MD steps before, or nullptr
+  int32_t n_extrap;         // stored MD steps usable for extrapolating the start charges (0..3)
+  int32_t n_atoms;
+  double* hist;             // per-unit Broyden history store (or nullptr)
+  const int64_t* hist_off;  // [n_units] offset of each unit's history block
   double* scratch;          // [gridDim.x][scratch_per_wg]
   int64_t scratch_per_wg;
   double* energy;           // [n_units] or nullptr
@@ -53,8 +60,12 @@ struct SccArgs {
   int32_t max_iter;
   double alpha;
   double w0;
+  double jac_factor;        // Jacobi off-diagonal target = max(1e-14, jac_factor * previous SCC residual)
   int32_t flags;
 };
+
+// doubles of Broyden history kept per unit of a bucket
+inline int64_t hist_doubles(int nmax) { return 2 + (int64_t)kMaxHist * kMaxHist + 2LL * kMaxHist * nmax; }
 
 // scratch doubles needed per workgroup for a bucket
 int64_t scc_scratch_per_wg(int nmax);

@@ -19,8 +19,9 @@
 //   W = 2 C_occ eps C_occ^T, E = Tr(P H0) + 1/2 Dq gamma Dq + E_rep and the
 //   pair-wise force contraction, all with fixed-order reductions.
 //
-// LDS holds the three n x n working matrices (X, A, T); H0, S and gamma live
-// in per-workgroup global scratch (L2 resident).
+// LDS holds the three n x n working matrices (X, A, T) with padded rows; H0,
+// S and gamma live in per-workgroup global scratch (L2 resident) and are read
+// with coalesced (row or, by symmetry, column) walks.
 #include <math.h>
 
 #include "internal.h"
@@ -120,6 +121,7 @@ __device__ void pair_band_grad(const DevParams& P, int spA, int spB, const doubl
   }
   if (nB == 4) {  // <s_A | p_B,b> = u_b V
     radial(P, t_sp, r, h, s, hp, sp);
+#pragma unroll 1
     for (int b = 0; b < 3; ++b) {
       const double pij = Pm[oA * ld + oB + 1 + b];
       const double wij = Wm[oA * ld + oB + 1 + b] - 0.5 * pij * vab;
@@ -132,6 +134,7 @@ __device__ void pair_band_grad(const DevParams& P, int spA, int spB, const doubl
   }
   if (nA == 4) {  // <p_A,a | s_B> = -u_a V
     radial(P, t_ps, r, h, s, hp, sp);
+#pragma unroll 1
     for (int a = 0; a < 3; ++a) {
       const double pij = Pm[(oA + 1 + a) * ld + oB];
       const double wij = Wm[(oA + 1 + a) * ld + oB] - 0.5 * pij * vab;
@@ -146,7 +149,9 @@ __device__ void pair_band_grad(const DevParams& P, int spA, int spB, const doubl
     double hs, ss, hsp, ssp, hpi, spi, hpip, spip;
     radial(P, 2, r, hs, ss, hsp, ssp);
     radial(P, 3, r, hpi, spi, hpip, spip);
+#pragma unroll 1
     for (int a = 0; a < 3; ++a)
+#pragma unroll 1
       for (int b = 0; b < 3; ++b) {
         const double pij = Pm[(oA + 1 + a) * ld + oB + 1 + b];
         const double wij = Wm[(oA + 1 + a) * ld + oB + 1 + b] - 0.5 * pij * vab;
@@ -224,18 +229,25 @@ __device__ double block_max(double v, double* red) {
   return r;
 }
 
+// LDS layout: n x n blocks of NMAX x LD doubles, LD = NMAX + 1 so that a
+// column walk (consecutive rows, one column) spreads over the LDS banks.
+// Elementwise loops use lane = column (tid & 63) and row groups tid >> 6, so
+// no integer division appears in the hot loops (n <= 64).
 template <int NMAX, int NT>
-struct Tile {
+struct Cfg {
+  static constexpr int LD = NMAX + 1;
   static constexpr int G = (NT == 256) ? 16 : 8;
   static constexpr int TM = NMAX / G;
+  static constexpr int RG = NT / 64;  // row groups of 64 lanes
   static_assert(TM * G == NMAX, "tile mismatch");
+  static_assert(NMAX <= 64, "one lane per column");
 };
 
-// C = A B over the leading n x n block (LD = NMAX); padding of A, B is zero.
+// C = A B over the leading n x n block; padding of A, B is zero.
 template <int NMAX, int NT>
 __device__ void gemm_nn(const double* __restrict__ A, const double* __restrict__ B, double* __restrict__ C,
                         int n) {
-  constexpr int G = Tile<NMAX, NT>::G, TM = Tile<NMAX, NT>::TM;
+  constexpr int G = Cfg<NMAX, NT>::G, TM = Cfg<NMAX, NT>::TM, LD = Cfg<NMAX, NT>::LD;
   const int tx = threadIdx.x % G, ty = threadIdx.x / G;
   double acc[TM][TM];
 #pragma unroll
@@ -245,9 +257,9 @@ __device__ void gemm_nn(const double* __restrict__ A, const double* __restrict__
   for (int k = 0; k < n; ++k) {
     double av[TM], bv[TM];
 #pragma unroll
-    for (int r = 0; r < TM; ++r) av[r] = A[(ty + G * r) * NMAX + k];
+    for (int r = 0; r < TM; ++r) av[r] = A[(ty + G * r) * LD + k];
 #pragma unroll
-    for (int c = 0; c < TM; ++c) bv[c] = B[k * NMAX + tx + G * c];
+    for (int c = 0; c < TM; ++c) bv[c] = B[k * LD + tx + G * c];
 #pragma unroll
     for (int r = 0; r < TM; ++r)
 #pragma unroll
@@ -256,14 +268,14 @@ __device__ void gemm_nn(const double* __restrict__ A, const double* __restrict__
 #pragma unroll
   for (int r = 0; r < TM; ++r)
 #pragma unroll
-    for (int c = 0; c < TM; ++c) C[(ty + G * r) * NMAX + tx + G * c] = acc[r][c];
+    for (int c = 0; c < TM; ++c) C[(ty + G * r) * LD + tx + G * c] = acc[r][c];
 }
 
 // C = A^T B
 template <int NMAX, int NT>
 __device__ void gemm_tn(const double* __restrict__ A, const double* __restrict__ B, double* __restrict__ C,
                         int n) {
-  constexpr int G = Tile<NMAX, NT>::G, TM = Tile<NMAX, NT>::TM;
+  constexpr int G = Cfg<NMAX, NT>::G, TM = Cfg<NMAX, NT>::TM, LD = Cfg<NMAX, NT>::LD;
   const int tx = threadIdx.x % G, ty = threadIdx.x / G;
   double acc[TM][TM];
 #pragma unroll
@@ -273,9 +285,9 @@ __device__ void gemm_tn(const double* __restrict__ A, const double* __restrict__
   for (int k = 0; k < n; ++k) {
     double av[TM], bv[TM];
 #pragma unroll
-    for (int r = 0; r < TM; ++r) av[r] = A[k * NMAX + ty + G * r];
+    for (int r = 0; r < TM; ++r) av[r] = A[k * LD + ty + G * r];
 #pragma unroll
-    for (int c = 0; c < TM; ++c) bv[c] = B[k * NMAX + tx + G * c];
+    for (int c = 0; c < TM; ++c) bv[c] = B[k * LD + tx + G * c];
 #pragma unroll
     for (int r = 0; r < TM; ++r)
 #pragma unroll
@@ -284,14 +296,14 @@ __device__ void gemm_tn(const double* __restrict__ A, const double* __restrict__
 #pragma unroll
   for (int r = 0; r < TM; ++r)
 #pragma unroll
-    for (int c = 0; c < TM; ++c) C[(ty + G * r) * NMAX + tx + G * c] = acc[r][c];
+    for (int c = 0; c < TM; ++c) C[(ty + G * r) * LD + tx + G * c] = acc[r][c];
 }
 
 // C = X diag(w) X^T restricted to the columns listed in idx[0..m)
 template <int NMAX, int NT>
 __device__ void gemm_xwxt(const double* __restrict__ X, const double* __restrict__ w, const int* __restrict__ idx,
                           int m, double* __restrict__ C) {
-  constexpr int G = Tile<NMAX, NT>::G, TM = Tile<NMAX, NT>::TM;
+  constexpr int G = Cfg<NMAX, NT>::G, TM = Cfg<NMAX, NT>::TM, LD = Cfg<NMAX, NT>::LD;
   const int tx = threadIdx.x % G, ty = threadIdx.x / G;
   double acc[TM][TM];
 #pragma unroll
@@ -303,9 +315,9 @@ __device__ void gemm_xwxt(const double* __restrict__ X, const double* __restrict
     const double wk = w[k];
     double av[TM], bv[TM];
 #pragma unroll
-    for (int r = 0; r < TM; ++r) av[r] = X[(ty + G * r) * NMAX + k] * wk;
+    for (int r = 0; r < TM; ++r) av[r] = X[(ty + G * r) * LD + k] * wk;
 #pragma unroll
-    for (int c = 0; c < TM; ++c) bv[c] = X[(tx + G * c) * NMAX + k];
+    for (int c = 0; c < TM; ++c) bv[c] = X[(tx + G * c) * LD + k];
 #pragma unroll
     for (int r = 0; r < TM; ++r)
 #pragma unroll
@@ -314,7 +326,7 @@ __device__ void gemm_xwxt(const double* __restrict__ X, const double* __restrict
 #pragma unroll
   for (int r = 0; r < TM; ++r)
 #pragma unroll
-    for (int c = 0; c < TM; ++c) C[(ty + G * r) * NMAX + tx + G * c] = acc[r][c];
+    for (int c = 0; c < TM; ++c) C[(ty + G * r) * LD + tx + G * c] = acc[r][c];
 }
 
 // index held by slot s in round r of the circle (round-robin) ordering of m indices
@@ -322,27 +334,35 @@ __device__ __forceinline__ int rr_index(int s, int r, int m) { return s == 0 ? 0
 
 struct Shared {
   int n, nocc, na, notpd;
-  int bcount, bhead, converged, n_iter;
+  int bcount, bhead, sweeps, pad;
   double homo, lumo;
 };
 
+
 template <int NMAX, int NT>
 __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
+  constexpr int LD = Cfg<NMAX, NT>::LD;
+  constexpr int RG = Cfg<NMAX, NT>::RG;
   constexpr int HALF = NMAX / 2;
-  __shared__ double sX[NMAX * NMAX];
-  __shared__ double sA[NMAX * NMAX];
-  __shared__ double sT[NMAX * NMAX];
+  constexpr int KSTEP_A = NT / 32;  // row-of-blocks step in the Jacobi block update
+  constexpr bool F_IN_X = NMAX * LD >= 3 * NT;
+  __shared__ double sX[NMAX * LD];
+  __shared__ double sA[NMAX * LD];
+  __shared__ double sT[NMAX * LD];
+  __shared__ double sFbuf[F_IN_X ? 1 : 3 * NT];
   __shared__ double sPos[NMAX * 3];
   __shared__ double sDqIn[NMAX], sDqOut[NMAX], sV[NMAX], sQ0[NMAX], sEig[NMAX], sW[NMAX], sQorb[NMAX];
   __shared__ int sOrbAtom[NMAX], sAtomOff[NMAX + 1], sSp[NMAX], sOcc[NMAX];
   __shared__ double sRed[NT];
-  __shared__ double sF[NT * 3];
-  __shared__ int sRp[HALF], sRq[HALF];
-  __shared__ double sRc[HALF], sRs[HALF], sRt[HALF];
-  __shared__ double sBa[kMaxHist * kMaxHist], sBc[kMaxHist], sBg[kMaxHist];
+  __shared__ int sRp[2][HALF], sRq[2][HALF];
+  __shared__ double sRc[2][HALF], sRs[2][HALF], sRt[2][HALF];
+  __shared__ double sBa[kMaxHist * kMaxHist], sBm[kMaxHist * (kMaxHist + 1)], sBc[kMaxHist], sBg[kMaxHist];
   __shared__ Shared sh;
+  double* sF = F_IN_X ? sX : sFbuf;
 
   const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int rgrp = tid >> 6;
   const DevParams& P = a.prm;
   double* scr = a.scratch + (int64_t)blockIdx.x * a.scratch_per_wg;
   double* gH0 = scr;
@@ -350,8 +370,8 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
   double* gG = scr + 2 * NMAX * NMAX;
   double* bXp = scr + 3 * NMAX * NMAX;
   double* bFp = bXp + NMAX;
-  double* bDF = bFp + NMAX;
-  double* bU = bDF + kMaxHist * NMAX;
+  double* sDF = bFp + NMAX;           // per-workgroup history (displaced jobs)
+  double* sU = sDF + kMaxHist * NMAX;
 
   for (int job = blockIdx.x; job < a.n_jobs; job += gridDim.x) {
     const int u = a.job_unit[job];
@@ -361,14 +381,20 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
     const int d_atom = disp >= 0 ? (disp >> 1) / 3 : -1;
     const int d_dir = disp >= 0 ? (disp >> 1) % 3 : 0;
     const double d_step = disp >= 0 ? ((disp & 1) ? -a.fd_h : a.fd_h) : 0.0;
+    // Broyden history: the unit's own store for undisplaced jobs (read-write),
+    // a workgroup copy of it for displaced jobs (read-only use of the store)
+    double* hst = a.hist ? a.hist + a.hist_off[u] : nullptr;  // [count, head, Gram H*H, dF H*NMAX, U H*NMAX]
+    const bool own_hist = hst && disp < 0 && (a.flags & JF_STORE_HIST);
+    double* bDF = own_hist ? hst + 2 + kMaxHist * kMaxHist : sDF;
+    double* bU = bDF + kMaxHist * NMAX;
 
-    // ---- load atoms
+    // ---- load atoms, clear the working matrices
     for (int t = tid; t < na; t += NT) {
       sSp[t] = a.species[a0 + t];
       for (int g = 0; g < 3; ++g) sPos[t * 3 + g] = a.pos[(int64_t)(a0 + t) * 3 + g];
       if (t == d_atom) sPos[t * 3 + d_dir] += d_step;
     }
-    for (int e = tid; e < NMAX * NMAX; e += NT) {
+    for (int e = tid; e < NMAX * LD; e += NT) {
       sX[e] = 0.0;
       sA[e] = 0.0;
       sT[e] = 0.0;
@@ -391,14 +417,32 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
       sh.notpd = bad ? 2 : 0;  // 2 marks a non-finite position
       sh.bcount = 0;
       sh.bhead = 0;
-      sh.converged = 0;
+      if (hst && (a.flags & JF_WARM_HIST)) {
+        sh.bcount = (int)hst[0];
+        sh.bhead = (int)hst[1];
+      }
+      sh.sweeps = 0;
     }
     __syncthreads();
     const int n = sh.n, nocc = sh.nocc;
     for (int t = tid; t < na; t += NT) {
       for (int o = sAtomOff[t]; o < sAtomOff[t + 1]; ++o) sOrbAtom[o] = t;
       sQ0[t] = P.q0[sSp[t]];
-      sDqIn[t] = (a.flags & JF_WARM_DQ) ? a.ws_dq[a0 + t] : 0.0;
+      double dq0 = (a.flags & JF_WARM_DQ) ? a.ws_dq[a0 + t] : 0.0;
+      if ((a.flags & JF_WARM_DQ) && a.n_extrap >= 2) {  // charges of earlier MD steps
+        const double d1 = a.ws_dq_hist[a0 + t], d2 = a.ws_dq_hist[(int64_t)a.n_atoms + a0 + t];
+        dq0 = a.n_extrap >= 3 ? 3.0 * dq0 - 3.0 * d1 + d2 : 2.0 * dq0 - d1;
+      }
+      sDqIn[t] = dq0;
+    }
+    {
+      const int m0 = sh.bcount;
+      for (int e = tid; e < m0 * kMaxHist; e += NT) sBa[e] = hst[2 + e];
+      if (!own_hist)
+        for (int e = tid; e < m0 * NMAX; e += NT) {
+          bDF[e] = hst[2 + kMaxHist * kMaxHist + e];
+          bU[e] = hst[2 + kMaxHist * kMaxHist + kMaxHist * NMAX + e];
+        }
     }
 
     // ---- H0, S (global scratch) and gamma
@@ -435,161 +479,174 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
     }
     __syncthreads();
 
-    // ---- S-orthonormal starting basis X: Cholesky of M = C0^T S C0
+    // ---- S-orthonormal starting basis X = C0 R^{-1}, M = C0^T S C0 = R^T R
     const bool warm = (a.flags & JF_WARM_C) != 0;
     if (warm) {
       const double* wc = a.ws_C + a.ws_off[u];
-      for (int e = tid; e < n * n; e += NT) {
-        const int i = e / n, j = e % n;
-        sX[i * NMAX + j] = wc[i * NMAX + j];
-        sA[i * NMAX + j] = gS[i * NMAX + j];
-      }
+      for (int i = rgrp; i < n; i += RG)
+        if (lane < n) {
+          sX[i * LD + lane] = wc[i * NMAX + lane];
+          sA[i * LD + lane] = gS[i * NMAX + lane];
+        }
       __syncthreads();
       gemm_nn<NMAX, NT>(sA, sX, sT, n);  // T = S C0
       __syncthreads();
       gemm_tn<NMAX, NT>(sX, sT, sA, n);  // M = C0^T S C0
       __syncthreads();
     } else {
-      for (int e = tid; e < n * n; e += NT) {
-        const int i = e / n, j = e % n;
-        sX[i * NMAX + j] = (i == j) ? 1.0 : 0.0;
-        sA[i * NMAX + j] = gS[i * NMAX + j];
-      }
-      __syncthreads();
-    }
-    // in-place upper Cholesky M = R^T R in sA
-    for (int k = 0; k < n; ++k) {
-      if (tid == 0) {
-        double dkk = sA[k * NMAX + k];
-        if (!(dkk > 0.0)) {
-          sh.notpd |= 1;
-          dkk = 1.0;
+      for (int i = rgrp; i < n; i += RG)
+        if (lane < n) {
+          sX[i * LD + lane] = (i == lane) ? 1.0 : 0.0;
+          sA[i * LD + lane] = gS[i * NMAX + lane];
         }
-        sA[k * NMAX + k] = sqrt(dkk);
-      }
-      __syncthreads();
-      const double rkk = sA[k * NMAX + k];
-      for (int j = k + 1 + tid; j < n; j += NT) sA[k * NMAX + j] /= rkk;
-      __syncthreads();
-      const int m = n - k - 1;
-      for (int idx = tid; idx < m * m; idx += NT) {
-        const int i = k + 1 + idx / m, j = k + 1 + idx % m;
-        if (j >= i) sA[i * NMAX + j] -= sA[k * NMAX + i] * sA[k * NMAX + j];
-      }
       __syncthreads();
     }
-    // X <- C0 R^{-1}, row by row
-    for (int i = tid; i < n; i += NT) {
-      for (int j = 0; j < n; ++j) {
-        double s = sX[i * NMAX + j];
-        for (int l = 0; l < j; ++l) s -= sX[i * NMAX + l] * sA[l * NMAX + j];
-        sX[i * NMAX + j] = s / sA[j * NMAX + j];
+    // right-looking Cholesky of M fused with the solve X R = C0
+    for (int k = 0; k < n; ++k) {
+      const double dkk = sA[k * LD + k];
+      const double rkk = dkk > 0.0 ? sqrt(dkk) : 1.0;
+      if (tid == 0 && !(dkk > 0.0)) sh.notpd |= 1;
+      const double irkk = 1.0 / rkk;
+      for (int t = tid; t < 2 * n; t += NT) {
+        if (t < n) {
+          if (t > k) sA[k * LD + t] *= irkk;  // row k of R
+        } else {
+          sX[(t - n) * LD + k] *= irkk;      // column k of X
+        }
       }
+      __syncthreads();
+      for (int i = k + 1 + rgrp; i < n; i += RG)
+        if (lane >= i && lane < n) sA[i * LD + lane] -= sA[k * LD + i] * sA[k * LD + lane];
+      for (int i = rgrp; i < n; i += RG)
+        if (lane > k && lane < n) sX[i * LD + lane] -= sX[i * LD + k] * sA[k * LD + lane];
+      __syncthreads();
     }
-    __syncthreads();
     int status = 0;
     if (sh.notpd) status |= (sh.notpd & 2) ? CAVDFTB_ST_NAN : CAVDFTB_ST_NOT_PD;
 
     int it = 0;
+    double res_prev = INFINITY;  // no charge residual known before the first iteration
     if (status == 0) {
       for (it = 1; it <= a.max_iter; ++it) {
-        // V = gamma Dq_in ; H = H0 + 1/2 S o (V_a + V_b) into sA
+        // V = gamma Dq_in (gamma symmetric: column walk is coalesced)
         for (int t = tid; t < na; t += NT) {
           double v = 0.0;
-          for (int c = 0; c < na; ++c) v += gG[t * NMAX + c] * sDqIn[c];
+          for (int c = 0; c < na; ++c) v += gG[c * NMAX + t] * sDqIn[c];
           sV[t] = v;
         }
         __syncthreads();
-        for (int e = tid; e < n * n; e += NT) {
-          const int i = e / n, j = e % n;
-          sA[i * NMAX + j] =
-              gH0[i * NMAX + j] + 0.5 * gS[i * NMAX + j] * (sV[sOrbAtom[i]] + sV[sOrbAtom[j]]);
-        }
+        // H = H0 + 1/2 S o (V_a + V_b) into sA
+        for (int i = rgrp; i < n; i += RG)
+          if (lane < n)
+            sA[i * LD + lane] = gH0[i * NMAX + lane] +
+                                0.5 * gS[i * NMAX + lane] * (sV[sOrbAtom[i]] + sV[sOrbAtom[lane]]);
         __syncthreads();
         gemm_nn<NMAX, NT>(sA, sX, sT, n);  // T = H X
         __syncthreads();
         gemm_tn<NMAX, NT>(sX, sT, sA, n);  // A = X^T H X
         __syncthreads();
-        for (int e = tid; e < n * n; e += NT) {
-          const int i = e / n, j = e % n;
-          if (j > i) {
-            const double v = 0.5 * (sA[i * NMAX + j] + sA[j * NMAX + i]);
-            sA[i * NMAX + j] = v;
-            sA[j * NMAX + i] = v;
+        for (int i = rgrp; i < n; i += RG)
+          if (lane > i && lane < n) {
+            const double v = 0.5 * (sA[i * LD + lane] + sA[lane * LD + i]);
+            sA[i * LD + lane] = v;
+            sA[lane * LD + i] = v;
           }
-        }
         __syncthreads();
 
         // ---- cyclic parallel Jacobi on A, rotations accumulated into X
         const int half = n / 2;
+        double thr = kJacobiThr;
         for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
           double off = 0.0;
-          for (int e = tid; e < n * n; e += NT) {
-            const int i = e / n, j = e % n;
-            if (j > i) off = fmax(off, fabs(sA[i * NMAX + j]));
-          }
-          if (block_max<NT>(off, sRed) < kJacobiThr) break;
-          for (int r = 0; r < n - 1; ++r) {
-            if (tid < half) {
+          for (int i = rgrp; i < n; i += RG)
+            if (lane > i && lane < n) off = fmax(off, fabs(sA[i * LD + lane]));
+          off = block_max<NT>(off, sRed);
+          // target: a fraction of the previous charge residual, and never above
+          // a fraction of the coupling this iteration starts from
+          if (sweep == 0) thr = fmax(kJacobiThr, a.jac_factor * fmin(res_prev, off));
+          if (off < thr) break;
+          if (tid == 0) sh.sweeps += 1;
+          // round r: rotations of round r (wave 0) overlap the X update of
+          // round r-1 (other waves); then the A update of round r.
+          for (int r = 0; r < n; ++r) {
+            const int b = r & 1;
+            if (r < n - 1 && tid < half) {
               int p = rr_index(tid, r, n), q = rr_index(n - 1 - tid, r, n);
               if (p > q) {
                 const int tmp = p;
                 p = q;
                 q = tmp;
               }
-              const double apq = sA[p * NMAX + q];
-              double c = 1.0, s = 0.0, t = 0.0;
+              const double app = sA[p * LD + p], aqq = sA[q * LD + q], apq = sA[p * LD + q];
+              double c = 1.0, sn = 0.0, t = 0.0;
               if (fabs(apq) > 1.0e-300) {
-                const double theta = (sA[q * NMAX + q] - sA[p * NMAX + p]) / (2.0 * apq);
-                t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-                c = 1.0 / sqrt(t * t + 1.0);
-                s = t * c;
+                const double d = aqq - app, h2 = 2.0 * apq;
+                const double rr = sqrt(fma(d, d, h2 * h2));
+                t = (d >= 0.0 ? h2 : -h2) / (fabs(d) + rr);
+                c = rsqrt(fma(t, t, 1.0));
+                sn = t * c;
               }
-              sRp[tid] = p;
-              sRq[tid] = q;
-              sRc[tid] = c;
-              sRs[tid] = s;
-              sRt[tid] = t;
+              sRp[b][tid] = p;
+              sRq[b][tid] = q;
+              sRc[b][tid] = c;
+              sRs[b][tid] = sn;
+              sRt[b][tid] = t;
+            }
+            if (RG > 1 && r > 0 && rgrp > 0 && lane < n) {
+              for (int k = rgrp - 1; k < half; k += RG - 1) {
+                const int p = sRp[b ^ 1][k], q = sRq[b ^ 1][k];
+                const double c = sRc[b ^ 1][k], sn = sRs[b ^ 1][k];
+                const double xp = sX[lane * LD + p], xq = sX[lane * LD + q];
+                sX[lane * LD + p] = c * xp - sn * xq;
+                sX[lane * LD + q] = sn * xp + c * xq;
+              }
             }
             __syncthreads();
-            for (int task = tid; task < half * half; task += NT) {
-              const int k = task / half, l = task % half;
-              const int p = sRp[k], q = sRq[k];
-              if (k == l) {
-                const double apq = sA[p * NMAX + q], t = sRt[k];
-                sA[p * NMAX + p] -= t * apq;
-                sA[q * NMAX + q] += t * apq;
-                if (t != 0.0) {
-                  sA[p * NMAX + q] = 0.0;
-                  sA[q * NMAX + p] = 0.0;
+            if (r == n - 1) break;
+            {
+              const int l = tid & 31;
+              if (l < half) {
+                const int pl = sRp[b][l], ql = sRq[b][l];
+                const double cl = sRc[b][l], sl = sRs[b][l];
+                for (int k = tid >> 5; k < half; k += KSTEP_A) {
+                  const int p = sRp[b][k], q = sRq[b][k];
+                  if (k == l) {
+                    const double apq = sA[p * LD + q], t = sRt[b][k];
+                    sA[p * LD + p] -= t * apq;
+                    sA[q * LD + q] += t * apq;
+                    if (t != 0.0) {
+                      sA[p * LD + q] = 0.0;
+                      sA[q * LD + p] = 0.0;
+                    }
+                  } else {
+                    const double ck = sRc[b][k], sk = sRs[b][k];
+                    const double b00 = sA[p * LD + pl], b01 = sA[p * LD + ql];
+                    const double b10 = sA[q * LD + pl], b11 = sA[q * LD + ql];
+                    const double r00 = ck * b00 - sk * b10, r01 = ck * b01 - sk * b11;
+                    const double r10 = sk * b00 + ck * b10, r11 = sk * b01 + ck * b11;
+                    sA[p * LD + pl] = cl * r00 - sl * r01;
+                    sA[p * LD + ql] = sl * r00 + cl * r01;
+                    sA[q * LD + pl] = cl * r10 - sl * r11;
+                    sA[q * LD + ql] = sl * r10 + cl * r11;
+                  }
                 }
-              } else {
-                const int pl = sRp[l], ql = sRq[l];
-                const double ck = sRc[k], sk = sRs[k], cl = sRc[l], sl = sRs[l];
-                const double b00 = sA[p * NMAX + pl], b01 = sA[p * NMAX + ql];
-                const double b10 = sA[q * NMAX + pl], b11 = sA[q * NMAX + ql];
-                const double r00 = ck * b00 - sk * b10, r01 = ck * b01 - sk * b11;
-                const double r10 = sk * b00 + ck * b10, r11 = sk * b01 + ck * b11;
-                sA[p * NMAX + pl] = cl * r00 - sl * r01;
-                sA[p * NMAX + ql] = sl * r00 + cl * r01;
-                sA[q * NMAX + pl] = cl * r10 - sl * r11;
-                sA[q * NMAX + ql] = sl * r10 + cl * r11;
               }
             }
-            for (int task = tid; task < half * n; task += NT) {
-              const int k = task / n, i = task % n;
-              const int p = sRp[k], q = sRq[k];
-              const double c = sRc[k], s = sRs[k];
-              const double xp = sX[i * NMAX + p], xq = sX[i * NMAX + q];
-              sX[i * NMAX + p] = c * xp - s * xq;
-              sX[i * NMAX + q] = s * xp + c * xq;
+            if (RG == 1 && lane < n) {  // single-wave workgroups: X update in this phase
+              for (int k = 0; k < half; ++k) {
+                const int p = sRp[b][k], q = sRq[b][k];
+                const double c = sRc[b][k], sn = sRs[b][k];
+                const double xp = sX[lane * LD + p], xq = sX[lane * LD + q];
+                sX[lane * LD + p] = c * xp - sn * xq;
+                sX[lane * LD + q] = sn * xp + c * xq;
+              }
             }
             __syncthreads();
           }
         }
 
         // ---- aufbau occupation from the eigenvalues on the diagonal
-        for (int i = tid; i < n; i += NT) sEig[i] = sA[i * NMAX + i];
+        for (int i = tid; i < n; i += NT) sEig[i] = sA[i * LD + i];
         __syncthreads();
         for (int i = tid; i < n; i += NT) {
           const double li = sEig[i];
@@ -604,12 +661,12 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
           if (rank == nocc) sh.lumo = li;
         }
         __syncthreads();
-        // ---- P = 2 C_occ C_occ^T into sT ; Mulliken charges
+        // ---- P = 2 C_occ C_occ^T into sT ; Mulliken charges (P, S symmetric: column sums)
         gemm_xwxt<NMAX, NT>(sX, sW, sOcc, nocc, sT);
         __syncthreads();
         for (int i = tid; i < n; i += NT) {
           double q = 0.0;
-          for (int j = 0; j < n; ++j) q += sT[i * NMAX + j] * gS[i * NMAX + j];
+          for (int j = 0; j < n; ++j) q += sT[j * LD + i] * gS[j * NMAX + i];
           sQorb[i] = q;
         }
         __syncthreads();
@@ -627,8 +684,10 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
           status |= CAVDFTB_ST_NAN;
           break;
         }
+        res_prev = res;
 
-        // ---- Johnson's modified Broyden mixing
+        // ---- Johnson's modified Broyden mixing (Gram matrix of stored dF kept in LDS)
+        int slot_new = -1;
         if (it > 1) {
           double part = 0.0;
           for (int t = tid; t < na; t += NT) {
@@ -637,11 +696,12 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
           }
           const double nrm = sqrt(block_sum<NT>(part, sRed));
           if (nrm > 1.0e-300) {
-            const int slot = sh.bcount < kMaxHist ? sh.bcount : sh.bhead;
+            slot_new = sh.bcount < kMaxHist ? sh.bcount : sh.bhead;
+            const double inrm = 1.0 / nrm;
             for (int t = tid; t < na; t += NT) {
-              const double df = ((sDqOut[t] - sDqIn[t]) - bFp[t]) / nrm;
-              bDF[slot * NMAX + t] = df;
-              bU[slot * NMAX + t] = a.alpha * df + (sDqIn[t] - bXp[t]) / nrm;
+              const double df = ((sDqOut[t] - sDqIn[t]) - bFp[t]) * inrm;
+              bDF[slot_new * NMAX + t] = df;
+              bU[slot_new * NMAX + t] = a.alpha * df + (sDqIn[t] - bXp[t]) * inrm;
             }
             __syncthreads();
             if (tid == 0) {
@@ -659,41 +719,38 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
         __syncthreads();
         const int m = sh.bcount;
         if (m > 0) {
-          for (int task = tid; task < m * m + m; task += NT) {
-            const int i = task / (m + 1), j = task % (m + 1);
+          // refresh the Gram row of the new slot, and c = dF . f
+          for (int k = tid; k < 2 * m; k += NT) {
+            const int kk = k < m ? k : k - m;
             double s = 0.0;
-            if (j < m) {
-              for (int t = 0; t < na; ++t) s += bDF[i * NMAX + t] * bDF[j * NMAX + t];
-              sBa[i * kMaxHist + j] = s + (i == j ? a.w0 * a.w0 : 0.0);
+            if (k < m) {
+              if (slot_new >= 0) {
+                for (int t = 0; t < na; ++t) s += bDF[slot_new * NMAX + t] * bDF[kk * NMAX + t];
+                sBa[slot_new * kMaxHist + kk] = s;
+                sBa[kk * kMaxHist + slot_new] = s;
+              }
             } else {
-              for (int t = 0; t < na; ++t) s += bDF[i * NMAX + t] * bFp[t];
-              sBc[i] = s;
+              for (int t = 0; t < na; ++t) s += bDF[kk * NMAX + t] * bFp[t];
+              sBc[kk] = s;
             }
           }
           __syncthreads();
-          if (tid == 0) {  // solve (w0^2 I + a) g = c by Cholesky (m <= 20)
-            for (int k = 0; k < m; ++k) {
-              double d = sBa[k * kMaxHist + k];
-              for (int l = 0; l < k; ++l) d -= sBa[k * kMaxHist + l] * sBa[k * kMaxHist + l];
-              d = sqrt(d);
-              sBa[k * kMaxHist + k] = d;
-              for (int i = k + 1; i < m; ++i) {
-                double v = sBa[i * kMaxHist + k];
-                for (int l = 0; l < k; ++l) v -= sBa[i * kMaxHist + l] * sBa[k * kMaxHist + l];
-                sBa[i * kMaxHist + k] = v / d;
-              }
-            }
-            for (int i = 0; i < m; ++i) {
-              double v = sBc[i];
-              for (int l = 0; l < i; ++l) v -= sBa[i * kMaxHist + l] * sBg[l];
-              sBg[i] = v / sBa[i * kMaxHist + i];
-            }
-            for (int i = m - 1; i >= 0; --i) {
-              double v = sBg[i];
-              for (int l = i + 1; l < m; ++l) v -= sBa[l * kMaxHist + i] * sBg[l];
-              sBg[i] = v / sBa[i * kMaxHist + i];
-            }
+          for (int e = tid; e < m * (m + 1); e += NT) {
+            const int i = e / (m + 1), j = e % (m + 1);
+            sBm[i * (kMaxHist + 1) + j] =
+                j < m ? sBa[i * kMaxHist + j] + (i == j ? a.w0 * a.w0 : 0.0) : sBc[i];
           }
+          __syncthreads();
+          // Gauss-Jordan on the SPD system (w0^2 I + a) g = c, one row per thread
+          for (int k = 0; k < m; ++k) {
+            double f = 0.0;
+            if (tid < m && tid != k) f = sBm[tid * (kMaxHist + 1) + k] / sBm[k * (kMaxHist + 1) + k];
+            __syncthreads();
+            if (tid < m && tid != k)
+              for (int j = k; j <= m; ++j) sBm[tid * (kMaxHist + 1) + j] -= f * sBm[k * (kMaxHist + 1) + j];
+            __syncthreads();
+          }
+          if (tid < m) sBg[tid] = sBm[tid * (kMaxHist + 1) + m] / sBm[tid * (kMaxHist + 1) + tid];
           __syncthreads();
         }
         for (int t = tid; t < na; t += NT) {
@@ -713,11 +770,23 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
     // ---- outputs
     if (status == 0 && (a.flags & JF_STORE)) {
       double* wc = a.ws_C + a.ws_off[u];
-      for (int e = tid; e < n * n; e += NT) {
-        const int i = e / n, j = e % n;
-        wc[i * NMAX + j] = sX[i * NMAX + j];
+      for (int i = rgrp; i < n; i += RG)
+        if (lane < n) wc[i * NMAX + lane] = sX[i * LD + lane];
+      for (int t = tid; t < na; t += NT) {
+        if (a.ws_dq_hist) {  // shift the charge history of the unit (MD steps)
+          a.ws_dq_hist[(int64_t)a.n_atoms + a0 + t] = a.ws_dq_hist[a0 + t];
+          a.ws_dq_hist[a0 + t] = a.ws_dq[a0 + t];
+        }
+        a.ws_dq[a0 + t] = sDqOut[t];
       }
-      for (int t = tid; t < na; t += NT) a.ws_dq[a0 + t] = sDqOut[t];
+    }
+    if (own_hist && (a.flags & JF_STORE_HIST)) {
+      const int m0 = status == 0 ? sh.bcount : 0;
+      for (int e = tid; e < m0 * kMaxHist; e += NT) hst[2 + e] = sBa[e];
+      if (tid == 0) {
+        hst[0] = (double)m0;
+        hst[1] = (double)(status == 0 ? sh.bhead : 0);
+      }
     }
     if (status & (CAVDFTB_ST_NOT_PD | CAVDFTB_ST_NAN)) {
       for (int t = tid; t < na; t += NT) sDqOut[t] = 0.0;
@@ -738,10 +807,10 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
         if (a.charges) a.charges[a0 + t] = -sDqOut[t];
     }
     if ((a.flags & JF_FORCES) && disp < 0) {
-      // V from the output charges, W = 2 C_occ eps C_occ^T into sA
+      // V from the output charges; W = 2 C_occ eps C_occ^T into sA
       for (int t = tid; t < na; t += NT) {
         double v = 0.0;
-        for (int c = 0; c < na; ++c) v += gG[t * NMAX + c] * sDqOut[c];
+        for (int c = 0; c < na; ++c) v += gG[c * NMAX + t] * sDqOut[c];
         sV[t] = v;
       }
       for (int i = tid; i < n; i += NT) sQorb[i] = sW[i] * sEig[i];  // occupation x eigenvalue
@@ -749,10 +818,8 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
       gemm_xwxt<NMAX, NT>(sX, sQorb, sOcc, nocc, sA);
       __syncthreads();
       double ebp = 0.0;
-      for (int e = tid; e < n * n; e += NT) {
-        const int i = e / n, j = e % n;
-        ebp += sT[i * NMAX + j] * gH0[i * NMAX + j];
-      }
+      for (int i = rgrp; i < n; i += RG)
+        if (lane < n) ebp += sT[i * LD + lane] * gH0[i * NMAX + lane];
       double ecp = 0.0;
       for (int t = tid; t < na; t += NT) ecp += 0.5 * sDqOut[t] * sV[t];
       // pair forces: task (A, part) sums g(A,B) over its B's
@@ -768,7 +835,7 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
           double d[3];
           for (int g = 0; g < 3; ++g) d[g] = sPos[B * 3 + g] - sPos[A * 3 + g];
           const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-          pair_band_grad(P, sSp[A], sSp[B], d, sT, sA, NMAX, oA, oB, sV[A] + sV[B], fa);
+          pair_band_grad(P, sSp[A], sSp[B], d, sT, sA, LD, oA, oB, sV[A] + sV[B], fa);
           double gm, dgm;
           gamma_pair(P.U[sSp[A]], P.U[sSp[B]], r, gm, dgm);
           const int pt = sSp[A] + sSp[B];
@@ -778,6 +845,7 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
           for (int g = 0; g < 3; ++g) fa[g] += radial_g * d[g] / r;
         }
       }
+      __syncthreads();  // sF may alias sX
       for (int g = 0; g < 3; ++g) sF[tid * 3 + g] = fa[g];
       const double etot = block_sum<NT>(ebp + ecp + erp, sRed);  // contains the barrier for sF
       for (int t = tid; t < na; t += NT) {
@@ -800,6 +868,7 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
         atomicAdd(&a.counters[0], 1ull);
         atomicAdd(&a.counters[1], (unsigned long long)it);
         atomicAdd(&a.counters[2], per_it * (unsigned long long)it + per_geo);
+        atomicAdd(&a.counters[3], (unsigned long long)sh.sweeps);
       }
     }
     __syncthreads();
