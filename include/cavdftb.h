@@ -27,8 +27,8 @@
  *     not make the call fail.  cavdftb_last_error returns a readable reason.
  *   - Units are given in CSR form (unit_atom_off); atom order inside a unit is
  *     free; species 0 = O (orbitals s, px, py, pz), 1 = H (s).  A unit may
- *     hold at most 64 orbitals (32 water molecules need 192: see
- *     CAVDFTB_MAX_ORBITALS) and its orbital count must be even.
+ *     hold at most CAVDFTB_MAX_ORBITALS (192) orbitals - 32 water molecules -
+ *     and its orbital count must be even.
  */
 #ifndef CAVDFTB_H
 #define CAVDFTB_H
@@ -54,7 +54,7 @@ extern "C" {
 #define CAVDFTB_BORN_MULLIKEN 0 /* Z_A = Q_A I (the paper's cheap replacement, Results) */
 #define CAVDFTB_BORN_FD 1       /* central finite differences of the SCC dipole (Results) */
 
-#define CAVDFTB_MAX_ORBITALS 64
+#define CAVDFTB_MAX_ORBITALS 192
 
 /* Synthetic SCC-DFTB parameter set.  Table index t (0..6): O-O ss sigma,
  * O-O sp sigma, O-O pp sigma, O-O pp pi, O-H (s_H s_O) sigma,
@@ -93,7 +93,7 @@ typedef struct cavdftb_ctx cavdftb_ctx;
  * NULL for the null stream) on the current device.  Allocates every workspace
  * (device memory ~ sum over units of 3 n_u^2 doubles plus O(atoms + modes)).
  * Returns CAVDFTB_EINVAL for inconsistent layouts (non-monotone offsets,
- * species outside {0,1}, an odd orbital count, more than 64 orbitals), and
+ * species outside {0,1}, an odd orbital count, more than 192 orbitals), and
  * CAVDFTB_ENOMEM / CAVDFTB_EHIP on allocation failure. */
 int cavdftb_create(const cavdftb_params* params, const cavdftb_layout* layout, void* hip_stream,
                    cavdftb_ctx** out);

@@ -22,12 +22,20 @@ __global__ void ws_identity_kernel(double* ws, const int64_t* ws_off, const int3
   if (u >= n_units) return;
   int n = 0;
   for (int a = unit_off[u]; a < unit_off[u + 1]; ++a) n += species[a] == 0 ? 4 : 1;
-  const int nmax = n <= 8 ? 8 : n <= 16 ? 16 : n <= 32 ? 32 : n <= 48 ? 48 : 64;
+  const int nmax = n <= 8 ? 8 : n <= 16 ? 16 : n <= 32 ? 32 : n <= 48 ? 48 : n <= 64 ? 64 : n <= 96 ? 96
+                 : n <= 128 ? 128 : 192;
   double* w = ws + ws_off[u];
   for (int e = threadIdx.x; e < nmax * nmax; e += blockDim.x) w[e] = (e / nmax == e % nmax) ? 1.0 : 0.0;
 }
 
-int bucket_of(int n) { return n <= 8 ? 8 : n <= 16 ? 16 : n <= 32 ? 32 : n <= 48 ? 48 : 64; }
+// orbital buckets: LDS-resident kernels up to 64, global-scratch kernels above
+constexpr int kNumBuckets = 8;
+constexpr int kBucketNmax[kNumBuckets] = {8, 16, 32, 48, 64, 96, 128, 192};
+int bucket_of(int n) {
+  for (int k = 0; k < kNumBuckets; ++k)
+    if (n <= kBucketNmax[k]) return kBucketNmax[k];
+  return -1;
+}
 
 struct Bucket {
   int nmax = 0;
@@ -352,13 +360,13 @@ int cavdftb_create(const cavdftb_params* params, const cavdftb_layout* L, void* 
   hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
   if (n_cu <= 0) n_cu = 256;
 
-  const int nmaxs[5] = {8, 16, 32, 48, 64};
+  const int* nmaxs = kBucketNmax;
   std::vector<int64_t> ws_off(U), hist_off(U);
   int64_t ws_total = 0, hist_total = 0;
-  std::vector<std::vector<int32_t>> bunits(5);
+  std::vector<std::vector<int32_t>> bunits(kNumBuckets);
   for (int u = 0; u < U; ++u) {
     const int nm = bucket_of(n_orb[u]);
-    for (int k = 0; k < 5; ++k)
+    for (int k = 0; k < kNumBuckets; ++k)
       if (nmaxs[k] == nm) bunits[k].push_back(u);
     ws_off[u] = ws_total;
     ws_total += (int64_t)nm * nm;
@@ -428,7 +436,7 @@ int cavdftb_create(const cavdftb_params* params, const cavdftb_layout* L, void* 
 
   // ---- buckets: unit lists, scratch, finite-difference job lists
   int cj = 0, fj = 0;
-  for (int k = 0; k < 5; ++k) {
+  for (int k = 0; k < kNumBuckets; ++k) {
     if (bunits[k].empty()) continue;
     Bucket b;
     b.nmax = nmaxs[k];
@@ -436,7 +444,8 @@ int cavdftb_create(const cavdftb_params* params, const cavdftb_layout* L, void* 
     b.cjob0 = cj;
     cj += b.n_units;
     b.scratch_per_wg = scc_scratch_per_wg(b.nmax);
-    const int per_cu = scc_blocks_per_cu(b.nmax);
+    int per_cu = scc_blocks_per_cu(b.nmax);
+    if (b.nmax > 64 && per_cu > 2) per_cu = 2;  // global-scratch buckets: bound the cache footprint
     b.n_wg = n_cu * per_cu;
     CK(dalloc(c, &b.d_units, b.n_units));
     CK(hipMemcpy(b.d_units, bunits[k].data(), b.n_units * sizeof(int32_t), hipMemcpyHostToDevice));

@@ -102,9 +102,9 @@ __global__ __launch_bounds__(kNT) void zpol_mulliken_kernel(const double* __rest
   }
 }
 
-// one thread per (unit, atom): Z[a][al][b] = (mu+_al - mu-_al) / 2h from the
+// one workgroup per unit, one thread per atom: Z[a][al][b] = (mu+_al - mu-_al) / 2h from the
 // displaced jobs of the unit (job order (atom*3 + dir)*2 + (minus)).
-__global__ __launch_bounds__(64) void born_fd_kernel(const int32_t* __restrict__ unit_off,
+__global__ __launch_bounds__(256) void born_fd_kernel(const int32_t* __restrict__ unit_off,
                                                       const int32_t* __restrict__ fd_unit,
                                                       const int32_t* __restrict__ fd_job0, int n_fd_units,
                                                       const double* __restrict__ mu_job, double h, double e0,
@@ -114,20 +114,20 @@ __global__ __launch_bounds__(64) void born_fd_kernel(const int32_t* __restrict__
   if (w >= n_fd_units) return;
   const int u = fd_unit[w];
   const int a0 = unit_off[u], na = unit_off[u + 1] - a0;
-  const int loc = threadIdx.x;
-  if (loc >= na) return;
   const int64_t j0 = fd_job0[w];
-  double Z[3][3];
-  for (int b = 0; b < 3; ++b) {
-    const int64_t jp = j0 + (int64_t)((loc * 3 + b) * 2);
-    for (int al = 0; al < 3; ++al) Z[al][b] = (mu_job[jp * 3 + al] - mu_job[(jp + 1) * 3 + al]) / (2.0 * h);
+  for (int loc = threadIdx.x; loc < na; loc += blockDim.x) {
+    double Z[3][3];
+    for (int b = 0; b < 3; ++b) {
+      const int64_t jp = j0 + (int64_t)((loc * 3 + b) * 2);
+      for (int al = 0; al < 3; ++al) Z[al][b] = (mu_job[jp * 3 + al] - mu_job[(jp + 1) * 3 + al]) / (2.0 * h);
+    }
+    const int64_t A = a0 + loc;
+    if (born)
+      for (int al = 0; al < 3; ++al)
+        for (int b = 0; b < 3; ++b) born[A * 9 + al * 3 + b] = Z[al][b];
+    if (zpol)
+      for (int b = 0; b < 3; ++b) zpol[A * 3 + b] = e0 * Z[0][b] + e1 * Z[1][b] + e2 * Z[2][b];
   }
-  const int64_t A = a0 + loc;
-  if (born)
-    for (int al = 0; al < 3; ++al)
-      for (int b = 0; b < 3; ++b) born[A * 9 + al * 3 + b] = Z[al][b];
-  if (zpol)
-    for (int b = 0; b < 3; ++b) zpol[A * 3 + b] = e0 * Z[0][b] + e1 * Z[1][b] + e2 * Z[2][b];
 }
 
 // OR the displaced-job status into the unit status, one thread per fd unit
@@ -286,8 +286,7 @@ hipError_t launch_born_fd_assemble(const int32_t* unit_off, const int32_t* fd_un
                                    const int32_t* job_status, double* born, double* zpol, int32_t* status,
                                    hipStream_t s) {
   if (n_fd_units <= 0) return hipSuccess;
-  // at most 64 orbitals per unit -> at most 64 atoms: one 64-thread block per unit
-  hipLaunchKernelGGL(born_fd_kernel, dim3(n_fd_units), dim3(64), 0, s, unit_off, fd_unit, fd_job0, n_fd_units,
+  hipLaunchKernelGGL(born_fd_kernel, dim3(n_fd_units), dim3(256), 0, s, unit_off, fd_unit, fd_job0, n_fd_units,
                      mu_job, h, pol[0], pol[1], pol[2], born, zpol);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

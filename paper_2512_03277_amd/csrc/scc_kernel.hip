@@ -229,104 +229,104 @@ __device__ double block_max(double v, double* red) {
   return r;
 }
 
-// LDS layout: n x n blocks of NMAX x LD doubles, LD = NMAX + 1 so that a
-// column walk (consecutive rows, one column) spreads over the LDS banks.
-// Elementwise loops use lane = column (tid & 63) and row groups tid >> 6, so
-// no integer division appears in the hot loops (n <= 64).
+// Working-matrix layout: NMAX x LD doubles, LD = NMAX + 1 so that a column
+// walk (consecutive rows, one column) spreads over the LDS banks.  For
+// NMAX <= 64 the three working matrices live in LDS; larger buckets keep them
+// in per-workgroup global scratch (L2 / Infinity-Cache resident).  Elementwise
+// loops use lane = column (tid & 63, in chunks of 64) and row groups tid >> 6,
+// so no integer division appears in the hot loops.
 template <int NMAX, int NT>
 struct Cfg {
   static constexpr int LD = NMAX + 1;
   static constexpr int G = (NT == 256) ? 16 : 8;
   static constexpr int TM = NMAX / G;
-  static constexpr int RG = NT / 64;  // row groups of 64 lanes
+  static constexpr int TMB = TM < 4 ? TM : 4;  // rows/cols per thread and output block
+  static constexpr int BLK = G * TMB;           // output block edge
+  static constexpr int RG = NT / 64;            // row groups of 64 lanes
+  static constexpr bool GM = NMAX > 64;         // working matrices in global scratch
   static_assert(TM * G == NMAX, "tile mismatch");
-  static_assert(NMAX <= 64, "one lane per column");
 };
 
-// C = A B over the leading n x n block; padding of A, B is zero.
-template <int NMAX, int NT>
-__device__ void gemm_nn(const double* __restrict__ A, const double* __restrict__ B, double* __restrict__ C,
-                        int n) {
-  constexpr int G = Cfg<NMAX, NT>::G, TM = Cfg<NMAX, NT>::TM, LD = Cfg<NMAX, NT>::LD;
+// C = op(A) B over the leading n x n block (op = transpose when TA); only the
+// n x n block of C is written, its zero padding is left untouched.
+template <int NMAX, int NT, bool TA>
+__device__ void gemm(const double* __restrict__ A, const double* __restrict__ B, double* __restrict__ C, int n) {
+  constexpr int G = Cfg<NMAX, NT>::G, TMB = Cfg<NMAX, NT>::TMB, BLK = Cfg<NMAX, NT>::BLK, LD = Cfg<NMAX, NT>::LD;
   const int tx = threadIdx.x % G, ty = threadIdx.x / G;
-  double acc[TM][TM];
+  for (int bi = 0; bi < n; bi += BLK)
+    for (int bj = 0; bj < n; bj += BLK) {
+      double acc[TMB][TMB];
 #pragma unroll
-  for (int r = 0; r < TM; ++r)
+      for (int r = 0; r < TMB; ++r)
 #pragma unroll
-    for (int c = 0; c < TM; ++c) acc[r][c] = 0.0;
-  for (int k = 0; k < n; ++k) {
-    double av[TM], bv[TM];
+        for (int c = 0; c < TMB; ++c) acc[r][c] = 0.0;
+      for (int k = 0; k < n; ++k) {
+        double av[TMB], bv[TMB];
 #pragma unroll
-    for (int r = 0; r < TM; ++r) av[r] = A[(ty + G * r) * LD + k];
+        for (int r = 0; r < TMB; ++r) {
+          const int row = bi + ty + G * r;
+          av[r] = row < NMAX ? (TA ? A[k * LD + row] : A[row * LD + k]) : 0.0;
+        }
 #pragma unroll
-    for (int c = 0; c < TM; ++c) bv[c] = B[k * LD + tx + G * c];
+        for (int c = 0; c < TMB; ++c) {
+          const int col = bj + tx + G * c;
+          bv[c] = col < NMAX ? B[k * LD + col] : 0.0;
+        }
 #pragma unroll
-    for (int r = 0; r < TM; ++r)
+        for (int r = 0; r < TMB; ++r)
 #pragma unroll
-      for (int c = 0; c < TM; ++c) acc[r][c] = fma(av[r], bv[c], acc[r][c]);
-  }
+          for (int c = 0; c < TMB; ++c) acc[r][c] = fma(av[r], bv[c], acc[r][c]);
+      }
 #pragma unroll
-  for (int r = 0; r < TM; ++r)
+      for (int r = 0; r < TMB; ++r)
 #pragma unroll
-    for (int c = 0; c < TM; ++c) C[(ty + G * r) * LD + tx + G * c] = acc[r][c];
-}
-
-// C = A^T B
-template <int NMAX, int NT>
-__device__ void gemm_tn(const double* __restrict__ A, const double* __restrict__ B, double* __restrict__ C,
-                        int n) {
-  constexpr int G = Cfg<NMAX, NT>::G, TM = Cfg<NMAX, NT>::TM, LD = Cfg<NMAX, NT>::LD;
-  const int tx = threadIdx.x % G, ty = threadIdx.x / G;
-  double acc[TM][TM];
-#pragma unroll
-  for (int r = 0; r < TM; ++r)
-#pragma unroll
-    for (int c = 0; c < TM; ++c) acc[r][c] = 0.0;
-  for (int k = 0; k < n; ++k) {
-    double av[TM], bv[TM];
-#pragma unroll
-    for (int r = 0; r < TM; ++r) av[r] = A[k * LD + ty + G * r];
-#pragma unroll
-    for (int c = 0; c < TM; ++c) bv[c] = B[k * LD + tx + G * c];
-#pragma unroll
-    for (int r = 0; r < TM; ++r)
-#pragma unroll
-      for (int c = 0; c < TM; ++c) acc[r][c] = fma(av[r], bv[c], acc[r][c]);
-  }
-#pragma unroll
-  for (int r = 0; r < TM; ++r)
-#pragma unroll
-    for (int c = 0; c < TM; ++c) C[(ty + G * r) * LD + tx + G * c] = acc[r][c];
+        for (int c = 0; c < TMB; ++c) {
+          const int row = bi + ty + G * r, col = bj + tx + G * c;
+          if (row < n && col < n) C[row * LD + col] = acc[r][c];
+        }
+    }
 }
 
 // C = X diag(w) X^T restricted to the columns listed in idx[0..m)
 template <int NMAX, int NT>
 __device__ void gemm_xwxt(const double* __restrict__ X, const double* __restrict__ w, const int* __restrict__ idx,
-                          int m, double* __restrict__ C) {
-  constexpr int G = Cfg<NMAX, NT>::G, TM = Cfg<NMAX, NT>::TM, LD = Cfg<NMAX, NT>::LD;
+                          int m, int n, double* __restrict__ C) {
+  constexpr int G = Cfg<NMAX, NT>::G, TMB = Cfg<NMAX, NT>::TMB, BLK = Cfg<NMAX, NT>::BLK, LD = Cfg<NMAX, NT>::LD;
   const int tx = threadIdx.x % G, ty = threadIdx.x / G;
-  double acc[TM][TM];
+  for (int bi = 0; bi < n; bi += BLK)
+    for (int bj = 0; bj < n; bj += BLK) {
+      double acc[TMB][TMB];
 #pragma unroll
-  for (int r = 0; r < TM; ++r)
+      for (int r = 0; r < TMB; ++r)
 #pragma unroll
-    for (int c = 0; c < TM; ++c) acc[r][c] = 0.0;
-  for (int kk = 0; kk < m; ++kk) {
-    const int k = idx[kk];
-    const double wk = w[k];
-    double av[TM], bv[TM];
+        for (int c = 0; c < TMB; ++c) acc[r][c] = 0.0;
+      for (int kk = 0; kk < m; ++kk) {
+        const int k = idx[kk];
+        const double wk = w[k];
+        double av[TMB], bv[TMB];
 #pragma unroll
-    for (int r = 0; r < TM; ++r) av[r] = X[(ty + G * r) * LD + k] * wk;
+        for (int r = 0; r < TMB; ++r) {
+          const int row = bi + ty + G * r;
+          av[r] = row < NMAX ? X[row * LD + k] * wk : 0.0;
+        }
 #pragma unroll
-    for (int c = 0; c < TM; ++c) bv[c] = X[(tx + G * c) * LD + k];
+        for (int c = 0; c < TMB; ++c) {
+          const int col = bj + tx + G * c;
+          bv[c] = col < NMAX ? X[col * LD + k] : 0.0;
+        }
 #pragma unroll
-    for (int r = 0; r < TM; ++r)
+        for (int r = 0; r < TMB; ++r)
 #pragma unroll
-      for (int c = 0; c < TM; ++c) acc[r][c] = fma(av[r], bv[c], acc[r][c]);
-  }
+          for (int c = 0; c < TMB; ++c) acc[r][c] = fma(av[r], bv[c], acc[r][c]);
+      }
 #pragma unroll
-  for (int r = 0; r < TM; ++r)
+      for (int r = 0; r < TMB; ++r)
 #pragma unroll
-    for (int c = 0; c < TM; ++c) C[(ty + G * r) * LD + tx + G * c] = acc[r][c];
+        for (int c = 0; c < TMB; ++c) {
+          const int row = bi + ty + G * r, col = bj + tx + G * c;
+          if (row < n && col < n) C[row * LD + col] = acc[r][c];
+        }
+    }
 }
 
 // index held by slot s in round r of the circle (round-robin) ordering of m indices
@@ -345,10 +345,11 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
   constexpr int RG = Cfg<NMAX, NT>::RG;
   constexpr int HALF = NMAX / 2;
   constexpr int KSTEP_A = NT / 32;  // row-of-blocks step in the Jacobi block update
-  constexpr bool F_IN_X = NMAX * LD >= 3 * NT;
-  __shared__ double sX[NMAX * LD];
-  __shared__ double sA[NMAX * LD];
-  __shared__ double sT[NMAX * LD];
+  constexpr bool GM = Cfg<NMAX, NT>::GM;
+  constexpr bool F_IN_X = !GM && NMAX * LD >= 3 * NT;
+  __shared__ double lX[GM ? 1 : NMAX * LD];
+  __shared__ double lA[GM ? 1 : NMAX * LD];
+  __shared__ double lT[GM ? 1 : NMAX * LD];
   __shared__ double sFbuf[F_IN_X ? 1 : 3 * NT];
   __shared__ double sPos[NMAX * 3];
   __shared__ double sDqIn[NMAX], sDqOut[NMAX], sV[NMAX], sQ0[NMAX], sEig[NMAX], sW[NMAX], sQorb[NMAX];
@@ -358,7 +359,6 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
   __shared__ double sRc[2][HALF], sRs[2][HALF], sRt[2][HALF];
   __shared__ double sBa[kMaxHist * kMaxHist], sBm[kMaxHist * (kMaxHist + 1)], sBc[kMaxHist], sBg[kMaxHist];
   __shared__ Shared sh;
-  double* sF = F_IN_X ? sX : sFbuf;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -372,6 +372,10 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
   double* bFp = bXp + NMAX;
   double* sDF = bFp + NMAX;           // per-workgroup history (displaced jobs)
   double* sU = sDF + kMaxHist * NMAX;
+  double* sX = GM ? sU + kMaxHist * NMAX : lX;
+  double* sA = GM ? sX + NMAX * LD : lA;
+  double* sT = GM ? sA + NMAX * LD : lT;
+  double* sF = F_IN_X ? sX : sFbuf;
 
   for (int job = blockIdx.x; job < a.n_jobs; job += gridDim.x) {
     const int u = a.job_unit[job];
@@ -484,20 +488,20 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
     if (warm) {
       const double* wc = a.ws_C + a.ws_off[u];
       for (int i = rgrp; i < n; i += RG)
-        if (lane < n) {
-          sX[i * LD + lane] = wc[i * NMAX + lane];
-          sA[i * LD + lane] = gS[i * NMAX + lane];
+        for (int j = lane; j < n; j += 64) {
+          sX[i * LD + j] = wc[i * NMAX + j];
+          sA[i * LD + j] = gS[i * NMAX + j];
         }
       __syncthreads();
-      gemm_nn<NMAX, NT>(sA, sX, sT, n);  // T = S C0
+      gemm<NMAX, NT, false>(sA, sX, sT, n);  // T = S C0
       __syncthreads();
-      gemm_tn<NMAX, NT>(sX, sT, sA, n);  // M = C0^T S C0
+      gemm<NMAX, NT, true>(sX, sT, sA, n);  // M = C0^T S C0
       __syncthreads();
     } else {
       for (int i = rgrp; i < n; i += RG)
-        if (lane < n) {
-          sX[i * LD + lane] = (i == lane) ? 1.0 : 0.0;
-          sA[i * LD + lane] = gS[i * NMAX + lane];
+        for (int j = lane; j < n; j += 64) {
+          sX[i * LD + j] = (i == j) ? 1.0 : 0.0;
+          sA[i * LD + j] = gS[i * NMAX + j];
         }
       __syncthreads();
     }
@@ -516,9 +520,11 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
       }
       __syncthreads();
       for (int i = k + 1 + rgrp; i < n; i += RG)
-        if (lane >= i && lane < n) sA[i * LD + lane] -= sA[k * LD + i] * sA[k * LD + lane];
+        for (int j = lane; j < n; j += 64)
+          if (j >= i) sA[i * LD + j] -= sA[k * LD + i] * sA[k * LD + j];
       for (int i = rgrp; i < n; i += RG)
-        if (lane > k && lane < n) sX[i * LD + lane] -= sX[i * LD + k] * sA[k * LD + lane];
+        for (int j = lane; j < n; j += 64)
+          if (j > k) sX[i * LD + j] -= sX[i * LD + k] * sA[k * LD + j];
       __syncthreads();
     }
     int status = 0;
@@ -537,20 +543,20 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
         __syncthreads();
         // H = H0 + 1/2 S o (V_a + V_b) into sA
         for (int i = rgrp; i < n; i += RG)
-          if (lane < n)
-            sA[i * LD + lane] = gH0[i * NMAX + lane] +
-                                0.5 * gS[i * NMAX + lane] * (sV[sOrbAtom[i]] + sV[sOrbAtom[lane]]);
+          for (int j = lane; j < n; j += 64)
+            sA[i * LD + j] = gH0[i * NMAX + j] + 0.5 * gS[i * NMAX + j] * (sV[sOrbAtom[i]] + sV[sOrbAtom[j]]);
         __syncthreads();
-        gemm_nn<NMAX, NT>(sA, sX, sT, n);  // T = H X
+        gemm<NMAX, NT, false>(sA, sX, sT, n);  // T = H X
         __syncthreads();
-        gemm_tn<NMAX, NT>(sX, sT, sA, n);  // A = X^T H X
+        gemm<NMAX, NT, true>(sX, sT, sA, n);  // A = X^T H X
         __syncthreads();
         for (int i = rgrp; i < n; i += RG)
-          if (lane > i && lane < n) {
-            const double v = 0.5 * (sA[i * LD + lane] + sA[lane * LD + i]);
-            sA[i * LD + lane] = v;
-            sA[lane * LD + i] = v;
-          }
+          for (int j = lane; j < n; j += 64)
+            if (j > i) {
+              const double v = 0.5 * (sA[i * LD + j] + sA[j * LD + i]);
+              sA[i * LD + j] = v;
+              sA[j * LD + i] = v;
+            }
         __syncthreads();
 
         // ---- cyclic parallel Jacobi on A, rotations accumulated into X
@@ -559,7 +565,8 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
         for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
           double off = 0.0;
           for (int i = rgrp; i < n; i += RG)
-            if (lane > i && lane < n) off = fmax(off, fabs(sA[i * LD + lane]));
+            for (int j = lane; j < n; j += 64)
+              if (j > i) off = fmax(off, fabs(sA[i * LD + j]));
           off = block_max<NT>(off, sRed);
           // target: a fraction of the previous charge residual, and never above
           // a fraction of the coupling this iteration starts from
@@ -570,8 +577,8 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
           // round r-1 (other waves); then the A update of round r.
           for (int r = 0; r < n; ++r) {
             const int b = r & 1;
-            if (r < n - 1 && tid < half) {
-              int p = rr_index(tid, r, n), q = rr_index(n - 1 - tid, r, n);
+            for (int kr = tid; r < n - 1 && kr < half; kr += NT) {
+              int p = rr_index(kr, r, n), q = rr_index(n - 1 - kr, r, n);
               if (p > q) {
                 const int tmp = p;
                 p = q;
@@ -586,26 +593,27 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
                 c = rsqrt(fma(t, t, 1.0));
                 sn = t * c;
               }
-              sRp[b][tid] = p;
-              sRq[b][tid] = q;
-              sRc[b][tid] = c;
-              sRs[b][tid] = sn;
-              sRt[b][tid] = t;
+              sRp[b][kr] = p;
+              sRq[b][kr] = q;
+              sRc[b][kr] = c;
+              sRs[b][kr] = sn;
+              sRt[b][kr] = t;
             }
-            if (RG > 1 && r > 0 && rgrp > 0 && lane < n) {
+            if (RG > 1 && r > 0 && rgrp > 0) {
               for (int k = rgrp - 1; k < half; k += RG - 1) {
                 const int p = sRp[b ^ 1][k], q = sRq[b ^ 1][k];
                 const double c = sRc[b ^ 1][k], sn = sRs[b ^ 1][k];
-                const double xp = sX[lane * LD + p], xq = sX[lane * LD + q];
-                sX[lane * LD + p] = c * xp - sn * xq;
-                sX[lane * LD + q] = sn * xp + c * xq;
+                for (int i = lane; i < n; i += 64) {
+                  const double xp = sX[i * LD + p], xq = sX[i * LD + q];
+                  sX[i * LD + p] = c * xp - sn * xq;
+                  sX[i * LD + q] = sn * xp + c * xq;
+                }
               }
             }
             __syncthreads();
             if (r == n - 1) break;
-            {
-              const int l = tid & 31;
-              if (l < half) {
+            for (int l = tid & 31; l < half; l += 32) {
+              {
                 const int pl = sRp[b][l], ql = sRq[b][l];
                 const double cl = sRc[b][l], sl = sRs[b][l];
                 for (int k = tid >> 5; k < half; k += KSTEP_A) {
@@ -632,13 +640,15 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
                 }
               }
             }
-            if (RG == 1 && lane < n) {  // single-wave workgroups: X update in this phase
+            if (RG == 1) {  // single-wave workgroups: X update in this phase
               for (int k = 0; k < half; ++k) {
                 const int p = sRp[b][k], q = sRq[b][k];
                 const double c = sRc[b][k], sn = sRs[b][k];
-                const double xp = sX[lane * LD + p], xq = sX[lane * LD + q];
-                sX[lane * LD + p] = c * xp - sn * xq;
-                sX[lane * LD + q] = sn * xp + c * xq;
+                for (int i = lane; i < n; i += 64) {
+                  const double xp = sX[i * LD + p], xq = sX[i * LD + q];
+                  sX[i * LD + p] = c * xp - sn * xq;
+                  sX[i * LD + q] = sn * xp + c * xq;
+                }
               }
             }
             __syncthreads();
@@ -662,7 +672,7 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
         }
         __syncthreads();
         // ---- P = 2 C_occ C_occ^T into sT ; Mulliken charges (P, S symmetric: column sums)
-        gemm_xwxt<NMAX, NT>(sX, sW, sOcc, nocc, sT);
+        gemm_xwxt<NMAX, NT>(sX, sW, sOcc, nocc, n, sT);
         __syncthreads();
         for (int i = tid; i < n; i += NT) {
           double q = 0.0;
@@ -771,7 +781,7 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
     if (status == 0 && (a.flags & JF_STORE)) {
       double* wc = a.ws_C + a.ws_off[u];
       for (int i = rgrp; i < n; i += RG)
-        if (lane < n) wc[i * NMAX + lane] = sX[i * LD + lane];
+        for (int j = lane; j < n; j += 64) wc[i * NMAX + j] = sX[i * LD + j];
       for (int t = tid; t < na; t += NT) {
         if (a.ws_dq_hist) {  // shift the charge history of the unit (MD steps)
           a.ws_dq_hist[(int64_t)a.n_atoms + a0 + t] = a.ws_dq_hist[a0 + t];
@@ -815,11 +825,11 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
       }
       for (int i = tid; i < n; i += NT) sQorb[i] = sW[i] * sEig[i];  // occupation x eigenvalue
       __syncthreads();
-      gemm_xwxt<NMAX, NT>(sX, sQorb, sOcc, nocc, sA);
+      gemm_xwxt<NMAX, NT>(sX, sQorb, sOcc, nocc, n, sA);
       __syncthreads();
       double ebp = 0.0;
       for (int i = rgrp; i < n; i += RG)
-        if (lane < n) ebp += sT[i * LD + lane] * gH0[i * NMAX + lane];
+        for (int j = lane; j < n; j += 64) ebp += sT[i * LD + j] * gH0[i * NMAX + j];
       double ecp = 0.0;
       for (int t = tid; t < na; t += NT) ecp += 0.5 * sDqOut[t] * sV[t];
       // pair forces: task (A, part) sums g(A,B) over its B's
@@ -877,7 +887,9 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
 
 }  // namespace
 
-int64_t scc_scratch_per_wg(int nmax) { return 3LL * nmax * nmax + (2LL + 2LL * kMaxHist) * nmax; }
+int64_t scc_scratch_per_wg(int nmax) {
+  return 3LL * nmax * nmax + (2LL + 2LL * kMaxHist) * nmax + (nmax > 64 ? 3LL * nmax * (nmax + 1) : 0);
+}
 
 template <int NMAX, int NT>
 static hipError_t launch_t(int n_wg, const SccArgs& args, hipStream_t stream) {
@@ -899,6 +911,9 @@ hipError_t launch_scc(int nmax, int n_wg, const SccArgs& args, hipStream_t strea
     case 32: return launch_t<32, 256>(n_wg, args, stream);
     case 48: return launch_t<48, 256>(n_wg, args, stream);
     case 64: return launch_t<64, 256>(n_wg, args, stream);
+    case 96: return launch_t<96, 256>(n_wg, args, stream);
+    case 128: return launch_t<128, 256>(n_wg, args, stream);
+    case 192: return launch_t<192, 256>(n_wg, args, stream);
     default: return hipErrorInvalidValue;
   }
 }
@@ -910,6 +925,9 @@ int scc_blocks_per_cu(int nmax) {
     case 32: return occ_t<32, 256>();
     case 48: return occ_t<48, 256>();
     case 64: return occ_t<64, 256>();
+    case 96: return occ_t<96, 256>();
+    case 128: return occ_t<128, 256>();
+    case 192: return occ_t<192, 256>();
     default: return 1;
   }
 }
