@@ -51,8 +51,20 @@ extern "C" {
 #define CAVDFTB_ST_NAN 8           /* non-finite position or charge */
 
 /* Born-charge modes */
-#define CAVDFTB_BORN_MULLIKEN 0 /* Z_A = Q_A I (the paper's cheap replacement, Results) */
-#define CAVDFTB_BORN_FD 1       /* central finite differences of the SCC dipole (Results) */
+#define CAVDFTB_BORN_MULLIKEN 0  /* Z_A = Q_A I (the paper's cheap replacement, Results) */
+#define CAVDFTB_BORN_FD 1        /* central finite differences of the SCC dipole (Results) */
+#define CAVDFTB_BORN_SURROGATE 2 /* learned ensemble, exact FD for units where it disagrees */
+
+/* Surrogate network: per species (O, H) and member, 32 -> 128 SiLU -> 128
+ * SiLU -> 9, flat FP32 parameters [W1 (32x128, row = input) | b1 | W2 (128x128)
+ * | b2 | W3 (128x9) | b3]; normalisation per species [x_mean 32 | x_std 32 |
+ * y_mean 9 | y_scale 9]. */
+#define CAVDFTB_SG_N_IN 32
+#define CAVDFTB_SG_N_HID 128
+#define CAVDFTB_SG_N_OUT 9
+#define CAVDFTB_SG_MEMBERS 4
+#define CAVDFTB_SG_N_PARAM 21897
+#define CAVDFTB_SG_N_NORM 82
 
 #define CAVDFTB_MAX_ORBITALS 192
 
@@ -139,8 +151,14 @@ int cavdftb_eval_units(cavdftb_ctx* ctx, const double* pos, double* energy, doub
  * SCC per unit; CAVDFTB_BORN_FD: central differences with step h (bohr) of the
  * converged SCC dipole, 6 n_atoms displaced SCCs per unit batched in one
  * launch, warm-started from the undisplaced solution (Results: the Born
- * charges are the bottleneck and are taken by finite differences).
- * ens_std is reserved and must be NULL. */
+ * charges are the bottleneck and are taken by finite differences);
+ * CAVDFTB_BORN_SURROGATE: the ensemble set by cavdftb_set_surrogate (mean of
+ * the members, acoustic sum rule imposed per unit); units whose largest
+ * ensemble standard deviation exceeds the threshold are recomputed with
+ * central differences of step h.  ens_std (device [n_atoms], may be NULL)
+ * receives each atom's largest per-component ensemble standard deviation
+ * (surrogate mode only; must be NULL otherwise).  Returns CAVDFTB_EINVAL for
+ * the surrogate mode before cavdftb_set_surrogate. */
 int cavdftb_born_charges(cavdftb_ctx* ctx, const double* pos, int32_t mode, double h, double* born,
                          double* ens_std, int32_t* unit_status);
 
@@ -153,6 +171,43 @@ int cavdftb_born_charges(cavdftb_ctx* ctx, const double* pos, int32_t mode, doub
  * mode functions; the nuclear force is -field[n] (e . Z_A).) */
 int cavdftb_cavity_forces(cavdftb_ctx* ctx, const double* mu_pol, const double* q, double* F, double* field,
                           double* fq);
+
+/* Learned Born-charge surrogate.
+ * cavdftb_set_surrogate copies the ensemble into the context: params (device
+ * FP32 [2 species][CAVDFTB_SG_MEMBERS][CAVDFTB_SG_N_PARAM]), norm (device FP32
+ * [2][CAVDFTB_SG_N_NORM]), and the fallback threshold on the ensemble standard
+ * deviation (elementary charges).
+ * cavdftb_sg_features: per atom the 32 radial descriptors (16 Gaussians of
+ * width 0.367 A on [0.5, 6] A per neighbour species, cosine cutoff at 6 A) and
+ * the local frame R = [e1 e2 e3] (row-major 3x3; O: bisector of its two
+ * nearest H and their plane normal, H: nearest O -> H and the plane normal of
+ * that water), device FP64 [n_atoms][32] and [n_atoms][9].
+ * The remaining calls work on plain device arrays on the given stream (a
+ * hipStream_t or NULL) and train one network (BF16 operands, FP32
+ * accumulation, FP32 master weights):
+ *   sg_prep     x[i][k] = (v[idx[i]][k] - norm[k]) / norm[width + k]  (FP64 in, FP32 out; idx may be NULL)
+ *   sg_forward  y [n][9] from x [n][32]; act [n][256] keeps the pre-activations for sg_backward (or NULL)
+ *   sg_backward grad [N_PARAM] of sum(dy . y); work holds ceil(n/64) x N_PARAM partial sums
+ *   sg_mse      loss[0] = mean (y - t)^2 over count values, dy = 2 (y - t) / count; work >= ceil(count/256)
+ *   sg_adam     Adam (Kingma & Ba) on count parameters, step = 1, 2, ...
+ *   sg_gather   dst[i][:] = src[idx[i]][:]  (FP32 rows of width values)
+ *   sg_moments  out = [mean(width) | std(width)] of the FP64 rows idx (or all n)
+ *   sg_to_local out[i] = R^T Z R for atoms idx[i] (training targets in the local frame, FP64) */
+int cavdftb_set_surrogate(cavdftb_ctx* ctx, const float* params, const float* norm, double std_threshold);
+int cavdftb_sg_features(cavdftb_ctx* ctx, const double* pos, double* feat, double* frames);
+int cavdftb_sg_prep(const double* v, const int32_t* idx, int32_t n, int32_t width, const float* norm, float* x,
+                    void* hip_stream);
+int cavdftb_sg_forward(const float* params, const float* x, int32_t n, float* y, float* act, void* hip_stream);
+int cavdftb_sg_backward(const float* params, const float* x, const float* act, const float* dy, int32_t n,
+                        float* grad, float* work, void* hip_stream);
+int cavdftb_sg_mse(const float* y, const float* t, int32_t count, float* dy, float* loss, float* work,
+                   void* hip_stream);
+int cavdftb_sg_adam(float* params, const float* grad, float* m, float* v, int32_t count, float lr, float beta1,
+                    float beta2, float eps, int32_t step, void* hip_stream);
+int cavdftb_sg_gather(const float* src, const int32_t* idx, int32_t n, int32_t width, float* dst, void* hip_stream);
+int cavdftb_sg_moments(const double* x, const int32_t* idx, int32_t n, int32_t width, float* out, void* hip_stream);
+int cavdftb_sg_to_local(const double* frames, const double* born, const int32_t* idx, int32_t n, double* out,
+                        void* hip_stream);
 
 /* Photon start at frozen matter (Step 0 reading): q_m = -lambda_m F_m/omega_m,
  * p_m = 0, with F from one SCC evaluation at r (device). */
@@ -191,7 +246,8 @@ typedef struct cavdftb_counters {
   double scc_flops;
   double scc_kernel_ms;
   int64_t scc_launches;
-  int64_t jacobi_sweeps; /* Jacobi sweeps summed over all SCC iterations of all jobs */
+  int64_t jacobi_sweeps;             /* Jacobi sweeps summed over all SCC iterations of all jobs */
+  int64_t surrogate_fallback_units;  /* units recomputed by finite differences in surrogate mode */
 } cavdftb_counters;
 int cavdftb_enable_timing(cavdftb_ctx* ctx, int32_t enable);
 int cavdftb_read_counters(cavdftb_ctx* ctx, cavdftb_counters* out);

@@ -15,7 +15,8 @@ LIB_PATH = os.path.join(_HERE, "libcavdftb.so")
 
 OK, EINVAL, ENOMEM, EHIP = 0, -1, -2, -3
 ST_NOT_CONVERGED, ST_NOT_PD, ST_DEGENERATE, ST_NAN = 1, 2, 4, 8
-BORN_MULLIKEN, BORN_FD = 0, 1
+BORN_MULLIKEN, BORN_FD, BORN_SURROGATE = 0, 1, 2
+SG_N_IN, SG_N_HID, SG_N_OUT, SG_MEMBERS, SG_N_PARAM, SG_N_NORM = 32, 128, 9, 4, 21897, 82
 N_OBS = 8
 OBS_NAMES = ("kinetic", "potential", "photon", "total", "temperature", "n_bad_units", "scc_iterations",
              "sum_mu_pol")
@@ -38,7 +39,8 @@ class Layout(ctypes.Structure):
 
 class Counters(ctypes.Structure):
     _fields_ = [("scc_jobs", ctypes.c_int64), ("scc_iterations", ctypes.c_int64), ("scc_flops", _c_d),
-                ("scc_kernel_ms", _c_d), ("scc_launches", ctypes.c_int64), ("jacobi_sweeps", ctypes.c_int64)]
+                ("scc_kernel_ms", _c_d), ("scc_launches", ctypes.c_int64), ("jacobi_sweeps", ctypes.c_int64),
+                ("surrogate_fallback_units", ctypes.c_int64)]
 
 
 SYMBOLS = {
@@ -52,6 +54,17 @@ SYMBOLS = {
     "cavdftb_born_charges": (ctypes.c_int, [_vp, _vp, _c_i32, _c_d, _vp, _vp, _vp]),
     "cavdftb_cavity_forces": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "cavdftb_init_photons": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "cavdftb_set_surrogate": (ctypes.c_int, [_vp, _vp, _vp, _c_d]),
+    "cavdftb_sg_features": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "cavdftb_sg_prep": (ctypes.c_int, [_vp, _vp, _c_i32, _c_i32, _vp, _vp, _vp]),
+    "cavdftb_sg_forward": (ctypes.c_int, [_vp, _vp, _c_i32, _vp, _vp, _vp]),
+    "cavdftb_sg_backward": (ctypes.c_int, [_vp, _vp, _vp, _vp, _c_i32, _vp, _vp, _vp]),
+    "cavdftb_sg_mse": (ctypes.c_int, [_vp, _vp, _c_i32, _vp, _vp, _vp, _vp]),
+    "cavdftb_sg_adam": (ctypes.c_int, [_vp, _vp, _vp, _vp, _c_i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                       ctypes.c_float, _c_i32, _vp]),
+    "cavdftb_sg_gather": (ctypes.c_int, [_vp, _vp, _c_i32, _c_i32, _vp, _vp]),
+    "cavdftb_sg_moments": (ctypes.c_int, [_vp, _vp, _c_i32, _c_i32, _vp, _vp]),
+    "cavdftb_sg_to_local": (ctypes.c_int, [_vp, _vp, _vp, _c_i32, _vp, _vp]),
     "cavdftb_step": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _c_i32, _c_d, _c_i32, _c_d, _vp]),
     "cavdftb_invalidate": (ctypes.c_int, [_vp]),
     "cavdftb_sync": (ctypes.c_int, [_vp, ctypes.POINTER(_c_i32)]),
@@ -188,12 +201,25 @@ class Context:
             _ptr(forces, t.float64, NA * 3, "forces"), _ptr(charges, t.float64, NA, "charges"),
             _ptr(dipole, t.float64, U * 3, "dipole"), _ptr(unit_status, t.int32, U, "unit_status")), "eval_units")
 
-    def born_charges(self, pos, mode, h, born, unit_status=None):
+    def born_charges(self, pos, mode, h, born, unit_status=None, ens_std=None):
         t = self.torch
         self._check(self.lib.cavdftb_born_charges(
             self.ctx, _ptr(pos, t.float64, self.n_atoms * 3, "pos"), int(mode), float(h),
-            _ptr(born, t.float64, self.n_atoms * 9, "born"), None,
+            _ptr(born, t.float64, self.n_atoms * 9, "born"), _ptr(ens_std, t.float64, self.n_atoms, "ens_std"),
             _ptr(unit_status, t.int32, self.n_units, "unit_status")), "born_charges")
+
+    def set_surrogate(self, params, norm, std_threshold=0.05):
+        t = self.torch
+        self._check(self.lib.cavdftb_set_surrogate(
+            self.ctx, _ptr(params, t.float32, 2 * SG_MEMBERS * SG_N_PARAM, "params"),
+            _ptr(norm, t.float32, 2 * SG_N_NORM, "norm"), float(std_threshold)), "set_surrogate")
+
+    def sg_features(self, pos, feat=None, frames=None):
+        t = self.torch
+        self._check(self.lib.cavdftb_sg_features(
+            self.ctx, _ptr(pos, t.float64, self.n_atoms * 3, "pos"),
+            _ptr(feat, t.float64, self.n_atoms * SG_N_IN, "feat"),
+            _ptr(frames, t.float64, self.n_atoms * 9, "frames")), "sg_features")
 
     def cavity_forces(self, mu_pol, q, F=None, field=None, fq=None):
         t = self.torch
@@ -240,3 +266,59 @@ def context_from_system(params, system, stream=None):
     """Convenience constructor from a cavgen system dictionary."""
     return Context(params, system["species"], system["unit_off"], system["unit_x"], system["omega"], system["k"],
                    system["theta"], system["lam"], system["pol"], stream=stream)
+
+
+# ---------------------------------------------------------------- surrogate training calls (no context)
+def _stream_handle(stream):
+    import torch
+    st = torch.cuda.current_stream() if stream is None else stream
+    return _vp(st.cuda_stream)
+
+
+def _rc(rc, what):
+    if rc != OK:
+        raise CavdftbError(f"{what} failed ({rc})")
+
+
+def sg_prep(v, idx, n, width, norm, x, stream=None):
+    _rc(load_library().cavdftb_sg_prep(_ptr(v, name="v"), _ptr(idx, name="idx"), int(n), int(width),
+                                       _ptr(norm, name="norm"), _ptr(x, name="x"), _stream_handle(stream)), "sg_prep")
+
+
+def sg_forward(params, x, n, y, act=None, stream=None):
+    _rc(load_library().cavdftb_sg_forward(_ptr(params, name="params"), _ptr(x, name="x"), int(n), _ptr(y, name="y"),
+                                          _ptr(act, name="act"), _stream_handle(stream)), "sg_forward")
+
+
+def sg_backward(params, x, act, dy, n, grad, work, stream=None):
+    _rc(load_library().cavdftb_sg_backward(_ptr(params, name="params"), _ptr(x, name="x"), _ptr(act, name="act"),
+                                           _ptr(dy, name="dy"), int(n), _ptr(grad, name="grad"),
+                                           _ptr(work, name="work"), _stream_handle(stream)), "sg_backward")
+
+
+def sg_mse(y, t, count, dy, loss, work, stream=None):
+    _rc(load_library().cavdftb_sg_mse(_ptr(y, name="y"), _ptr(t, name="t"), int(count), _ptr(dy, name="dy"),
+                                      _ptr(loss, name="loss"), _ptr(work, name="work"), _stream_handle(stream)),
+        "sg_mse")
+
+
+def sg_adam(params, grad, m, v, count, lr, beta1, beta2, eps, step, stream=None):
+    _rc(load_library().cavdftb_sg_adam(_ptr(params, name="params"), _ptr(grad, name="grad"), _ptr(m, name="m"),
+                                       _ptr(v, name="v"), int(count), float(lr), float(beta1), float(beta2),
+                                       float(eps), int(step), _stream_handle(stream)), "sg_adam")
+
+
+def sg_gather(src, idx, n, width, dst, stream=None):
+    _rc(load_library().cavdftb_sg_gather(_ptr(src, name="src"), _ptr(idx, name="idx"), int(n), int(width),
+                                         _ptr(dst, name="dst"), _stream_handle(stream)), "sg_gather")
+
+
+def sg_moments(x, idx, n, width, out, stream=None):
+    _rc(load_library().cavdftb_sg_moments(_ptr(x, name="x"), _ptr(idx, name="idx"), int(n), int(width),
+                                          _ptr(out, name="out"), _stream_handle(stream)), "sg_moments")
+
+
+def sg_to_local(frames, born, idx, n, out, stream=None):
+    _rc(load_library().cavdftb_sg_to_local(_ptr(frames, name="frames"), _ptr(born, name="born"),
+                                           _ptr(idx, name="idx"), int(n), _ptr(out, name="out"),
+                                           _stream_handle(stream)), "sg_to_local")

@@ -51,6 +51,11 @@ struct Bucket {
   int32_t* d_fd_job_disp = nullptr;
   int32_t* d_fd_unit = nullptr;  // [n_units] unit of each fd block
   int32_t* d_fd_job0 = nullptr;  // [n_units] first fd job (relative to this bucket's mu_job base)
+  // compacted displaced jobs of the units the surrogate hands back (fallback)
+  int32_t* d_fb_job_unit = nullptr;
+  int32_t* d_fb_job_disp = nullptr;
+  int32_t* d_fb_job0 = nullptr;
+  int32_t* d_fb_n = nullptr;
   double* d_scratch = nullptr;
 };
 
@@ -84,6 +89,22 @@ struct cavdftb_ctx {
   int32_t *d_status = nullptr, *d_cjob_status = nullptr, *d_cjob_iters = nullptr;
   int32_t *d_fjob_status = nullptr, *d_fjob_iters = nullptr;
   unsigned long long* d_counters = nullptr;
+  // learned Born-charge surrogate
+  float* d_sg_params = nullptr;  // [2][members][N_PARAM]
+  float* d_sg_norm = nullptr;    // [2][N_NORM]
+  double sg_thr = 0.05;
+  bool sg_ready = false;
+  double* d_sg_feat = nullptr;    // [NA][32]
+  double* d_sg_frames = nullptr;  // [NA][9]
+  float* d_sg_x = nullptr;        // [NA][32], rows of species O then H
+  float* d_sg_y = nullptr;        // [members][NA][9]
+  double* d_sg_std = nullptr;     // [NA]
+  double* d_born = nullptr;       // [NA][9]
+  int32_t* d_unit_flag = nullptr; // [U]
+  int32_t* d_sp_idx = nullptr;    // [NA] atoms of species O, then of species H
+  int32_t* d_pos_in_sp = nullptr; // [NA]
+  int32_t* d_n_sp = nullptr;      // [2]
+  int n_sp[2] = {0, 0};
   std::vector<void*> allocs;
   // controls
   double tol = 1e-8;
@@ -238,13 +259,25 @@ int eval_center(cavdftb_ctx* c, const double* pos, bool forces, bool md = false)
   return CAVDFTB_OK;
 }
 
-// displaced SCCs for the central-difference Born charges; needs eval_center first
-int eval_fd(cavdftb_ctx* c, const double* pos, double h, double* born) {
+// displaced SCCs for the central-difference Born charges; needs eval_center
+// first.  With unit_flag, only the flagged units (compacted on the device).
+int eval_fd(cavdftb_ctx* c, const double* pos, double h, double* born, const int32_t* unit_flag = nullptr) {
   for (const Bucket& b : c->buckets) {
     SccArgs a = base_args(c, pos);
-    a.job_unit = b.d_fd_job_unit;
-    a.job_disp = b.d_fd_job_disp;
-    a.n_jobs = b.n_fd_jobs;
+    const int32_t* job0 = b.d_fd_job0;
+    if (unit_flag) {
+      hipError_t e = launch_fd_compact(b.n_units, b.d_units, c->d_unit_off, unit_flag, b.d_fb_job_unit,
+                                       b.d_fb_job_disp, b.d_fb_job0, b.d_fb_n, c->stream);
+      if (e != hipSuccess) return hip_fail(c, e, "fallback compaction");
+      a.job_unit = b.d_fb_job_unit;
+      a.job_disp = b.d_fb_job_disp;
+      a.n_jobs_dev = b.d_fb_n;
+      job0 = b.d_fb_job0;
+    } else {
+      a.job_unit = b.d_fd_job_unit;
+      a.job_disp = b.d_fd_job_disp;
+    }
+    a.n_jobs = b.n_fd_jobs;  // capacity; the device count bounds the compacted list
     a.fd_h = h;
     a.mu_job = c->d_mu_job + (int64_t)b.fjob0 * 3;
     a.job_status = c->d_fjob_status + b.fjob0;
@@ -252,11 +285,42 @@ int eval_fd(cavdftb_ctx* c, const double* pos, double h, double* born) {
     a.flags = JF_WARM_C | JF_WARM_DQ | (c->keep_hist ? JF_WARM_HIST : 0);
     int rc = run_scc(c, b, a);
     if (rc) return rc;
-    hipError_t e = launch_born_fd_assemble(c->d_unit_off, b.d_fd_unit, b.d_fd_job0, b.n_units,
+    hipError_t e = launch_born_fd_assemble(c->d_unit_off, b.d_fd_unit, job0, b.n_units,
                                            c->d_mu_job + (int64_t)b.fjob0 * 3, h, c->pol,
-                                           c->d_fjob_status + b.fjob0, born, c->d_zpol, c->d_status, c->stream);
+                                           c->d_fjob_status + b.fjob0, unit_flag, born, c->d_zpol, c->d_status,
+                                           c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "born fd assemble");
   }
+  return CAVDFTB_OK;
+}
+
+// surrogate Born charges at pos into born (ensemble mean, acoustic sum imposed),
+// ensemble spread into d_sg_std and the fallback flags into d_unit_flag
+int sg_infer(cavdftb_ctx* c, const double* pos, double* born) {
+  hipStream_t st = c->stream;
+  hipError_t e = launch_sg_features(c->NA, c->d_atom_unit, c->d_unit_off, c->d_species, pos, c->d_sg_feat,
+                                    c->d_sg_frames, st);
+  if (e != hipSuccess) return hip_fail(c, e, "surrogate features");
+  int64_t off = 0, ybase = 0;
+  for (int sp = 0; sp < 2; ++sp) {
+    const int n = c->n_sp[sp];
+    if (n > 0) {
+      e = launch_sg_prep(n, CAVDFTB_SG_N_IN, c->d_sp_idx + off, c->d_sg_feat, c->d_sg_norm + sp * CAVDFTB_SG_N_NORM,
+                         c->d_sg_x + off * CAVDFTB_SG_N_IN, st);
+      for (int m = 0; m < CAVDFTB_SG_MEMBERS && e == hipSuccess; ++m)
+        e = launch_sg_forward(c->d_sg_params + ((int64_t)sp * CAVDFTB_SG_MEMBERS + m) * CAVDFTB_SG_N_PARAM,
+                              c->d_sg_x + off * CAVDFTB_SG_N_IN, n,
+                              c->d_sg_y + ybase + (int64_t)m * n * CAVDFTB_SG_N_OUT, nullptr, st);
+      if (e != hipSuccess) return hip_fail(c, e, "surrogate forward");
+    }
+    off += n;
+    ybase += (int64_t)CAVDFTB_SG_MEMBERS * n * CAVDFTB_SG_N_OUT;
+  }
+  e = launch_sg_combine(c->NA, c->d_species, c->d_pos_in_sp, c->d_n_sp, c->d_sg_y, c->d_sg_norm, c->d_sg_frames,
+                        born, c->d_sg_std, st);
+  if (e == hipSuccess)
+    e = launch_sg_asr_flag(c->U, c->d_unit_off, born, c->d_sg_std, c->sg_thr, c->d_unit_flag, c->d_counters + 4, st);
+  if (e != hipSuccess) return hip_fail(c, e, "surrogate combine");
   return CAVDFTB_OK;
 }
 
@@ -282,6 +346,12 @@ int matter_stage(cavdftb_ctx* c, const double* r, int born_mode, double h) {
   if (born_mode == CAVDFTB_BORN_FD) {
     rc = eval_fd(c, r, h, nullptr);
     if (rc) return rc;
+  } else if (born_mode == CAVDFTB_BORN_SURROGATE) {
+    rc = sg_infer(c, r, c->d_born);
+    if (rc == CAVDFTB_OK) rc = eval_fd(c, r, h, c->d_born, c->d_unit_flag);
+    if (rc) return rc;
+    e = launch_zpol_from_born(c->NA, c->d_born, c->pol, c->d_zpol, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "zpol");
   } else {
     e = launch_zpol_mulliken(c->d_charges, c->pol, c->NA, c->d_zpol, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "zpol");
@@ -412,7 +482,34 @@ int cavdftb_create(const cavdftb_params* params, const cavdftb_layout* L, void* 
   CK(dalloc(c, &c->d_status, U));
   CK(dalloc(c, &c->d_cjob_status, U));
   CK(dalloc(c, &c->d_cjob_iters, U));
-  CK(dalloc(c, &c->d_counters, 4));
+  CK(dalloc(c, &c->d_sg_params, 2 * (size_t)CAVDFTB_SG_MEMBERS * CAVDFTB_SG_N_PARAM));
+  CK(dalloc(c, &c->d_sg_norm, 2 * (size_t)CAVDFTB_SG_N_NORM));
+  CK(dalloc(c, &c->d_sg_feat, (size_t)NA * CAVDFTB_SG_N_IN));
+  CK(dalloc(c, &c->d_sg_frames, (size_t)NA * 9));
+  CK(dalloc(c, &c->d_sg_x, (size_t)NA * CAVDFTB_SG_N_IN));
+  CK(dalloc(c, &c->d_sg_y, (size_t)CAVDFTB_SG_MEMBERS * NA * CAVDFTB_SG_N_OUT));
+  CK(dalloc(c, &c->d_sg_std, NA));
+  CK(dalloc(c, &c->d_born, (size_t)NA * 9));
+  CK(dalloc(c, &c->d_unit_flag, U));
+  CK(dalloc(c, &c->d_sp_idx, NA));
+  CK(dalloc(c, &c->d_pos_in_sp, NA));
+  CK(dalloc(c, &c->d_n_sp, 2));
+  {
+    std::vector<int32_t> idx, pos_in(NA);
+    for (int sp = 0; sp < 2; ++sp) {
+      int k = 0;
+      for (int a2 = 0; a2 < NA; ++a2)
+        if (L->species[a2] == sp) {
+          idx.push_back(a2);
+          pos_in[a2] = k++;
+        }
+      c->n_sp[sp] = k;
+    }
+    CK(hipMemcpy(c->d_sp_idx, idx.data(), NA * sizeof(int32_t), hipMemcpyHostToDevice));
+    CK(hipMemcpy(c->d_pos_in_sp, pos_in.data(), NA * sizeof(int32_t), hipMemcpyHostToDevice));
+    CK(hipMemcpy(c->d_n_sp, c->n_sp, 2 * sizeof(int32_t), hipMemcpyHostToDevice));
+  }
+  CK(dalloc(c, &c->d_counters, 8));
   CK(hipMemcpy(c->d_unit_off, c->h_unit_off.data(), (U + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
   CK(hipMemcpy(c->d_species, L->species, NA, hipMemcpyHostToDevice));
   CK(hipMemcpy(c->d_unit_x, L->unit_x, U * sizeof(double), hipMemcpyHostToDevice));
@@ -429,7 +526,7 @@ int cavdftb_create(const cavdftb_params* params, const cavdftb_layout* L, void* 
   CK(hipMemset(c->d_ws_dq, 0, NA * sizeof(double)));
   CK(hipMemcpy(c->d_hist_off, hist_off.data(), U * sizeof(int64_t), hipMemcpyHostToDevice));
   CK(hipMemset(c->d_hist, 0, hist_total * sizeof(double)));
-  CK(hipMemset(c->d_counters, 0, 4 * sizeof(unsigned long long)));
+  CK(hipMemset(c->d_counters, 0, 8 * sizeof(unsigned long long)));
   CK(hipMemset(c->d_status, 0, U * sizeof(int32_t)));
   CK(hipMemset(c->d_cjob_iters, 0, U * sizeof(int32_t)));
   CK(hipMemset(c->d_energy, 0, U * sizeof(double)));
@@ -469,6 +566,10 @@ int cavdftb_create(const cavdftb_params* params, const cavdftb_layout* L, void* 
     CK(dalloc(c, &b.d_fd_job_disp, b.n_fd_jobs));
     CK(dalloc(c, &b.d_fd_unit, b.n_units));
     CK(dalloc(c, &b.d_fd_job0, b.n_units));
+    CK(dalloc(c, &b.d_fb_job_unit, b.n_fd_jobs));
+    CK(dalloc(c, &b.d_fb_job_disp, b.n_fd_jobs));
+    CK(dalloc(c, &b.d_fb_job0, b.n_units));
+    CK(dalloc(c, &b.d_fb_n, 1));
     CK(hipMemcpy(b.d_fd_job_unit, jun.data(), jun.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     CK(hipMemcpy(b.d_fd_job_disp, jdisp.data(), jdisp.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     CK(hipMemcpy(b.d_fd_unit, fdu.data(), fdu.size() * sizeof(int32_t), hipMemcpyHostToDevice));
@@ -558,19 +659,31 @@ int cavdftb_eval_units(cavdftb_ctx* ctx, const double* pos, double* energy, doub
 int cavdftb_born_charges(cavdftb_ctx* ctx, const double* pos, int32_t mode, double h, double* born,
                          double* ens_std, int32_t* unit_status) {
   if (!ctx) return CAVDFTB_EINVAL;
-  if (!pos || !born || ens_std) return fail(ctx, CAVDFTB_EINVAL, "born_charges: bad pointer arguments");
-  if (mode != CAVDFTB_BORN_MULLIKEN && mode != CAVDFTB_BORN_FD)
+  if (!pos || !born || (ens_std && mode != CAVDFTB_BORN_SURROGATE))
+    return fail(ctx, CAVDFTB_EINVAL, "born_charges: bad pointer arguments");
+  if (mode != CAVDFTB_BORN_MULLIKEN && mode != CAVDFTB_BORN_FD && mode != CAVDFTB_BORN_SURROGATE)
     return fail(ctx, CAVDFTB_EINVAL, "born_charges: unknown mode");
-  if (mode == CAVDFTB_BORN_FD && !(h > 0.0)) return fail(ctx, CAVDFTB_EINVAL, "born_charges: need h > 0");
+  if (mode != CAVDFTB_BORN_MULLIKEN && !(h > 0.0)) return fail(ctx, CAVDFTB_EINVAL, "born_charges: need h > 0");
+  if (mode == CAVDFTB_BORN_SURROGATE && !ctx->sg_ready)
+    return fail(ctx, CAVDFTB_EINVAL, "born_charges: no surrogate set (cavdftb_set_surrogate)");
   int rc = eval_center(ctx, pos, false);
   if (rc) return rc;
   ctx->primed = false;
   if (mode == CAVDFTB_BORN_MULLIKEN) {
     hipError_t e = launch_born_mulliken(ctx->d_charges, ctx->NA, born, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "born mulliken");
-  } else {
+  } else if (mode == CAVDFTB_BORN_FD) {
     rc = eval_fd(ctx, pos, h, born);
     if (rc) return rc;
+  } else {
+    rc = sg_infer(ctx, pos, born);
+    if (rc == CAVDFTB_OK) rc = eval_fd(ctx, pos, h, born, ctx->d_unit_flag);
+    if (rc) return rc;
+    if (ens_std) {
+      hipError_t e = hipMemcpyAsync(ens_std, ctx->d_sg_std, ctx->NA * sizeof(double), hipMemcpyDeviceToDevice,
+                                    ctx->stream);
+      if (e != hipSuccess) return hip_fail(ctx, e, "ens_std copy");
+    }
   }
   if (unit_status) {
     hipError_t e = hipMemcpyAsync(unit_status, ctx->d_status, ctx->U * sizeof(int32_t), hipMemcpyDeviceToDevice,
@@ -593,6 +706,84 @@ int cavdftb_cavity_forces(cavdftb_ctx* ctx, const double* mu_pol, const double* 
     if (e != hipSuccess) return hip_fail(ctx, e, "cavity gather");
   }
   return CAVDFTB_OK;
+}
+
+int cavdftb_set_surrogate(cavdftb_ctx* ctx, const float* params, const float* norm, double std_threshold) {
+  if (!ctx) return CAVDFTB_EINVAL;
+  if (!params || !norm || !(std_threshold >= 0.0))
+    return fail(ctx, CAVDFTB_EINVAL, "set_surrogate: need params, norm and a threshold >= 0");
+  hipError_t e = hipMemcpyAsync(ctx->d_sg_params, params,
+                                2 * (size_t)CAVDFTB_SG_MEMBERS * CAVDFTB_SG_N_PARAM * sizeof(float),
+                                hipMemcpyDeviceToDevice, ctx->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(ctx->d_sg_norm, norm, 2 * (size_t)CAVDFTB_SG_N_NORM * sizeof(float), hipMemcpyDeviceToDevice,
+                       ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "set_surrogate copy");
+  ctx->sg_thr = std_threshold;
+  ctx->sg_ready = true;
+  return CAVDFTB_OK;
+}
+
+int cavdftb_sg_features(cavdftb_ctx* ctx, const double* pos, double* feat, double* frames) {
+  if (!ctx) return CAVDFTB_EINVAL;
+  if (!pos || (!feat && !frames)) return fail(ctx, CAVDFTB_EINVAL, "sg_features: null pointer");
+  hipError_t e = launch_sg_features(ctx->NA, ctx->d_atom_unit, ctx->d_unit_off, ctx->d_species, pos, feat, frames,
+                                    ctx->stream);
+  return e == hipSuccess ? CAVDFTB_OK : hip_fail(ctx, e, "sg_features");
+}
+
+int cavdftb_sg_prep(const double* v, const int32_t* idx, int32_t n, int32_t width, const float* norm, float* x,
+                    void* hip_stream) {
+  if (!v || !norm || !x || n < 0 || width <= 0) return CAVDFTB_EINVAL;
+  return launch_sg_prep(n, width, idx, v, norm, x, (hipStream_t)hip_stream) == hipSuccess ? CAVDFTB_OK
+                                                                                        : CAVDFTB_EHIP;
+}
+
+int cavdftb_sg_forward(const float* params, const float* x, int32_t n, float* y, float* act, void* hip_stream) {
+  if (!params || !x || !y || n < 0) return CAVDFTB_EINVAL;
+  return launch_sg_forward(params, x, n, y, act, (hipStream_t)hip_stream) == hipSuccess ? CAVDFTB_OK : CAVDFTB_EHIP;
+}
+
+int cavdftb_sg_backward(const float* params, const float* x, const float* act, const float* dy, int32_t n,
+                        float* grad, float* work, void* hip_stream) {
+  if (!params || !x || !act || !dy || !grad || !work || n <= 0) return CAVDFTB_EINVAL;
+  return launch_sg_backward(params, x, act, dy, n, grad, work, (hipStream_t)hip_stream) == hipSuccess ? CAVDFTB_OK
+                                                                                                    : CAVDFTB_EHIP;
+}
+
+int cavdftb_sg_mse(const float* y, const float* t, int32_t count, float* dy, float* loss, float* work,
+                   void* hip_stream) {
+  if (!y || !t || !dy || !loss || !work || count <= 0) return CAVDFTB_EINVAL;
+  return launch_sg_mse(y, t, count, dy, loss, work, (hipStream_t)hip_stream) == hipSuccess ? CAVDFTB_OK
+                                                                                          : CAVDFTB_EHIP;
+}
+
+int cavdftb_sg_adam(float* params, const float* grad, float* m, float* v, int32_t count, float lr, float beta1,
+                    float beta2, float eps, int32_t step, void* hip_stream) {
+  if (!params || !grad || !m || !v || count <= 0 || step < 1) return CAVDFTB_EINVAL;
+  return launch_sg_adam(params, grad, m, v, count, lr, beta1, beta2, eps, step, (hipStream_t)hip_stream) ==
+                 hipSuccess
+             ? CAVDFTB_OK
+             : CAVDFTB_EHIP;
+}
+
+int cavdftb_sg_gather(const float* src, const int32_t* idx, int32_t n, int32_t width, float* dst, void* hip_stream) {
+  if (!src || !idx || !dst || n < 0 || width <= 0) return CAVDFTB_EINVAL;
+  return launch_sg_gather(src, idx, n, width, dst, (hipStream_t)hip_stream) == hipSuccess ? CAVDFTB_OK
+                                                                                         : CAVDFTB_EHIP;
+}
+
+int cavdftb_sg_moments(const double* x, const int32_t* idx, int32_t n, int32_t width, float* out, void* hip_stream) {
+  if (!x || !out || n <= 0 || width <= 0) return CAVDFTB_EINVAL;
+  return launch_sg_moments(x, idx, n, width, out, (hipStream_t)hip_stream) == hipSuccess ? CAVDFTB_OK
+                                                                                        : CAVDFTB_EHIP;
+}
+
+int cavdftb_sg_to_local(const double* frames, const double* born, const int32_t* idx, int32_t n, double* out,
+                        void* hip_stream) {
+  if (!frames || !born || !out || n < 0) return CAVDFTB_EINVAL;
+  return launch_sg_to_local(n, idx, frames, born, out, (hipStream_t)hip_stream) == hipSuccess ? CAVDFTB_OK
+                                                                                             : CAVDFTB_EHIP;
 }
 
 int cavdftb_init_photons(cavdftb_ctx* ctx, const double* r, double* qm, double* pm) {
@@ -620,9 +811,11 @@ int cavdftb_step(cavdftb_ctx* ctx, double* r, double* p, double* qm, double* pm,
   if (!ctx) return CAVDFTB_EINVAL;
   if (!r || !p || (ctx->M > 0 && (!qm || !pm)) || n_steps < 0 || !(dt > 0.0))
     return fail(ctx, CAVDFTB_EINVAL, "step: bad arguments");
-  if (born_mode != CAVDFTB_BORN_MULLIKEN && born_mode != CAVDFTB_BORN_FD)
+  if (born_mode != CAVDFTB_BORN_MULLIKEN && born_mode != CAVDFTB_BORN_FD && born_mode != CAVDFTB_BORN_SURROGATE)
     return fail(ctx, CAVDFTB_EINVAL, "step: unknown born mode");
-  if (born_mode == CAVDFTB_BORN_FD && !(h_fd > 0.0)) return fail(ctx, CAVDFTB_EINVAL, "step: need h_fd > 0");
+  if (born_mode != CAVDFTB_BORN_MULLIKEN && !(h_fd > 0.0)) return fail(ctx, CAVDFTB_EINVAL, "step: need h_fd > 0");
+  if (born_mode == CAVDFTB_BORN_SURROGATE && !ctx->sg_ready)
+    return fail(ctx, CAVDFTB_EINVAL, "step: no surrogate set (cavdftb_set_surrogate)");
   hipStream_t s = ctx->stream;
   CavArgs ca = cav_args(ctx);
   hipError_t e;
@@ -694,13 +887,17 @@ int cavdftb_read_counters(cavdftb_ctx* ctx, cavdftb_counters* out) {
   out->scc_kernel_ms = ctx->t_ms;
   out->scc_launches = ctx->launches;
   out->jacobi_sweeps = (int64_t)h[3];
+  unsigned long long h4 = 0;
+  e = hipMemcpy(&h4, ctx->d_counters + 4, sizeof(h4), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(ctx, e, "counters copy");
+  out->surrogate_fallback_units = (int64_t)h4;
   return CAVDFTB_OK;
 }
 
 int cavdftb_reset_counters(cavdftb_ctx* ctx) {
   if (!ctx) return CAVDFTB_EINVAL;
   hipError_t e = hipStreamSynchronize(ctx->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(ctx->d_counters, 0, 4 * sizeof(unsigned long long), ctx->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(ctx->d_counters, 0, 8 * sizeof(unsigned long long), ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "reset counters");
   harvest_events(ctx);

@@ -35,7 +35,9 @@ struct SccArgs {
   const int8_t* species;    // [n_atoms]
   const int32_t* job_unit;  // [n_jobs]
   const int32_t* job_disp;  // [n_jobs] or nullptr; -1 = none, else (atom*3+dir)*2 + (step<0)
+  const int32_t* unit_mask; // [n_units] or nullptr: jobs of units with mask 0 are skipped
   int32_t n_jobs;
+  const int32_t* n_jobs_dev; // if set, the job count is read from device memory (compacted job lists)
   double fd_h;
   const int64_t* ws_off;    // [n_units] offset of the unit's stored basis in ws_C (doubles)
   double* ws_C;             // stored MO bases, NMAX x NMAX per unit of the bucket
@@ -94,8 +96,8 @@ hipError_t launch_zpol_mulliken(const double* charges, const double pol[3], int 
                                 hipStream_t s);
 hipError_t launch_born_fd_assemble(const int32_t* unit_off, const int32_t* fd_unit, const int32_t* fd_job0,
                                    int n_fd_units, const double* mu_job, double h, const double pol[3],
-                                   const int32_t* job_status, double* born, double* zpol, int32_t* status,
-                                   hipStream_t s);
+                                   const int32_t* job_status, const int32_t* unit_mask, double* born, double* zpol,
+                                   int32_t* status, hipStream_t s);
 hipError_t launch_kick_drift(int n_atoms, const int32_t* atom_unit, const double* inv_mass, const double* forces,
                              const double* zpol, const double* field, double dt, double* r, double* p,
                              int do_drift, hipStream_t s);
@@ -106,5 +108,30 @@ hipError_t launch_observables(int n_units, int n_atoms, int n_modes, const int32
                               const double* qm, const double* pm, const double* omega, const double* lam,
                               const double* F, const double* mu_pol, const int32_t* status,
                               const int32_t* job_iters, int n_jobs, double* obs, hipStream_t s);
+
+// ---- surrogate kernels (sg_kernels.hip) ----
+hipError_t launch_sg_features(int n_atoms, const int32_t* atom_unit, const int32_t* unit_off, const int8_t* species,
+                              const double* pos, double* feat, double* frames, hipStream_t s);
+hipError_t launch_sg_prep(int n, int width, const int32_t* idx, const double* v, const float* norm, float* x,
+                          hipStream_t s);
+hipError_t launch_sg_forward(const float* P, const float* x, int n, float* y, float* act, hipStream_t s);
+hipError_t launch_sg_backward(const float* P, const float* x, const float* act, const float* dy, int n, float* grad,
+                              float* work, hipStream_t s);
+hipError_t launch_sg_mse(const float* y, const float* t, int count, float* dy, float* loss, float* work,
+                         hipStream_t s);
+hipError_t launch_sg_adam(float* w, const float* g, float* m, float* v, int count, float lr, float b1, float b2,
+                          float eps, int step, hipStream_t s);
+hipError_t launch_sg_gather(const float* src, const int32_t* idx, int n, int width, float* dst, hipStream_t s);
+hipError_t launch_sg_moments(const double* x, const int32_t* idx, int n, int width, float* out, hipStream_t s);
+hipError_t launch_sg_to_local(int n, const int32_t* idx, const double* frames, const double* born, double* out,
+                              hipStream_t s);
+hipError_t launch_sg_combine(int n_atoms, const int8_t* species, const int32_t* pos_in_species,
+                             const int32_t* n_species, const float* ybuf, const float* norm, const double* frames,
+                             double* born, double* std, hipStream_t s);
+hipError_t launch_sg_asr_flag(int n_units, const int32_t* unit_off, double* born, const double* std, double thr,
+                              int32_t* flag, unsigned long long* n_flagged, hipStream_t s);
+hipError_t launch_zpol_from_born(int n, const double* born, const double pol[3], double* zp, hipStream_t s);
+hipError_t launch_fd_compact(int n_units_b, const int32_t* units_b, const int32_t* unit_off, const int32_t* flag,
+                             int32_t* job_unit, int32_t* job_disp, int32_t* job0, int32_t* n_jobs, hipStream_t s);
 
 }  // namespace cavdftb

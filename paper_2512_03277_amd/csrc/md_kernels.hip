@@ -108,11 +108,12 @@ __global__ __launch_bounds__(256) void born_fd_kernel(const int32_t* __restrict_
                                                       const int32_t* __restrict__ fd_unit,
                                                       const int32_t* __restrict__ fd_job0, int n_fd_units,
                                                       const double* __restrict__ mu_job, double h, double e0,
-                                                      double e1, double e2, double* __restrict__ born,
-                                                      double* __restrict__ zpol) {
+                                                      double e1, double e2, const int32_t* __restrict__ mask,
+                                                      double* __restrict__ born, double* __restrict__ zpol) {
   const int w = blockIdx.x;
   if (w >= n_fd_units) return;
   const int u = fd_unit[w];
+  if (mask && !mask[u]) return;
   const int a0 = unit_off[u], na = unit_off[u + 1] - a0;
   const int64_t j0 = fd_job0[w];
   for (int loc = threadIdx.x; loc < na; loc += blockDim.x) {
@@ -135,10 +136,12 @@ __global__ __launch_bounds__(kNT) void born_fd_status_kernel(const int32_t* __re
                                                              const int32_t* __restrict__ fd_unit,
                                                              const int32_t* __restrict__ fd_job0, int n_fd_units,
                                                              const int32_t* __restrict__ job_status,
+                                                             const int32_t* __restrict__ mask,
                                                              int32_t* __restrict__ status) {
   const int w = blockIdx.x * kNT + threadIdx.x;
   if (w >= n_fd_units) return;
   const int u = fd_unit[w];
+  if (mask && !mask[u]) return;
   const int na = unit_off[u + 1] - unit_off[u];
   int st = status[u];
   for (int j = 0; j < 6 * na; ++j) st |= job_status[fd_job0[w] + j];
@@ -283,16 +286,16 @@ hipError_t launch_zpol_mulliken(const double* charges, const double pol[3], int 
 
 hipError_t launch_born_fd_assemble(const int32_t* unit_off, const int32_t* fd_unit, const int32_t* fd_job0,
                                    int n_fd_units, const double* mu_job, double h, const double pol[3],
-                                   const int32_t* job_status, double* born, double* zpol, int32_t* status,
-                                   hipStream_t s) {
+                                   const int32_t* job_status, const int32_t* unit_mask, double* born, double* zpol,
+                                   int32_t* status, hipStream_t s) {
   if (n_fd_units <= 0) return hipSuccess;
   hipLaunchKernelGGL(born_fd_kernel, dim3(n_fd_units), dim3(256), 0, s, unit_off, fd_unit, fd_job0, n_fd_units,
-                     mu_job, h, pol[0], pol[1], pol[2], born, zpol);
+                     mu_job, h, pol[0], pol[1], pol[2], unit_mask, born, zpol);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (status && job_status) {
     hipLaunchKernelGGL(born_fd_status_kernel, dim3(nblk(n_fd_units)), dim3(kNT), 0, s, unit_off, fd_unit, fd_job0,
-                       n_fd_units, job_status, status);
+                       n_fd_units, job_status, unit_mask, status);
     e = hipGetLastError();
   }
   return e;

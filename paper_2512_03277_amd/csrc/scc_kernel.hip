@@ -377,8 +377,16 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
   double* sT = GM ? sA + NMAX * LD : lT;
   double* sF = F_IN_X ? sX : sFbuf;
 
-  for (int job = blockIdx.x; job < a.n_jobs; job += gridDim.x) {
+  const int n_jobs = a.n_jobs_dev ? *a.n_jobs_dev : a.n_jobs;
+  for (int job = blockIdx.x; job < n_jobs; job += gridDim.x) {
     const int u = a.job_unit[job];
+    if (a.unit_mask && !a.unit_mask[u]) {  // block-uniform skip (fallback launches)
+      if (tid == 0) {
+        if (a.job_status) a.job_status[job] = 0;
+        if (a.job_iters) a.job_iters[job] = 0;
+      }
+      continue;
+    }
     const int disp = a.job_disp ? a.job_disp[job] : -1;
     const int a0 = a.unit_off[u];
     const int na = a.unit_off[u + 1] - a0;

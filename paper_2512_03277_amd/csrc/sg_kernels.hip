@@ -1,0 +1,599 @@
+// Learned Born-charge surrogate kernels (gfx950).
+//
+// The paper obtains the Born charges by finite differences and names them the
+// bottleneck of the method (Results; Conclusion).  These kernels evaluate and
+// train the replacement: radial descriptors and atom-local frames, a per-species
+// 32 -> 128 -> 128 -> 9 SiLU network ensemble with BF16 operands and FP32
+// accumulation, the ensemble mean/spread with the acoustic-sum projection, and
+// the Adam update of the FP32 master weights.  Every reduction has a fixed
+// order (per-tile partial sums reduced in tile order), so results do not depend
+// on scheduling.
+#include <math.h>
+
+#include "internal.h"
+
+namespace cavdftb {
+namespace {
+
+constexpr int NIN = CAVDFTB_SG_N_IN, NHID = CAVDFTB_SG_N_HID, NOUT = CAVDFTB_SG_N_OUT;
+constexpr int OFF_W1 = 0, OFF_B1 = OFF_W1 + NIN * NHID, OFF_W2 = OFF_B1 + NHID, OFF_B2 = OFF_W2 + NHID * NHID,
+              OFF_W3 = OFF_B2 + NHID, OFF_B3 = OFF_W3 + NHID * NOUT, NPAR = OFF_B3 + NOUT;
+static_assert(NPAR == CAVDFTB_SG_N_PARAM, "parameter layout");
+constexpr int TILE = 64;  // atoms per workgroup
+constexpr int NT = 256;
+
+constexpr double kAng = 1.8897261246;
+
+// float -> bfloat16 -> float, round to nearest even (finite inputs)
+__device__ __forceinline__ float bf16r(float x) {
+  unsigned int u = __float_as_uint(x);
+  u = (u + 0x7FFFu + ((u >> 16) & 1u)) & 0xFFFF0000u;
+  return __uint_as_float(u);
+}
+
+__device__ __forceinline__ float silu(float z) { return z / (1.0f + expf(-z)); }
+__device__ __forceinline__ float dsilu(float z) {
+  const float s = 1.0f / (1.0f + expf(-z));
+  return s * (1.0f + z * (1.0f - s));
+}
+
+// ---------------------------------------------------------------- descriptors and frames
+__device__ void unit3(double v[3]) {
+  const double r = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+  v[0] /= r;
+  v[1] /= r;
+  v[2] /= r;
+}
+__device__ void cross3(const double a[3], const double b[3], double c[3]) {
+  c[0] = a[1] * b[2] - a[2] * b[1];
+  c[1] = a[2] * b[0] - a[0] * b[2];
+  c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+// two nearest atoms of species `sp` to atom a within [a0, a1), excluding `skip`
+// (ties broken by the lower index)
+__device__ void nearest2(const double* pos, const int8_t* species, int a0, int a1, int a, int sp, int skip,
+                         int& i1, int& i2) {
+  double d1 = INFINITY, d2 = INFINITY;
+  i1 = -1;
+  i2 = -1;
+  for (int b = a0; b < a1; ++b) {
+    if (b == a || b == skip || species[b] != sp) continue;
+    const double dx = pos[b * 3] - pos[a * 3], dy = pos[b * 3 + 1] - pos[a * 3 + 1],
+                 dz = pos[b * 3 + 2] - pos[a * 3 + 2];
+    const double d = sqrt(dx * dx + dy * dy + dz * dz);
+    if (d < d1) {
+      d2 = d1;
+      i2 = i1;
+      d1 = d;
+      i1 = b;
+    } else if (d < d2) {
+      d2 = d;
+      i2 = b;
+    }
+  }
+}
+
+__global__ __launch_bounds__(NT) void features_kernel(int n_atoms, const int32_t* __restrict__ atom_unit,
+                                                      const int32_t* __restrict__ unit_off,
+                                                      const int8_t* __restrict__ species,
+                                                      const double* __restrict__ pos, double* __restrict__ feat,
+                                                      double* __restrict__ frames) {
+  const int a = blockIdx.x * NT + threadIdx.x;
+  if (a >= n_atoms) return;
+  const int u = atom_unit[a];
+  const int a0 = unit_off[u], a1 = unit_off[u + 1];
+  const double rc = 6.0 * kAng;
+  const double r0 = 0.5 * kAng, dr = (6.0 - 0.5) * kAng / 15.0;
+  double g[NIN];
+  for (int k = 0; k < NIN; ++k) g[k] = 0.0;
+  for (int b = a0; b < a1; ++b) {
+    if (b == a) continue;
+    const double dx = pos[b * 3] - pos[a * 3], dy = pos[b * 3 + 1] - pos[a * 3 + 1], dz = pos[b * 3 + 2] - pos[a * 3 + 2];
+    const double r = sqrt(dx * dx + dy * dy + dz * dz);
+    if (r >= rc) continue;
+    const double fc = 0.5 * (cos(M_PI * r / rc) + 1.0);
+    const int s = species[b];
+    for (int k = 0; k < 16; ++k) {
+      const double t = r - (r0 + k * dr);
+      g[s * 16 + k] += exp(-t * t / (2.0 * dr * dr)) * fc;
+    }
+  }
+  if (feat)
+    for (int k = 0; k < NIN; ++k) feat[(int64_t)a * NIN + k] = g[k];
+  if (!frames) return;
+  double e1[3] = {1, 0, 0}, e2[3] = {0, 1, 0}, e3[3];
+  if (species[a] == 0) {
+    int h1, h2;
+    nearest2(pos, species, a0, a1, a, 1, -1, h1, h2);
+    if (h2 >= 0) {
+      double v1[3], v2[3];
+      for (int c = 0; c < 3; ++c) {
+        v1[c] = pos[h1 * 3 + c] - pos[a * 3 + c];
+        v2[c] = pos[h2 * 3 + c] - pos[a * 3 + c];
+      }
+      unit3(v1);
+      unit3(v2);
+      for (int c = 0; c < 3; ++c) e1[c] = v1[c] + v2[c];
+      unit3(e1);
+      cross3(v1, v2, e2);
+      unit3(e2);
+    }
+  } else {
+    int o, o2;
+    nearest2(pos, species, a0, a1, a, 0, -1, o, o2);
+    if (o >= 0) {
+      int hh, hh2;
+      nearest2(pos, species, a0, a1, o, 1, a, hh, hh2);
+      double v1[3], v2[3];
+      for (int c = 0; c < 3; ++c) v1[c] = pos[a * 3 + c] - pos[o * 3 + c];
+      for (int c = 0; c < 3; ++c) e1[c] = v1[c];
+      unit3(e1);
+      if (hh >= 0) {
+        for (int c = 0; c < 3; ++c) v2[c] = pos[hh * 3 + c] - pos[o * 3 + c];
+        cross3(v1, v2, e2);
+        unit3(e2);
+        const double pr = e2[0] * e1[0] + e2[1] * e1[1] + e2[2] * e1[2];
+        for (int c = 0; c < 3; ++c) e2[c] -= pr * e1[c];
+        unit3(e2);
+      }
+    }
+  }
+  cross3(e1, e2, e3);
+  for (int c = 0; c < 3; ++c) {  // R = [e1 e2 e3], row-major R[c][j]
+    frames[(int64_t)a * 9 + c * 3 + 0] = e1[c];
+    frames[(int64_t)a * 9 + c * 3 + 1] = e2[c];
+    frames[(int64_t)a * 9 + c * 3 + 2] = e3[c];
+  }
+}
+
+// standardised FP32 rows of the listed atoms: x = (v - mean) / scale, with
+// norm = [mean(width) | scale(width)]
+__global__ __launch_bounds__(NT) void prep_kernel(int n, int width, const int32_t* __restrict__ idx,
+                                                  const double* __restrict__ v, const float* __restrict__ norm,
+                                                  float* __restrict__ x) {
+  const int e = blockIdx.x * NT + threadIdx.x;
+  if (e >= n * width) return;
+  const int i = e / width, k = e % width;
+  const int a = idx ? idx[i] : i;
+  x[e] = (float)((v[(int64_t)a * width + k] - (double)norm[k]) / (double)norm[width + k]);
+}
+
+// ---------------------------------------------------------------- network
+// one hidden layer for a 64-atom tile: out[a][j] = sum_k bf16(in[a][k]) bf16(W[k][j]) + b[j]
+template <int K>
+__device__ void dense_hidden(const float* __restrict__ in, int ldin, const float* __restrict__ W,
+                             const float* __restrict__ b, float* __restrict__ zout, float* __restrict__ hout) {
+  const int og = threadIdx.x & 15, ag = threadIdx.x >> 4;  // 8 outputs x 4 atoms per thread
+  float acc[4][8];
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 8; ++j) acc[i][j] = 0.0f;
+  for (int k = 0; k < K; ++k) {
+    float av[4], wv[8];
+    for (int i = 0; i < 4; ++i) av[i] = bf16r(in[(ag * 4 + i) * ldin + k]);
+    for (int j = 0; j < 8; ++j) wv[j] = bf16r(W[k * NHID + og * 8 + j]);
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 8; ++j) acc[i][j] = fmaf(av[i], wv[j], acc[i][j]);
+  }
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 8; ++j) {
+      const float z = acc[i][j] + b[og * 8 + j];
+      zout[(ag * 4 + i) * NHID + og * 8 + j] = z;
+      hout[(ag * 4 + i) * NHID + og * 8 + j] = silu(z);
+    }
+}
+
+__global__ __launch_bounds__(NT) void forward_kernel(const float* __restrict__ P, const float* __restrict__ x, int n,
+                                                     float* __restrict__ y, float* __restrict__ act) {
+  __shared__ float sx[TILE * NIN];
+  __shared__ float sz[TILE * NHID];
+  __shared__ float sh1[TILE * NHID];
+  __shared__ float sh2[TILE * NHID];
+  const int t0 = blockIdx.x * TILE;
+  const int m = min(TILE, n - t0);
+  for (int e = threadIdx.x; e < TILE * NIN; e += NT) sx[e] = (e / NIN) < m ? x[(int64_t)t0 * NIN + e] : 0.0f;
+  __syncthreads();
+  dense_hidden<NIN>(sx, NIN, P + OFF_W1, P + OFF_B1, sz, sh1);
+  __syncthreads();
+  if (act)
+    for (int e = threadIdx.x; e < m * NHID; e += NT) act[(int64_t)(t0 + e / NHID) * 2 * NHID + e % NHID] = sz[e];
+  __syncthreads();
+  dense_hidden<NHID>(sh1, NHID, P + OFF_W2, P + OFF_B2, sz, sh2);
+  __syncthreads();
+  if (act)
+    for (int e = threadIdx.x; e < m * NHID; e += NT)
+      act[(int64_t)(t0 + e / NHID) * 2 * NHID + NHID + e % NHID] = sz[e];
+  for (int e = threadIdx.x; e < m * NOUT; e += NT) {
+    const int a = e / NOUT, o = e % NOUT;
+    float s = 0.0f;
+    for (int k = 0; k < NHID; ++k) s = fmaf(bf16r(sh2[a * NHID + k]), bf16r(P[OFF_W3 + k * NOUT + o]), s);
+    y[(int64_t)(t0 + a) * NOUT + o] = s + P[OFF_B3 + o];
+  }
+}
+
+// partial gradients of sum(dy . y) for one 64-atom tile into work[tile][NPAR]
+__global__ __launch_bounds__(NT) void backward_kernel(const float* __restrict__ P, const float* __restrict__ x,
+                                                      const float* __restrict__ act, const float* __restrict__ dy,
+                                                      int n, float* __restrict__ work) {
+  __shared__ float sx[TILE * NIN];
+  __shared__ float sa[TILE * NHID];   // h1, later dz1
+  __shared__ float sb[TILE * NHID];   // h2, later dz2
+  __shared__ float sdy[TILE * NOUT];
+  float* g = work + (int64_t)blockIdx.x * NPAR;
+  const int t0 = blockIdx.x * TILE;
+  const int m = min(TILE, n - t0);
+  for (int e = threadIdx.x; e < TILE * NIN; e += NT) sx[e] = (e / NIN) < m ? x[(int64_t)t0 * NIN + e] : 0.0f;
+  for (int e = threadIdx.x; e < TILE * NHID; e += NT) {
+    const int a = e / NHID, k = e % NHID;
+    sa[e] = a < m ? silu(act[(int64_t)(t0 + a) * 2 * NHID + k]) : 0.0f;
+    sb[e] = a < m ? silu(act[(int64_t)(t0 + a) * 2 * NHID + NHID + k]) : 0.0f;
+  }
+  for (int e = threadIdx.x; e < TILE * NOUT; e += NT) sdy[e] = (e / NOUT) < m ? dy[(int64_t)t0 * NOUT + e] : 0.0f;
+  __syncthreads();
+  // dW3 = h2^T dy, db3 = sum dy
+  for (int e = threadIdx.x; e < NHID * NOUT + NOUT; e += NT) {
+    float s = 0.0f;
+    if (e < NHID * NOUT) {
+      const int k = e / NOUT, o = e % NOUT;
+      for (int a = 0; a < TILE; ++a) s = fmaf(bf16r(sb[a * NHID + k]), bf16r(sdy[a * NOUT + o]), s);
+      g[OFF_W3 + e] = s;
+    } else {
+      const int o = e - NHID * NOUT;
+      for (int a = 0; a < TILE; ++a) s += sdy[a * NOUT + o];
+      g[OFF_B3 + o] = s;
+    }
+  }
+  __syncthreads();
+  // dz2 = (dy W3^T) * silu'(z2)   (in place of h2)
+  float tmp[TILE * NHID / NT];
+  for (int r = 0, e = threadIdx.x; e < TILE * NHID; e += NT, ++r) {
+    const int a = e / NHID, k = e % NHID;
+    float s = 0.0f;
+    for (int o = 0; o < NOUT; ++o) s = fmaf(bf16r(sdy[a * NOUT + o]), bf16r(P[OFF_W3 + k * NOUT + o]), s);
+    tmp[r] = a < m ? s * dsilu(act[(int64_t)(t0 + a) * 2 * NHID + NHID + k]) : 0.0f;
+  }
+  // dW2 needs h1 and dz2; h2 is no longer needed
+  __syncthreads();
+  for (int r = 0, e = threadIdx.x; e < TILE * NHID; e += NT, ++r) sb[e] = tmp[r];
+  __syncthreads();
+  // dW2[k][j] = sum_a h1[a][k] dz2[a][j] ; db2 = sum dz2
+  for (int e = threadIdx.x; e < NHID * NHID; e += NT) {
+    const int k = e / NHID, j = e % NHID;
+    float s = 0.0f;
+    for (int a = 0; a < TILE; ++a) s = fmaf(bf16r(sa[a * NHID + k]), bf16r(sb[a * NHID + j]), s);
+    g[OFF_W2 + e] = s;
+  }
+  for (int j = threadIdx.x; j < NHID; j += NT) {
+    float s = 0.0f;
+    for (int a = 0; a < TILE; ++a) s += sb[a * NHID + j];
+    g[OFF_B2 + j] = s;
+  }
+  // dz1 = (dz2 W2^T) * silu'(z1)
+  for (int r = 0, e = threadIdx.x; e < TILE * NHID; e += NT, ++r) {
+    const int a = e / NHID, k = e % NHID;
+    float s = 0.0f;
+    for (int j = 0; j < NHID; ++j) s = fmaf(bf16r(sb[a * NHID + j]), bf16r(P[OFF_W2 + k * NHID + j]), s);
+    tmp[r] = a < m ? s * dsilu(act[(int64_t)(t0 + a) * 2 * NHID + k]) : 0.0f;
+  }
+  __syncthreads();
+  for (int r = 0, e = threadIdx.x; e < TILE * NHID; e += NT, ++r) sa[e] = tmp[r];
+  __syncthreads();
+  // dW1[i][k] = sum_a x[a][i] dz1[a][k] ; db1 = sum dz1
+  for (int e = threadIdx.x; e < NIN * NHID; e += NT) {
+    const int i = e / NHID, k = e % NHID;
+    float s = 0.0f;
+    for (int a = 0; a < TILE; ++a) s = fmaf(bf16r(sx[a * NIN + i]), bf16r(sa[a * NHID + k]), s);
+    g[OFF_W1 + e] = s;
+  }
+  for (int k = threadIdx.x; k < NHID; k += NT) {
+    float s = 0.0f;
+    for (int a = 0; a < TILE; ++a) s += sa[a * NHID + k];
+    g[OFF_B1 + k] = s;
+  }
+}
+
+__global__ __launch_bounds__(NT) void reduce_tiles_kernel(const float* __restrict__ work, int n_tiles, int width,
+                                                          float* __restrict__ out) {
+  const int p = blockIdx.x * NT + threadIdx.x;
+  if (p >= width) return;
+  float s = 0.0f;
+  for (int t = 0; t < n_tiles; ++t) s += work[(int64_t)t * width + p];
+  out[p] = s;
+}
+
+// loss = mean (y - t)^2 ; dy = 2 (y - t) / (n * 9); per-block partial losses in work
+__global__ __launch_bounds__(NT) void mse_kernel(const float* __restrict__ y, const float* __restrict__ t, int count,
+                                                 float* __restrict__ dy, float* __restrict__ work) {
+  __shared__ float red[NT];
+  const int e = blockIdx.x * NT + threadIdx.x;
+  float d = 0.0f;
+  if (e < count) {
+    d = y[e] - t[e];
+    dy[e] = 2.0f * d / (float)count;
+  }
+  red[threadIdx.x] = d * d;
+  __syncthreads();
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) work[blockIdx.x] = red[0];
+}
+
+__global__ void mse_finish_kernel(const float* __restrict__ work, int nb, int count, float* __restrict__ loss) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    float s = 0.0f;
+    for (int b = 0; b < nb; ++b) s += work[b];
+    loss[0] = s / (float)count;
+  }
+}
+
+__global__ __launch_bounds__(NT) void adam_kernel(float* __restrict__ w, const float* __restrict__ g,
+                                                  float* __restrict__ m, float* __restrict__ v, int count, float lr,
+                                                  float b1, float b2, float eps, float c1, float c2) {
+  const int p = blockIdx.x * NT + threadIdx.x;
+  if (p >= count) return;
+  const float gp = g[p];
+  const float mp = b1 * m[p] + (1.0f - b1) * gp;
+  const float vp = b2 * v[p] + (1.0f - b2) * gp * gp;
+  m[p] = mp;
+  v[p] = vp;
+  w[p] -= lr * (mp / c1) / (sqrtf(vp / c2) + eps);
+}
+
+__global__ __launch_bounds__(NT) void gather_kernel_f(const float* __restrict__ src, const int32_t* __restrict__ idx,
+                                                      int n, int width, float* __restrict__ dst) {
+  const int e = blockIdx.x * NT + threadIdx.x;
+  if (e >= n * width) return;
+  const int i = e / width, k = e % width;
+  dst[e] = src[(int64_t)idx[i] * width + k];
+}
+
+// mean and standard deviation of each column (two passes, fixed order)
+__global__ __launch_bounds__(NT) void moments_kernel(const double* __restrict__ x, const int32_t* __restrict__ idx,
+                                                     int n, int width, float* __restrict__ out) {
+  __shared__ double red[NT];
+  const int k = blockIdx.x;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += NT) s += x[(int64_t)(idx ? idx[i] : i) * width + k];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int st = NT / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  const double mean = red[0] / n;
+  __syncthreads();
+  double q = 0.0;
+  for (int i = threadIdx.x; i < n; i += NT) {
+    const double d = x[(int64_t)(idx ? idx[i] : i) * width + k] - mean;
+    q += d * d;
+  }
+  red[threadIdx.x] = q;
+  __syncthreads();
+  for (int st = NT / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[k] = (float)mean;
+    const double sd = sqrt(red[0] / n);
+    out[width + k] = (float)(sd > 1e-12 ? sd : 1.0);
+  }
+}
+
+// Z_loc = R^T Z R for the listed atoms (training targets), as FP64
+__global__ __launch_bounds__(NT) void to_local_kernel(int n, const int32_t* __restrict__ idx,
+                                                      const double* __restrict__ frames,
+                                                      const double* __restrict__ born, double* __restrict__ out) {
+  const int i = blockIdx.x * NT + threadIdx.x;
+  if (i >= n) return;
+  const int64_t a = idx ? idx[i] : i;
+  const double* R = frames + a * 9;
+  const double* Z = born + a * 9;
+  for (int p = 0; p < 3; ++p)
+    for (int q = 0; q < 3; ++q) {
+      double s = 0.0;
+      for (int j = 0; j < 3; ++j)
+        for (int k = 0; k < 3; ++k) s += R[j * 3 + p] * Z[j * 3 + k] * R[k * 3 + q];
+      out[(int64_t)i * 9 + p * 3 + q] = s;
+    }
+}
+
+// ensemble combination: per atom, member outputs y_m -> Z_m = R (y y_scale + y_mean) R^T;
+// mean over members into born, largest per-component standard deviation into std
+__global__ __launch_bounds__(NT) void combine_kernel(int n_atoms, const int8_t* __restrict__ species,
+                                                     const int32_t* __restrict__ pos_in_species,
+                                                     const int32_t* __restrict__ n_species,
+                                                     const float* __restrict__ ybuf, const float* __restrict__ norm,
+                                                     const double* __restrict__ frames, double* __restrict__ born,
+                                                     double* __restrict__ std) {
+  const int a = blockIdx.x * NT + threadIdx.x;
+  if (a >= n_atoms) return;
+  const int s = species[a];
+  const int i = pos_in_species[a];
+  const float* nm = norm + s * CAVDFTB_SG_N_NORM;
+  const double* R = frames + (int64_t)a * 9;
+  double mean[9], m2[9];
+  for (int e = 0; e < 9; ++e) mean[e] = m2[e] = 0.0;
+  const int64_t base_s = s == 0 ? 0 : (int64_t)CAVDFTB_SG_MEMBERS * n_species[0] * NOUT;
+  for (int mb = 0; mb < CAVDFTB_SG_MEMBERS; ++mb) {
+    const float* y = ybuf + base_s + ((int64_t)mb * n_species[s] + i) * NOUT;
+    double zl[9];
+    for (int e = 0; e < 9; ++e) zl[e] = (double)y[e] * nm[2 * NIN + NOUT + e] + nm[2 * NIN + e];
+    for (int p = 0; p < 3; ++p)
+      for (int q = 0; q < 3; ++q) {
+        double v = 0.0;
+        for (int j = 0; j < 3; ++j)
+          for (int k = 0; k < 3; ++k) v += R[p * 3 + j] * zl[j * 3 + k] * R[q * 3 + k];
+        const double d = v - mean[p * 3 + q];  // Welford
+        mean[p * 3 + q] += d / (mb + 1);
+        m2[p * 3 + q] += d * (v - mean[p * 3 + q]);
+      }
+  }
+  double smax = 0.0;
+  for (int e = 0; e < 9; ++e) {
+    born[(int64_t)a * 9 + e] = mean[e];
+    smax = fmax(smax, sqrt(m2[e] / CAVDFTB_SG_MEMBERS));
+  }
+  if (std) std[a] = smax;
+}
+
+// per unit: acoustic-sum projection of the ensemble mean and the fallback flag
+__global__ __launch_bounds__(NT) void asr_flag_kernel(int n_units, const int32_t* __restrict__ unit_off,
+                                                      double* __restrict__ born, const double* __restrict__ std,
+                                                      double thr, int32_t* __restrict__ flag,
+                                                      unsigned long long* __restrict__ n_flagged) {
+  const int u = blockIdx.x * NT + threadIdx.x;
+  if (u >= n_units) return;
+  const int a0 = unit_off[u], a1 = unit_off[u + 1];
+  double s[9];
+  for (int e = 0; e < 9; ++e) s[e] = 0.0;
+  double smax = 0.0;
+  for (int a = a0; a < a1; ++a) {
+    for (int e = 0; e < 9; ++e) s[e] += born[(int64_t)a * 9 + e];
+    smax = fmax(smax, std[a]);
+  }
+  for (int a = a0; a < a1; ++a)
+    for (int e = 0; e < 9; ++e) born[(int64_t)a * 9 + e] -= s[e] / (a1 - a0);
+  flag[u] = smax > thr ? 1 : 0;
+  if (n_flagged && smax > thr) atomicAdd(n_flagged, 1ull);
+}
+
+__global__ __launch_bounds__(NT) void zpol_from_born_kernel(int n, const double* __restrict__ born, double e0,
+                                                            double e1, double e2, double* __restrict__ zp) {
+  const int a = blockIdx.x * NT + threadIdx.x;
+  if (a >= n) return;
+  for (int b = 0; b < 3; ++b)
+    zp[a * 3 + b] = e0 * born[(int64_t)a * 9 + b] + e1 * born[(int64_t)a * 9 + 3 + b] + e2 * born[(int64_t)a * 9 + 6 + b];
+}
+
+// compact the displaced-job list of the flagged units of one bucket, in unit
+// order (one workgroup; block scan over chunks of NT units)
+__global__ __launch_bounds__(NT) void fd_compact_kernel(int n_units_b, const int32_t* __restrict__ units_b,
+                                                        const int32_t* __restrict__ unit_off,
+                                                        const int32_t* __restrict__ flag, int32_t* __restrict__ job_unit,
+                                                        int32_t* __restrict__ job_disp, int32_t* __restrict__ job0,
+                                                        int32_t* __restrict__ n_jobs) {
+  __shared__ int scan[NT];
+  __shared__ int base;
+  if (threadIdx.x == 0) base = 0;
+  __syncthreads();
+  for (int c0 = 0; c0 < n_units_b; c0 += NT) {
+    const int w = c0 + threadIdx.x;
+    int cnt = 0, u = -1, na = 0;
+    if (w < n_units_b) {
+      u = units_b[w];
+      na = unit_off[u + 1] - unit_off[u];
+      cnt = flag[u] ? 6 * na : 0;
+    }
+    scan[threadIdx.x] = cnt;
+    __syncthreads();
+    for (int d = 1; d < NT; d <<= 1) {  // inclusive Hillis-Steele scan
+      const int v = (int)threadIdx.x >= d ? scan[threadIdx.x - d] : 0;
+      __syncthreads();
+      scan[threadIdx.x] += v;
+      __syncthreads();
+    }
+    const int start = base + scan[threadIdx.x] - cnt;
+    if (w < n_units_b) {
+      job0[w] = cnt ? start : -1;
+      for (int j = 0; j < cnt; ++j) {
+        job_unit[start + j] = u;
+        job_disp[start + j] = j;  // (atom*3 + dir)*2 + sign, in order
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == NT - 1) base += scan[NT - 1];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) n_jobs[0] = base;
+}
+
+inline int nb(int64_t n) { return (int)((n + NT - 1) / NT); }
+
+}  // namespace
+
+hipError_t launch_sg_features(int n_atoms, const int32_t* atom_unit, const int32_t* unit_off, const int8_t* species,
+                              const double* pos, double* feat, double* frames, hipStream_t s) {
+  hipLaunchKernelGGL(features_kernel, dim3(nb(n_atoms)), dim3(NT), 0, s, n_atoms, atom_unit, unit_off, species, pos,
+                     feat, frames);
+  return hipGetLastError();
+}
+hipError_t launch_sg_prep(int n, int width, const int32_t* idx, const double* v, const float* norm, float* x,
+                          hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(prep_kernel, dim3(nb((int64_t)n * width)), dim3(NT), 0, s, n, width, idx, v, norm, x);
+  return hipGetLastError();
+}
+hipError_t launch_sg_forward(const float* P, const float* x, int n, float* y, float* act, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(forward_kernel, dim3((n + TILE - 1) / TILE), dim3(NT), 0, s, P, x, n, y, act);
+  return hipGetLastError();
+}
+hipError_t launch_sg_backward(const float* P, const float* x, const float* act, const float* dy, int n, float* grad,
+                              float* work, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int tiles = (n + TILE - 1) / TILE;
+  hipLaunchKernelGGL(backward_kernel, dim3(tiles), dim3(NT), 0, s, P, x, act, dy, n, work);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(reduce_tiles_kernel, dim3(nb(NPAR)), dim3(NT), 0, s, work, tiles, NPAR, grad);
+  return hipGetLastError();
+}
+hipError_t launch_sg_mse(const float* y, const float* t, int count, float* dy, float* loss, float* work,
+                         hipStream_t s) {
+  const int blocks = nb(count);
+  hipLaunchKernelGGL(mse_kernel, dim3(blocks), dim3(NT), 0, s, y, t, count, dy, work);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(mse_finish_kernel, dim3(1), dim3(64), 0, s, work, blocks, count, loss);
+  return hipGetLastError();
+}
+hipError_t launch_sg_adam(float* w, const float* g, float* m, float* v, int count, float lr, float b1, float b2,
+                          float eps, int step, hipStream_t s) {
+  const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+  hipLaunchKernelGGL(adam_kernel, dim3(nb(count)), dim3(NT), 0, s, w, g, m, v, count, lr, b1, b2, eps, c1, c2);
+  return hipGetLastError();
+}
+hipError_t launch_sg_gather(const float* src, const int32_t* idx, int n, int width, float* dst, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(gather_kernel_f, dim3(nb((int64_t)n * width)), dim3(NT), 0, s, src, idx, n, width, dst);
+  return hipGetLastError();
+}
+hipError_t launch_sg_moments(const double* x, const int32_t* idx, int n, int width, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(moments_kernel, dim3(width), dim3(NT), 0, s, x, idx, n, width, out);
+  return hipGetLastError();
+}
+hipError_t launch_sg_to_local(int n, const int32_t* idx, const double* frames, const double* born, double* out,
+                              hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(to_local_kernel, dim3(nb(n)), dim3(NT), 0, s, n, idx, frames, born, out);
+  return hipGetLastError();
+}
+hipError_t launch_sg_combine(int n_atoms, const int8_t* species, const int32_t* pos_in_species,
+                             const int32_t* n_species, const float* ybuf, const float* norm, const double* frames,
+                             double* born, double* std, hipStream_t s) {
+  hipLaunchKernelGGL(combine_kernel, dim3(nb(n_atoms)), dim3(NT), 0, s, n_atoms, species, pos_in_species, n_species,
+                     ybuf, norm, frames, born, std);
+  return hipGetLastError();
+}
+hipError_t launch_sg_asr_flag(int n_units, const int32_t* unit_off, double* born, const double* std, double thr,
+                              int32_t* flag, unsigned long long* n_flagged, hipStream_t s) {
+  hipLaunchKernelGGL(asr_flag_kernel, dim3(nb(n_units)), dim3(NT), 0, s, n_units, unit_off, born, std, thr, flag,
+                     n_flagged);
+  return hipGetLastError();
+}
+hipError_t launch_fd_compact(int n_units_b, const int32_t* units_b, const int32_t* unit_off, const int32_t* flag,
+                             int32_t* job_unit, int32_t* job_disp, int32_t* job0, int32_t* n_jobs, hipStream_t s) {
+  hipLaunchKernelGGL(fd_compact_kernel, dim3(1), dim3(NT), 0, s, n_units_b, units_b, unit_off, flag, job_unit, job_disp,
+                     job0, n_jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_zpol_from_born(int n, const double* born, const double pol[3], double* zp, hipStream_t s) {
+  hipLaunchKernelGGL(zpol_from_born_kernel, dim3(nb(n)), dim3(NT), 0, s, n, born, pol[0], pol[1], pol[2], zp);
+  return hipGetLastError();
+}
+
+}  // namespace cavdftb

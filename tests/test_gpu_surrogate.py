@@ -1,0 +1,188 @@
+"""GPU tests of the learned Born-charge surrogate against the surrogate oracle.
+
+Bars: descriptors and frames abs 1e-12; network outputs and gradients within
+1e-3 of the largest value of each tensor (BF16 operands on both sides; the
+oracle accumulates in FP64, the kernels in FP32, so a BF16 rounding can flip);
+Born tensors through the full surrogate path within 1e-3 of max |Z|; the
+fallback path equals exact finite differences bitwise.
+"""
+import numpy as np
+import pytest
+
+from cavgen import make_params, make_system
+from oracle import surrogate as osg
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2512_03277_amd as cd  # noqa: E402
+from paper_2512_03277_amd import binding as B  # noqa: E402
+from paper_2512_03277_amd import surrogate as dsg  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def params():
+    return make_params()
+
+
+def _t(a, dtype=torch.float64):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device=DEV)
+
+
+def test_features_and_frames_parity(params):
+    s = make_system(5, n_units=10)
+    ctx = cd.context_from_system(params, s)
+    feat = torch.empty(ctx.n_atoms, 32, dtype=torch.float64, device=DEV)
+    fr = torch.empty(ctx.n_atoms, 9, dtype=torch.float64, device=DEV)
+    ctx.sg_features(_t(s["pos"]), feat, fr)
+    ctx.sync()
+    off = s["unit_off"]
+    for u in range(ctx.n_units):
+        a0, a1 = off[u], off[u + 1]
+        G = osg.descriptors(s["species"][a0:a1], s["pos"][a0:a1])
+        R = osg.local_frames(s["species"][a0:a1], s["pos"][a0:a1])
+        assert np.max(np.abs(feat[a0:a1].cpu().numpy() - G)) < 1e-12
+        assert np.max(np.abs(fr[a0:a1].cpu().numpy().reshape(-1, 3, 3) - R)) < 1e-12
+
+
+def _close(a, b, rel=1e-3):
+    return np.max(np.abs(a - b)) <= rel * np.max(np.abs(b))
+
+
+def test_network_forward_backward_parity():
+    rng = np.random.default_rng(0)
+    th = osg.init_params(rng)
+    n = 150                                           # two full tiles and a ragged one
+    x = rng.normal(size=(n, 32))
+    dy = rng.normal(size=(n, 9)) * 0.1
+    y_ref, cache = osg.forward(th, x, emulate_bf16=True)
+    g_ref = osg.backward(th, cache, dy, emulate_bf16=True)
+    w = _t(th, torch.float32)
+    xt = _t(x, torch.float32)
+    y = torch.empty(n, 9, dtype=torch.float32, device=DEV)
+    act = torch.empty(n, 256, dtype=torch.float32, device=DEV)
+    B.sg_forward(w, xt, n, y, act)
+    grad = torch.empty(osg.N_PARAM, dtype=torch.float32, device=DEV)
+    work = torch.empty(3, osg.N_PARAM, dtype=torch.float32, device=DEV)
+    B.sg_backward(w, xt, act, _t(dy, torch.float32), n, grad, work)
+    torch.cuda.synchronize()
+    assert _close(y.cpu().numpy().astype(np.float64), y_ref)
+    assert np.allclose(act[:, :128].cpu().numpy(), cache["z1"], rtol=0, atol=2e-3 * np.abs(cache["z1"]).max())
+    g = grad.cpu().numpy().astype(np.float64)
+    gr, gg = osg.unpack(g_ref), osg.unpack(g)
+    for name in gr:
+        assert _close(gg[name], gr[name]), name
+
+
+def test_mse_and_adam_parity():
+    rng = np.random.default_rng(1)
+    y = rng.normal(size=(70, 9))
+    t = rng.normal(size=(70, 9))
+    loss_ref, dy_ref = osg.mse_and_grad(y, t)
+    dy = torch.empty(70 * 9, dtype=torch.float32, device=DEV)
+    loss = torch.empty(1, dtype=torch.float32, device=DEV)
+    work = torch.empty(3, dtype=torch.float32, device=DEV)
+    B.sg_mse(_t(y, torch.float32), _t(t, torch.float32), 630, dy, loss, work)
+    th = rng.normal(size=500)
+    g = rng.normal(size=500)
+    m0, v0 = rng.normal(size=500) * 0.01, np.abs(rng.normal(size=500)) * 0.01
+    ref, mref, vref = osg.adam_step(th, g, m0, v0, 3, lr=1e-3)
+    w, m, v = _t(th, torch.float32), _t(m0, torch.float32), _t(v0, torch.float32)
+    B.sg_adam(w, _t(g, torch.float32), m, v, 500, 1e-3, 0.9, 0.999, 1e-8, 3)
+    torch.cuda.synchronize()
+    assert float(loss) == pytest.approx(loss_ref, rel=1e-5)
+    assert np.allclose(dy.cpu().numpy().reshape(70, 9), dy_ref, rtol=1e-5, atol=1e-9)
+    assert np.allclose(w.cpu().numpy(), ref, rtol=1e-5, atol=1e-7)
+    assert np.allclose(m.cpu().numpy(), mref, rtol=1e-5, atol=1e-9)
+
+
+def _random_ensemble(seed):
+    rng = np.random.default_rng(seed)
+    nets = [[osg.init_params(rng) for _ in range(4)] for _ in range(2)]
+    norms = []
+    for _ in range(2):
+        norms.append({"x_mean": rng.uniform(0, 1, 32), "x_std": rng.uniform(0.5, 2, 32),
+                      "y_mean": rng.normal(0, 0.2, 9), "y_scale": rng.uniform(0.05, 0.2, 9)})
+    P = np.stack([np.stack(nets[s]) for s in (0, 1)]).astype(np.float32)
+    N = np.stack([np.concatenate([nm["x_mean"], nm["x_std"], nm["y_mean"], nm["y_scale"]]) for nm in norms])
+    return nets, norms, _t(P, torch.float32), _t(N.astype(np.float32), torch.float32)
+
+
+def test_surrogate_born_matches_oracle_prediction(params):
+    s = make_system(5, n_units=8)
+    nets, norms, P, N = _random_ensemble(2)
+    # the oracle works on the FP32-rounded weights and normalisation the GPU receives
+    nets = [[np.asarray(P[sp, m].cpu().numpy(), dtype=np.float64) for m in range(4)] for sp in (0, 1)]
+    Nh = N.cpu().numpy().astype(np.float64)
+    norms = [{"x_mean": Nh[sp, :32], "x_std": Nh[sp, 32:64], "y_mean": Nh[sp, 64:73], "y_scale": Nh[sp, 73:82]}
+             for sp in (0, 1)]
+    ctx = cd.context_from_system(params, s)
+    ctx.set_scc(1e-10, 300, 0.2)
+    ctx.set_surrogate(P.view(-1), N.view(-1), 1e9)
+    Z = torch.empty(ctx.n_atoms, 9, dtype=torch.float64, device=DEV)
+    std = torch.empty(ctx.n_atoms, dtype=torch.float64, device=DEV)
+    st = torch.zeros(ctx.n_units, dtype=torch.int32, device=DEV)
+    ctx.born_charges(_t(s["pos"]), cd.BORN_SURROGATE, 1e-3, Z, st, std)
+    ctx.sync()
+    Zg = Z.cpu().numpy().reshape(-1, 3, 3)
+    sg = std.cpu().numpy()
+    off = s["unit_off"]
+    for u in range(ctx.n_units):
+        a0, a1 = off[u], off[u + 1]
+        zr, sr = osg.predict_unit(s["species"][a0:a1], s["pos"][a0:a1], nets, norms, emulate_bf16=True)
+        assert np.max(np.abs(Zg[a0:a1] - zr)) <= 1e-3 * np.max(np.abs(zr))
+        assert np.max(np.abs(Zg[a0:a1].sum(0))) < 1e-12            # acoustic sum rule exactly
+        assert np.max(np.abs(sg[a0:a1] - sr.reshape(-1, 9).max(1))) <= 1e-3 * np.max(np.abs(zr))
+    assert ctx.read_counters()["surrogate_fallback_units"] == 0
+
+
+def test_fallback_reproduces_exact_finite_differences(params):
+    s = make_system(5, n_units=6)
+    _, _, P, N = _random_ensemble(3)
+    ctx = cd.context_from_system(params, s)
+    ctx.set_scc(1e-12, 300, 0.2)
+    ctx.set_surrogate(P.view(-1), N.view(-1), 0.0)      # threshold 0: every unit falls back
+    pos = _t(s["pos"])
+    Zs = torch.empty(ctx.n_atoms, 9, dtype=torch.float64, device=DEV)
+    Zf = torch.empty_like(Zs)
+    ctx.born_charges(pos, cd.BORN_SURROGATE, 1e-3, Zs)
+    ctx.reset_warm_start()
+    ctx.born_charges(pos, cd.BORN_SURROGATE, 1e-3, Zs)
+    ctx.reset_warm_start()
+    ctx.born_charges(pos, cd.BORN_FD, 1e-3, Zf)
+    ctx.sync()
+    assert torch.equal(Zs, Zf)
+    assert ctx.read_counters()["surrogate_fallback_units"] == 2 * ctx.n_units
+
+
+def test_surrogate_md_steps_run_and_stay_finite(params):
+    s = make_system(5, n_units=12)
+    _, _, P, N = _random_ensemble(4)
+    ctx = cd.context_from_system(params, s)
+    ctx.set_scc(1e-8, 200, 0.2)
+    ctx.set_surrogate(P.view(-1), N.view(-1), 0.3)
+    masses = params["mass"][s["species"]]
+    r, p = _t(s["pos"]), _t(s["vel"] * masses[:, None])
+    qm = torch.zeros(ctx.n_modes, dtype=torch.float64, device=DEV)
+    pm = torch.zeros_like(qm)
+    obs = torch.zeros(5, cd.N_OBS, dtype=torch.float64, device=DEV)
+    ctx.init_photons(r, qm, pm)
+    ctx.step(r, p, qm, pm, 5, s["dt"], cd.BORN_SURROGATE, 1e-3, obs)
+    assert ctx.sync() == 0
+    assert torch.isfinite(r).all() and torch.isfinite(obs).all()
+
+
+def test_trained_network_beats_the_mulliken_replacement(params):
+    # the gain of the learned part: on held-out snapshots (later in time) the
+    # trained ensemble is much closer to the exact Born charges than Z = Q I
+    data = dsg.build_training_set(params, n_units=48, n_train=5, n_val=2, stride=8, n_sub=2)
+    fe, ta = data["train"]
+    psg, nsg, losses = dsg.train_ensemble(fe, ta, epochs=12, batch=256)
+    assert all(np.isfinite(v) for v in losses.values())
+    ev = dsg.evaluate(psg, nsg, params, data["system"], data["val_pos"], data["val_born"])
+    assert ev["rmse_surrogate"] < 0.5 * ev["rmse_mulliken"], ev
