@@ -192,7 +192,10 @@ int cavdftb_cavity_forces(cavdftb_ctx* ctx, const double* mu_pol, const double* 
  *   sg_adam     Adam (Kingma & Ba) on count parameters, step = 1, 2, ...
  *   sg_gather   dst[i][:] = src[idx[i]][:]  (FP32 rows of width values)
  *   sg_moments  out = [mean(width) | std(width)] of the FP64 rows idx (or all n)
- *   sg_to_local out[i] = R^T Z R for atoms idx[i] (training targets in the local frame, FP64) */
+ *   sg_to_local out[i] = R^T Z R - Q I for atoms idx[i] (training targets: the correction to the
+ *               Mulliken replacement in the local frame, FP64; charges may be NULL for R^T Z R)
+ * In surrogate mode the network output is that correction: Z = Q_A I + R dZ_loc R^T
+ * with the Mulliken charges Q_A of the same SCC evaluation. */
 int cavdftb_set_surrogate(cavdftb_ctx* ctx, const float* params, const float* norm, double std_threshold);
 int cavdftb_sg_features(cavdftb_ctx* ctx, const double* pos, double* feat, double* frames);
 int cavdftb_sg_prep(const double* v, const int32_t* idx, int32_t n, int32_t width, const float* norm, float* x,
@@ -206,8 +209,8 @@ int cavdftb_sg_adam(float* params, const float* grad, float* m, float* v, int32_
                     float beta2, float eps, int32_t step, void* hip_stream);
 int cavdftb_sg_gather(const float* src, const int32_t* idx, int32_t n, int32_t width, float* dst, void* hip_stream);
 int cavdftb_sg_moments(const double* x, const int32_t* idx, int32_t n, int32_t width, float* out, void* hip_stream);
-int cavdftb_sg_to_local(const double* frames, const double* born, const int32_t* idx, int32_t n, double* out,
-                        void* hip_stream);
+int cavdftb_sg_to_local(const double* frames, const double* born, const double* charges, const int32_t* idx,
+                        int32_t n, double* out, void* hip_stream);
 
 /* Photon start at frozen matter (Step 0 reading): q_m = -lambda_m F_m/omega_m,
  * p_m = 0, with F from one SCC evaluation at r (device). */

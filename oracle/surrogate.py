@@ -16,11 +16,14 @@ one; readings listed in the design doc):
                of that O and its two nearest H; e3 = e1 x e2.  R = [e1 e2 e3].
   network      per central species, per member: 32 -> 128 SiLU -> 128 SiLU -> 9,
                on standardised inputs x = (G - mu_x) / sd_x; the 9 outputs y
-               give Z_loc = (y * y_scale + y_mean) reshaped 3 x 3 (row-major).
-  prediction   Z_lab = R Z_loc R^T per member; ensemble mean and per-component
-               standard deviation; then per unit Z_A -= (1/N_a) sum_B Z_B
-               (acoustic sum rule).  A unit whose largest standard deviation
-               exceeds the threshold is recomputed by exact finite differences.
+               give dZ_loc = (y * y_scale + y_mean) reshaped 3 x 3 (row-major),
+               the correction to the paper's Mulliken replacement Q_A I in the
+               atom's frame (the charge-flux part the replacement misses).
+  prediction   Z = Q_A I + R dZ_loc R^T per member, with the exact Mulliken
+               charge Q_A of the SCC; ensemble mean and per-component standard
+               deviation; then per unit Z_A -= (1/N_a) sum_B Z_B (acoustic sum
+               rule).  A unit whose largest standard deviation exceeds the
+               threshold is recomputed by exact finite differences.
   training     mean squared error on the standardised local-frame targets,
                Adam with FP32 master weights, BF16 operands at every matrix
                product (round to nearest even), FP32 accumulation.
@@ -197,11 +200,11 @@ def adam_step(theta, grad, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
 
 
 # ---------------------------------------------------------------- prediction
-def predict_unit(species, pos, nets, norms, emulate_bf16=False):
+def predict_unit(species, pos, nets, norms, charges, emulate_bf16=False):
     """nets[s] = list of flat parameter vectors (members) for species s;
-    norms[s] = dict(x_mean, x_std, y_mean, y_scale).  Returns the ensemble mean
-    Born tensors after the acoustic-sum projection (Na,3,3) and the
-    per-atom per-component ensemble standard deviation (Na,3,3)."""
+    norms[s] = dict(x_mean, x_std, y_mean, y_scale); charges = Mulliken Q_A.
+    Returns the ensemble mean Born tensors after the acoustic-sum projection
+    (Na,3,3) and the per-atom per-component ensemble standard deviation."""
     species = np.asarray(species)
     G = descriptors(species, pos)
     R = local_frames(species, pos)
@@ -218,12 +221,17 @@ def predict_unit(species, pos, nets, norms, emulate_bf16=False):
             y, _ = forward(nets[s][mb], x, emulate_bf16)
             zl = (y * nm["y_scale"] + nm["y_mean"]).reshape(-1, 3, 3)
             Zm[mb, idx] = np.einsum("nij,njk,nlk->nil", R[idx], zl, R[idx])
+    Zm = Zm + np.asarray(charges)[None, :, None, None] * np.eye(3)[None, None]
     mean = Zm.mean(0)
     std = Zm.std(0)
     mean = mean - mean.mean(0, keepdims=True)
     return mean, std
 
 
-def to_local(Z, R):
-    """Z_loc = R^T Z R (training targets in the atom's frame)."""
-    return np.einsum("nji,njk,nkl->nil", R, Z, R)
+def to_local(Z, R, charges=None):
+    """Training targets in the atom's frame: R^T Z R - Q I (the correction to the
+    Mulliken replacement), or R^T Z R without charges."""
+    zl = np.einsum("nji,njk,nkl->nil", R, Z, R)
+    if charges is not None:
+        zl = zl - np.asarray(charges)[:, None, None] * np.eye(3)[None]
+    return zl

@@ -64,7 +64,7 @@ SYMBOLS = {
                                        ctypes.c_float, _c_i32, _vp]),
     "cavdftb_sg_gather": (ctypes.c_int, [_vp, _vp, _c_i32, _c_i32, _vp, _vp]),
     "cavdftb_sg_moments": (ctypes.c_int, [_vp, _vp, _c_i32, _c_i32, _vp, _vp]),
-    "cavdftb_sg_to_local": (ctypes.c_int, [_vp, _vp, _vp, _c_i32, _vp, _vp]),
+    "cavdftb_sg_to_local": (ctypes.c_int, [_vp, _vp, _vp, _vp, _c_i32, _vp, _vp]),
     "cavdftb_step": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _c_i32, _c_d, _c_i32, _c_d, _vp]),
     "cavdftb_invalidate": (ctypes.c_int, [_vp]),
     "cavdftb_sync": (ctypes.c_int, [_vp, ctypes.POINTER(_c_i32)]),
@@ -318,7 +318,7 @@ def sg_moments(x, idx, n, width, out, stream=None):
                                           _ptr(out, name="out"), _stream_handle(stream)), "sg_moments")
 
 
-def sg_to_local(frames, born, idx, n, out, stream=None):
+def sg_to_local(frames, born, charges, idx, n, out, stream=None):
     _rc(load_library().cavdftb_sg_to_local(_ptr(frames, name="frames"), _ptr(born, name="born"),
-                                           _ptr(idx, name="idx"), int(n), _ptr(out, name="out"),
-                                           _stream_handle(stream)), "sg_to_local")
+                                           _ptr(charges, name="charges"), _ptr(idx, name="idx"), int(n),
+                                           _ptr(out, name="out"), _stream_handle(stream)), "sg_to_local")

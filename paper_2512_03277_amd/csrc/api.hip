@@ -317,7 +317,7 @@ int sg_infer(cavdftb_ctx* c, const double* pos, double* born) {
     ybase += (int64_t)CAVDFTB_SG_MEMBERS * n * CAVDFTB_SG_N_OUT;
   }
   e = launch_sg_combine(c->NA, c->d_species, c->d_pos_in_sp, c->d_n_sp, c->d_sg_y, c->d_sg_norm, c->d_sg_frames,
-                        born, c->d_sg_std, st);
+                        c->d_charges, born, c->d_sg_std, st);
   if (e == hipSuccess)
     e = launch_sg_asr_flag(c->U, c->d_unit_off, born, c->d_sg_std, c->sg_thr, c->d_unit_flag, c->d_counters + 4, st);
   if (e != hipSuccess) return hip_fail(c, e, "surrogate combine");
@@ -779,11 +779,12 @@ int cavdftb_sg_moments(const double* x, const int32_t* idx, int32_t n, int32_t w
                                                                                         : CAVDFTB_EHIP;
 }
 
-int cavdftb_sg_to_local(const double* frames, const double* born, const int32_t* idx, int32_t n, double* out,
-                        void* hip_stream) {
+int cavdftb_sg_to_local(const double* frames, const double* born, const double* charges, const int32_t* idx,
+                        int32_t n, double* out, void* hip_stream) {
   if (!frames || !born || !out || n < 0) return CAVDFTB_EINVAL;
-  return launch_sg_to_local(n, idx, frames, born, out, (hipStream_t)hip_stream) == hipSuccess ? CAVDFTB_OK
-                                                                                             : CAVDFTB_EHIP;
+  return launch_sg_to_local(n, idx, frames, born, charges, out, (hipStream_t)hip_stream) == hipSuccess
+             ? CAVDFTB_OK
+             : CAVDFTB_EHIP;
 }
 
 int cavdftb_init_photons(cavdftb_ctx* ctx, const double* r, double* qm, double* pm) {

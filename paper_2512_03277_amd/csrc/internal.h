@@ -123,11 +123,11 @@ hipError_t launch_sg_adam(float* w, const float* g, float* m, float* v, int coun
                           float eps, int step, hipStream_t s);
 hipError_t launch_sg_gather(const float* src, const int32_t* idx, int n, int width, float* dst, hipStream_t s);
 hipError_t launch_sg_moments(const double* x, const int32_t* idx, int n, int width, float* out, hipStream_t s);
-hipError_t launch_sg_to_local(int n, const int32_t* idx, const double* frames, const double* born, double* out,
-                              hipStream_t s);
+hipError_t launch_sg_to_local(int n, const int32_t* idx, const double* frames, const double* born,
+                              const double* charges, double* out, hipStream_t s);
 hipError_t launch_sg_combine(int n_atoms, const int8_t* species, const int32_t* pos_in_species,
                              const int32_t* n_species, const float* ybuf, const float* norm, const double* frames,
-                             double* born, double* std, hipStream_t s);
+                             const double* charges, double* born, double* std, hipStream_t s);
 hipError_t launch_sg_asr_flag(int n_units, const int32_t* unit_off, double* born, const double* std, double thr,
                               int32_t* flag, unsigned long long* n_flagged, hipStream_t s);
 hipError_t launch_zpol_from_born(int n, const double* born, const double pol[3], double* zp, hipStream_t s);

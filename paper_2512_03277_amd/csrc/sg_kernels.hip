@@ -382,10 +382,11 @@ __global__ __launch_bounds__(NT) void moments_kernel(const double* __restrict__ 
   }
 }
 
-// Z_loc = R^T Z R for the listed atoms (training targets), as FP64
+// training targets: R^T Z R - Q I (Q optional) for the listed atoms, FP64
 __global__ __launch_bounds__(NT) void to_local_kernel(int n, const int32_t* __restrict__ idx,
                                                       const double* __restrict__ frames,
-                                                      const double* __restrict__ born, double* __restrict__ out) {
+                                                      const double* __restrict__ born,
+                                                      const double* __restrict__ charges, double* __restrict__ out) {
   const int i = blockIdx.x * NT + threadIdx.x;
   if (i >= n) return;
   const int64_t a = idx ? idx[i] : i;
@@ -396,17 +397,20 @@ __global__ __launch_bounds__(NT) void to_local_kernel(int n, const int32_t* __re
       double s = 0.0;
       for (int j = 0; j < 3; ++j)
         for (int k = 0; k < 3; ++k) s += R[j * 3 + p] * Z[j * 3 + k] * R[k * 3 + q];
+      if (charges && p == q) s -= charges[a];
       out[(int64_t)i * 9 + p * 3 + q] = s;
     }
 }
 
-// ensemble combination: per atom, member outputs y_m -> Z_m = R (y y_scale + y_mean) R^T;
-// mean over members into born, largest per-component standard deviation into std
+// ensemble combination: per atom, member outputs y_m -> Z_m = Q I + R (y y_scale + y_mean) R^T
+// (Q the Mulliken charge); mean over members into born, largest per-component
+// standard deviation into std
 __global__ __launch_bounds__(NT) void combine_kernel(int n_atoms, const int8_t* __restrict__ species,
                                                      const int32_t* __restrict__ pos_in_species,
                                                      const int32_t* __restrict__ n_species,
                                                      const float* __restrict__ ybuf, const float* __restrict__ norm,
-                                                     const double* __restrict__ frames, double* __restrict__ born,
+                                                     const double* __restrict__ frames,
+                                                     const double* __restrict__ charges, double* __restrict__ born,
                                                      double* __restrict__ std) {
   const int a = blockIdx.x * NT + threadIdx.x;
   if (a >= n_atoms) return;
@@ -432,8 +436,9 @@ __global__ __launch_bounds__(NT) void combine_kernel(int n_atoms, const int8_t* 
       }
   }
   double smax = 0.0;
+  const double qa = charges ? charges[a] : 0.0;
   for (int e = 0; e < 9; ++e) {
-    born[(int64_t)a * 9 + e] = mean[e];
+    born[(int64_t)a * 9 + e] = mean[e] + ((e % 4) == 0 ? qa : 0.0);
     smax = fmax(smax, sqrt(m2[e] / CAVDFTB_SG_MEMBERS));
   }
   if (std) std[a] = smax;
@@ -565,17 +570,17 @@ hipError_t launch_sg_moments(const double* x, const int32_t* idx, int n, int wid
   hipLaunchKernelGGL(moments_kernel, dim3(width), dim3(NT), 0, s, x, idx, n, width, out);
   return hipGetLastError();
 }
-hipError_t launch_sg_to_local(int n, const int32_t* idx, const double* frames, const double* born, double* out,
-                              hipStream_t s) {
+hipError_t launch_sg_to_local(int n, const int32_t* idx, const double* frames, const double* born,
+                              const double* charges, double* out, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(to_local_kernel, dim3(nb(n)), dim3(NT), 0, s, n, idx, frames, born, out);
+  hipLaunchKernelGGL(to_local_kernel, dim3(nb(n)), dim3(NT), 0, s, n, idx, frames, born, charges, out);
   return hipGetLastError();
 }
 hipError_t launch_sg_combine(int n_atoms, const int8_t* species, const int32_t* pos_in_species,
                              const int32_t* n_species, const float* ybuf, const float* norm, const double* frames,
-                             double* born, double* std, hipStream_t s) {
+                             const double* charges, double* born, double* std, hipStream_t s) {
   hipLaunchKernelGGL(combine_kernel, dim3(nb(n_atoms)), dim3(NT), 0, s, n_atoms, species, pos_in_species, n_species,
-                     ybuf, norm, frames, born, std);
+                     ybuf, norm, frames, charges, born, std);
   return hipGetLastError();
 }
 hipError_t launch_sg_asr_flag(int n_units, const int32_t* unit_off, double* born, const double* std, double thr,

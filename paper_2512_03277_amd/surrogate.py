@@ -71,26 +71,30 @@ def sub_clusters(system, pos, rng):
 
 
 def exact_born(params, system, pos_list, h=1e-3, tol=1e-10):
-    """Finite-difference Born charges for each position set (device tensors
-    [n_atoms, 3]); returns (born [n_snap, n_atoms, 9], bad-unit count)."""
+    """Finite-difference Born charges and Mulliken charges for each position set
+    (device tensors [n_atoms, 3]); returns (born [n_snap, n_atoms, 9],
+    charges [n_snap, n_atoms], bad-unit count)."""
     torch = _torch()
     dev = torch.device("cuda:0")
     ctx = B.context_from_system(params, system)
     ctx.set_scc(tol, 300, 0.2)
     out = torch.empty(len(pos_list), ctx.n_atoms, 9, dtype=torch.float64, device=dev)
+    q = torch.empty(len(pos_list), ctx.n_atoms, dtype=torch.float64, device=dev)
     st = torch.zeros(ctx.n_units, dtype=torch.int32, device=dev)
     bad = 0
     for k, pos in enumerate(pos_list):
+        ctx.eval_units(pos.contiguous(), charges=q[k], unit_status=st)
         ctx.born_charges(pos.contiguous(), B.BORN_FD, h, out[k], st)
         bad += int((st != 0).sum())
     ctx.sync()
     ctx.close()
-    return out, bad
+    return out, q, bad
 
 
-def features_and_targets(params, system, pos_list, born):
-    """Per species: descriptor rows (FP64 [N_s, 32]) and local-frame targets
-    (FP64 [N_s, 9]) over all snapshots."""
+def features_and_targets(params, system, pos_list, born, charges):
+    """Per species: descriptor rows (FP64 [N_s, 32]) and local-frame targets,
+    the correction R^T Z R - Q I to the Mulliken replacement (FP64 [N_s, 9]),
+    over all snapshots."""
     torch = _torch()
     dev = torch.device("cuda:0")
     ctx = B.context_from_system(params, system)
@@ -103,7 +107,7 @@ def features_and_targets(params, system, pos_list, born):
     zl = torch.empty(NA, 9, dtype=torch.float64, device=dev)
     for k, pos in enumerate(pos_list):
         ctx.sg_features(pos.contiguous(), feat, frames)
-        B.sg_to_local(frames, born[k].contiguous(), None, NA, zl)
+        B.sg_to_local(frames, born[k].contiguous(), charges[k].contiguous(), None, NA, zl)
         for s in (0, 1):
             m = sp == s
             feats[s].append(feat[m].clone())
@@ -242,7 +246,7 @@ def build_training_set(params, n_units=1024, n_train=16, n_val=4, stride=10, n_s
     if log:
         log(f"sampled {n_train + n_val} snapshots of {n_units} units in {time.time() - t0:.1f} s")
     t0 = time.time()
-    born, bad = exact_born(params, s, list(snaps))
+    born, charges, bad = exact_born(params, s, list(snaps))
     if log:
         log(f"exact Born labels: {len(snaps)} x {n_units} units in {time.time() - t0:.1f} s ({bad} bad units)")
     sub_pos, sub_sys = [], []
@@ -251,12 +255,12 @@ def build_training_set(params, n_units=1024, n_train=16, n_val=4, stride=10, n_s
         ss = sub_clusters(s, host[k], rng)
         sub_sys.append(ss)
         sub_pos.append(ss["pos"])
-    fe_t, ta_t = features_and_targets(params, s, list(snaps[:n_train]), born[:n_train])
+    fe_t, ta_t = features_and_targets(params, s, list(snaps[:n_train]), born[:n_train], charges[:n_train])
     torch = _torch()
     for ss in sub_sys:
         p = [torch.tensor(ss["pos"], device=snaps.device)]
-        bz, _ = exact_born(params, ss, p)
-        f2, t2 = features_and_targets(params, ss, p, bz)
+        bz, qz, _ = exact_born(params, ss, p)
+        f2, t2 = features_and_targets(params, ss, p, bz, qz)
         for sp in (0, 1):
             fe_t[sp] = torch.cat([fe_t[sp], f2[sp]])
             ta_t[sp] = torch.cat([ta_t[sp], t2[sp]])
@@ -272,6 +276,8 @@ def main(argv=None):
     ap.add_argument("--train-snapshots", type=int, default=16)
     ap.add_argument("--val-snapshots", type=int, default=4)
     ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--dump", default=None, help="also save a sample of the training rows (npz) for inspection")
+    ap.add_argument("--no-train", action="store_true")
     ap.add_argument("--out", default=os.path.join(os.path.dirname(os.path.abspath(__file__)), "data",
                                                   "surrogate_ensemble.npz"))
     args = ap.parse_args(argv)
@@ -284,6 +290,17 @@ def main(argv=None):
                               log=log)
     fe, ta = data["train"]
     log(f"training atoms: O {fe[0].shape[0]}, H {fe[1].shape[0]}")
+    if args.dump:
+        rng = np.random.default_rng(1)
+        out = {}
+        for sp in (0, 1):
+            pick = rng.choice(fe[sp].shape[0], size=min(20000, fe[sp].shape[0]), replace=False)
+            out[f"feat{sp}"] = fe[sp][pick].cpu().numpy()
+            out[f"targ{sp}"] = ta[sp][pick].cpu().numpy()
+        np.savez(args.dump, **out)
+        log(f"wrote {args.dump}")
+    if args.no_train:
+        return 0
     t0 = time.time()
     psg, nsg, losses = train_ensemble(fe, ta, epochs=args.epochs, log=log)
     log(f"training took {time.time() - t0:.1f} s")

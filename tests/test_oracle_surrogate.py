@@ -82,13 +82,14 @@ def test_prediction_equivariant_with_exact_sum_rule(cluster):
     nets = [[sg.init_params(rng) for _ in range(4)] for _ in range(2)]
     norms = [{"x_mean": np.zeros(32), "x_std": np.ones(32), "y_mean": np.zeros(9), "y_scale": np.full(9, 0.3)}
              for _ in range(2)]
-    Z, std = sg.predict_unit(sp, pos, nets, norms)
+    q = np.where(np.asarray(sp) == 0, -0.5, 0.25)
+    Z, std = sg.predict_unit(sp, pos, nets, norms, q)
     assert np.max(np.abs(Z.sum(0))) < 1e-13
     Q = _rot(5)
-    Z2, std2 = sg.predict_unit(sp, pos @ Q.T + 0.7, nets, norms)
+    Z2, std2 = sg.predict_unit(sp, pos @ Q.T + 0.7, nets, norms, q)
     assert np.allclose(Z2, np.einsum("ij,njk,lk->nil", Q, Z, Q), atol=1e-12)
     assert np.all(std >= 0)
-    Zb, _ = sg.predict_unit(sp, pos, nets, norms, emulate_bf16=True)
+    Zb, _ = sg.predict_unit(sp, pos, nets, norms, q, emulate_bf16=True)
     assert np.max(np.abs(Zb - Z)) < 0.05 * np.max(np.abs(Z))   # BF16 operands: small, non-zero change
     assert np.max(np.abs(Zb - Z)) > 0.0
 
@@ -106,3 +107,6 @@ def test_local_frame_round_trip(cluster):
     Z = np.random.default_rng(6).normal(size=(len(sp), 3, 3))
     zl = sg.to_local(Z, R)
     assert np.allclose(np.einsum("nij,njk,nlk->nil", R, zl, R), Z, atol=1e-13)
+    q = np.arange(len(sp)) * 0.01
+    zq = sg.to_local(Z, R, q)
+    assert np.allclose(zq + q[:, None, None] * np.eye(3), zl, atol=1e-14)
