@@ -11,9 +11,16 @@ obtained by finite differences of the SCC dipole).  Two forms:
 Layout: Z[A][a][b] = d mu_a / d R_{A b}.  Displaced SCCs are warm-started from
 the undisplaced charges.
 
+  Exact by the Maxwell relation (the force on an atom responds to a uniform
+  field exactly as the dipole responds to that atom's displacement):
+      Z_A[a][b] = d F_{A b} / d field_a
+               = (F_{A b}(+e e_a) - F_{A b}(-e e_a)) / (2 e)
+  six field-perturbed SCC evaluations per unit instead of 6 N_a displaced ones.
+
 Pinned by: acoustic sum rule sum_A Z_A = 0 for a neutral unit, the rotational
 sum rule sum_A Z_A (theta x R_A) = theta x mu, the C2v pattern of a symmetric
-monomer in its own frame (tests/test_oracle_born.py).
+monomer in its own frame, and agreement of the two independent exact routes
+(tests/test_oracle_born_cavity_md.py).
 """
 import numpy as np
 
@@ -23,6 +30,24 @@ from .scc import scc_unit
 def born_mulliken(charges):
     charges = np.asarray(charges, dtype=np.float64)
     return charges[:, None, None] * np.eye(3)[None, :, :]
+
+
+def born_field(params, species, pos, e=1.0e-4, tol=1e-12, max_iter=200, dq_center=None):
+    """Returns (Z (Na,3,3), worst SCC status over the 6 field-perturbed runs)."""
+    pos = np.asarray(pos, dtype=np.float64)
+    na = len(species)
+    Z = np.zeros((na, 3, 3))
+    worst = 0
+    for a in range(3):
+        fs = []
+        for sgn in (1.0, -1.0):
+            fld = np.zeros(3)
+            fld[a] = sgn * e
+            r = scc_unit(params, species, pos, tol=tol, max_iter=max_iter, dq_start=dq_center, field=fld)
+            worst |= r["status"]
+            fs.append(r["forces"])
+        Z[:, a, :] = (fs[0] - fs[1]) / (2.0 * e)
+    return Z, worst
 
 
 def born_fd(params, species, pos, h=1.0e-3, tol=1e-12, max_iter=200, dq_center=None):

@@ -117,14 +117,21 @@ def repulsion(params, species, pos, deriv=False):
     return (e, grad) if deriv else e
 
 
-def energy_forces(params, species, pos, P, W, dq, H0):
-    """Total energy and forces F = -dE/dR from a converged density."""
+def energy_forces(params, species, pos, P, W, dq, H0, field=None):
+    """Total energy and forces F = -dE/dR from a converged density.  With a
+    uniform field, E gains sum_A Dq_A (field . R_A) (the energy -mu . field of
+    the Mulliken dipole), V_A gains field . R_A and F_A gains -Dq_A field."""
     G, dG = gamma_matrix(params, species, pos, deriv=True)
     V = G @ dq
+    vext = np.zeros(len(species)) if field is None else pos @ np.asarray(field, dtype=np.float64)
+    V = V + vext
     off = orbital_offsets(params, species)
     e_band = float((P * H0).sum())
     e_coul = 0.5 * float(dq @ G @ dq)
     e_rep, grad = repulsion(params, species, pos, deriv=True)
+    e_field = float(dq @ vext)
+    if field is not None:
+        grad = grad + dq[:, None] * np.asarray(field, dtype=np.float64)[None, :]
     na = len(species)
     for a in range(na):
         for b in range(a + 1, na):
@@ -138,13 +145,15 @@ def energy_forces(params, species, pos, P, W, dq, H0):
             g = g + dq[a] * dq[b] * dG[a, b] * d / r
             grad[b] += g
             grad[a] -= g
-    return e_band + e_coul + e_rep, -grad, {"band": e_band, "coulomb": e_coul, "repulsion": e_rep}
+    return e_band + e_coul + e_rep + e_field, -grad, {"band": e_band, "coulomb": e_coul, "repulsion": e_rep,
+                                                       "field": e_field}
 
 
 def scc_unit(params, species, pos, tol=1e-12, max_iter=200, mixer="broyden", dq_start=None,
-             gamma_scale=1.0, want_forces=True, mix_alpha=0.2):
-    """SCC-DFTB of one unit.  Returns a dict with energy, forces (Na,3), dq (Na,),
-    charges Q = -dq, dipole (3,), P, W, eps, S, H0, n_iter, status."""
+             gamma_scale=1.0, want_forces=True, mix_alpha=0.2, field=None):
+    """SCC-DFTB of one unit, optionally in a uniform external field (3,).
+    Returns a dict with energy, forces (Na,3), dq (Na,), charges Q = -dq,
+    dipole (3,), P, W, eps, S, H0, n_iter, status."""
     species = np.asarray(species)
     pos = np.asarray(pos, dtype=np.float64)
     status = 0
@@ -163,9 +172,10 @@ def scc_unit(params, species, pos, tol=1e-12, max_iter=200, mixer="broyden", dq_
         return {"status": ST_NOT_PD}
     mix = Broyden(alpha=mix_alpha) if mixer == "broyden" else Linear(alpha=mix_alpha)
     dq_in = np.zeros(len(species)) if dq_start is None else np.array(dq_start, dtype=np.float64)
+    vext = np.zeros(len(species)) if field is None else pos @ np.asarray(field, dtype=np.float64)
     converged = False
     for it in range(1, max_iter + 1):
-        V = G @ dq_in
+        V = G @ dq_in + vext
         Vo = V[orb_atom]
         H = H0 + 0.5 * S * (Vo[:, None] + Vo[None, :])
         Hp = solve_triangular(L, solve_triangular(L, H, lower=True).T, lower=True).T
@@ -190,7 +200,7 @@ def scc_unit(params, species, pos, tol=1e-12, max_iter=200, mixer="broyden", dq_
         "status": status, "n_occ": n_occ,
     }
     if want_forces:
-        e, f, parts = energy_forces(params, species, pos, P, W, dq_out, H0)
+        e, f, parts = energy_forces(params, species, pos, P, W, dq_out, H0, field=field)
         if gamma_scale != 1.0:
             # energy of the scaled model (used only by the non-SCC limit pin)
             e = parts["band"] + 0.5 * gamma_scale * float(dq_out @ gamma_matrix(params, species, pos) @ dq_out) \

@@ -6,7 +6,7 @@ from cavgen import make_system, monomer_template, mode_comb
 from cavgen.constants import FS, AMU
 from oracle import cavity as cav
 from oracle import md
-from oracle.born import born_fd, born_mulliken
+from oracle.born import born_fd, born_field, born_mulliken
 from oracle.harmonic import HarmonicBackend, polariton_hessian
 from oracle.scc import scc_unit
 
@@ -43,6 +43,42 @@ def test_born_fd_sum_rules(monomer_born):
     # H1 and H2 are mirror images under y -> -y
     Mr = np.diag([1.0, -1.0, 1.0])
     assert np.max(np.abs(Mr @ Z[1] @ Mr - Z[2])) < 1e-8
+
+
+def test_field_energy_and_force_consistency(params):
+    # the field term is the energy -mu . field of the Mulliken dipole: dE/dfield = -mu,
+    # and the forces stay the exact negative gradient in a field
+    s = make_system(1, n_units=1)
+    sp, pos = s["species"], s["pos"]
+    f = np.array([2e-3, -1e-3, 3e-3])
+    r0 = scc_unit(params, sp, pos, tol=1e-13, field=f)
+    h = 1e-5
+    for a in range(3):
+        e = np.zeros(3)
+        e[a] = h
+        ep = scc_unit(params, sp, pos, tol=1e-13, field=f + e)["energy"]
+        em = scc_unit(params, sp, pos, tol=1e-13, field=f - e)["energy"]
+        assert -(ep - em) / (2 * h) == pytest.approx(r0["dipole"][a], rel=1e-6, abs=1e-10)
+    for (at, g) in [(0, 2), (1, 0)]:
+        d = np.zeros_like(pos)
+        d[at, g] = 1e-4
+        ep = scc_unit(params, sp, pos + d, tol=1e-13, field=f)["energy"]
+        em = scc_unit(params, sp, pos - d, tol=1e-13, field=f)["energy"]
+        assert r0["forces"][at, g] == pytest.approx(-(ep - em) / 2e-4, rel=1e-6, abs=1e-9)
+
+
+def test_maxwell_relation_born_equals_displacement_born(params, monomer_born):
+    # two independent exact routes: dF/dfield and dmu/dR
+    pos, c, Z, st = monomer_born
+    Zf, stf = born_field(params, np.array([0, 1, 1]), pos, e=1e-4, tol=1e-13, dq_center=c["dq"])
+    assert stf == 0
+    assert np.max(np.abs(Zf - Z)) < 2e-6
+    s = make_system(2, n_units=1)
+    sp, p3 = s["species"][:9], s["pos"][:9]
+    c3 = scc_unit(params, sp, p3, tol=1e-13)
+    Zd, _ = born_fd(params, sp, p3, h=1e-3, tol=1e-13, dq_center=c3["dq"])
+    Zm, _ = born_field(params, sp, p3, e=1e-4, tol=1e-13, dq_center=c3["dq"])
+    assert np.max(np.abs(Zm - Zd)) < 5e-6
 
 
 def _free_state(q0, p0, omega):
