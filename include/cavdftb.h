@@ -53,7 +53,8 @@ extern "C" {
 /* Born-charge modes */
 #define CAVDFTB_BORN_MULLIKEN 0  /* Z_A = Q_A I (the paper's cheap replacement, Results) */
 #define CAVDFTB_BORN_FD 1        /* central finite differences of the SCC dipole (Results) */
-#define CAVDFTB_BORN_SURROGATE 2 /* learned ensemble, exact FD for units where it disagrees */
+#define CAVDFTB_BORN_SURROGATE 2 /* learned ensemble, exact route for units where it disagrees */
+#define CAVDFTB_BORN_FIELD 3     /* exact, from the force response to a uniform field (Maxwell relation) */
 
 /* Surrogate network: per species (O, H) and member, 32 -> 128 SiLU -> 128
  * SiLU -> 9, flat FP32 parameters [W1 (32x128, row = input) | b1 | W2 (128x128)
@@ -152,10 +153,15 @@ int cavdftb_eval_units(cavdftb_ctx* ctx, const double* pos, double* energy, doub
  * converged SCC dipole, 6 n_atoms displaced SCCs per unit batched in one
  * launch, warm-started from the undisplaced solution (Results: the Born
  * charges are the bottleneck and are taken by finite differences);
+ * CAVDFTB_BORN_FIELD: the same tensor from the Maxwell relation
+ * d mu_a / d R_Ab = d F_Ab / d field_a, as central differences of the SCC
+ * forces in a uniform field +-h e_a (h in atomic units of field, e.g. 1e-4):
+ * 6 field-perturbed SCCs per unit instead of 6 n_atoms, same warm start;
  * CAVDFTB_BORN_SURROGATE: the ensemble set by cavdftb_set_surrogate (mean of
  * the members, acoustic sum rule imposed per unit); units whose largest
- * ensemble standard deviation exceeds the threshold are recomputed with
- * central differences of step h.  ens_std (device [n_atoms], may be NULL)
+ * ensemble standard deviation exceeds the threshold are recomputed by the
+ * exact route chosen with cavdftb_set_fallback (default CAVDFTB_BORN_FD),
+ * with step h of that route.  ens_std (device [n_atoms], may be NULL)
  * receives each atom's largest per-component ensemble standard deviation
  * (surrogate mode only; must be NULL otherwise).  Returns CAVDFTB_EINVAL for
  * the surrogate mode before cavdftb_set_surrogate. */
@@ -197,6 +203,10 @@ int cavdftb_cavity_forces(cavdftb_ctx* ctx, const double* mu_pol, const double* 
  * In surrogate mode the network output is that correction: Z = Q_A I + R dZ_loc R^T
  * with the Mulliken charges Q_A of the same SCC evaluation. */
 int cavdftb_set_surrogate(cavdftb_ctx* ctx, const float* params, const float* norm, double std_threshold);
+/* Exact route of the surrogate's fallback units: CAVDFTB_BORN_FD (default) or
+ * CAVDFTB_BORN_FIELD; the step passed with the surrogate mode is that route's
+ * step (bohr, or atomic units of field).  CAVDFTB_EINVAL for any other mode. */
+int cavdftb_set_fallback(cavdftb_ctx* ctx, int32_t mode);
 int cavdftb_sg_features(cavdftb_ctx* ctx, const double* pos, double* feat, double* frames);
 int cavdftb_sg_prep(const double* v, const int32_t* idx, int32_t n, int32_t width, const float* norm, float* x,
                     void* hip_stream);
@@ -222,7 +232,7 @@ int cavdftb_init_photons(cavdftb_ctx* ctx, const double* r, double* qm, double* 
  *   matter at r(t+dt); p += dt/2 (-dV/dr - E'_n e.Z) with E' from the old q;
  *   p_m -= dt/2 lambda omega F(t+dt); exact rotation of (q_m, p_m) by omega dt
  * (Theory, Step 1 Eq. pj1 and Step 3 Eq. qknk, in mode space).  born_mode as
- * in cavdftb_born_charges, with fd step h_fd.  The forces at r(t) are those of
+ * in cavdftb_born_charges, with h_fd the step of its exact route.  The forces at r(t) are those of
  * the previous call on the same context, or are evaluated first when the
  * context has not stepped yet (or after cavdftb_invalidate).
  * obs (device [n_steps][CAVDFTB_N_OBS] or NULL) receives per step:

@@ -28,14 +28,16 @@ exact-Born path (tests/test_oracle_cavity.py, tests/test_oracle_md.py).
 import numpy as np
 
 from . import cavity as cav
-from .born import born_fd, born_mulliken
+from .born import born_fd, born_field, born_mulliken
 from .scc import scc_unit
 from cavgen.constants import KB
 
 
 class DFTBBackend:
     """SCC-DFTB matter for every unit; Born charges by the Mulliken replacement
-    or by central finite differences."""
+    or by central finite differences (born="fd": of the dipole in the atom
+    displacements; born="field": of the forces in a uniform field, step h in
+    atomic units of field)."""
 
     def __init__(self, params, species, unit_off, born="mulliken", tol=1e-12, h=1e-3, max_iter=200):
         self.params, self.species, self.unit_off = params, np.asarray(species), np.asarray(unit_off)
@@ -59,6 +61,10 @@ class DFTBBackend:
             if self.born == "fd":
                 Z, st = born_fd(self.params, sp, r[a0:a1], h=self.h, tol=self.tol, max_iter=self.max_iter,
                                 dq_center=res["dq"])
+                out["status"][u] |= st
+            elif self.born == "field":
+                Z, st = born_field(self.params, sp, r[a0:a1], e=self.h, tol=self.tol, max_iter=self.max_iter,
+                                   dq_center=res["dq"])
                 out["status"][u] |= st
             else:
                 Z = born_mulliken(res["charges"])

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libcavdftb.so")
 
 OK, EINVAL, ENOMEM, EHIP = 0, -1, -2, -3
 ST_NOT_CONVERGED, ST_NOT_PD, ST_DEGENERATE, ST_NAN = 1, 2, 4, 8
-BORN_MULLIKEN, BORN_FD, BORN_SURROGATE = 0, 1, 2
+BORN_MULLIKEN, BORN_FD, BORN_SURROGATE, BORN_FIELD = 0, 1, 2, 3
 SG_N_IN, SG_N_HID, SG_N_OUT, SG_MEMBERS, SG_N_PARAM, SG_N_NORM = 32, 128, 9, 4, 21897, 82
 N_OBS = 8
 OBS_NAMES = ("kinetic", "potential", "photon", "total", "temperature", "n_bad_units", "scc_iterations",
@@ -55,6 +55,7 @@ SYMBOLS = {
     "cavdftb_cavity_forces": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "cavdftb_init_photons": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "cavdftb_set_surrogate": (ctypes.c_int, [_vp, _vp, _vp, _c_d]),
+    "cavdftb_set_fallback": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "cavdftb_sg_features": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "cavdftb_sg_prep": (ctypes.c_int, [_vp, _vp, _c_i32, _c_i32, _vp, _vp, _vp]),
     "cavdftb_sg_forward": (ctypes.c_int, [_vp, _vp, _c_i32, _vp, _vp, _vp]),
@@ -213,6 +214,9 @@ class Context:
         self._check(self.lib.cavdftb_set_surrogate(
             self.ctx, _ptr(params, t.float32, 2 * SG_MEMBERS * SG_N_PARAM, "params"),
             _ptr(norm, t.float32, 2 * SG_N_NORM, "norm"), float(std_threshold)), "set_surrogate")
+
+    def set_fallback(self, mode):
+        self._check(self.lib.cavdftb_set_fallback(self.ctx, int(mode)), "set_fallback")
 
     def sg_features(self, pos, feat=None, frames=None):
         t = self.torch

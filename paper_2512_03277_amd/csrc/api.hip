@@ -51,7 +51,10 @@ struct Bucket {
   int32_t* d_fd_job_disp = nullptr;
   int32_t* d_fd_unit = nullptr;  // [n_units] unit of each fd block
   int32_t* d_fd_job0 = nullptr;  // [n_units] first fd job (relative to this bucket's mu_job base)
-  // compacted displaced jobs of the units the surrogate hands back (fallback)
+  // field jobs of the Maxwell-relation Born charges: six per unit, -2 - (dir*2 + sign)
+  int32_t* d_ff_job_unit = nullptr;
+  int32_t* d_ff_job_disp = nullptr;
+  // compacted displaced (or field) jobs of the units the surrogate hands back (fallback)
   int32_t* d_fb_job_unit = nullptr;
   int32_t* d_fb_job_disp = nullptr;
   int32_t* d_fb_job0 = nullptr;
@@ -86,6 +89,8 @@ struct cavdftb_ctx {
   double *d_energy = nullptr, *d_forces = nullptr, *d_charges = nullptr, *d_dipole = nullptr;
   double *d_mu_pol = nullptr, *d_F = nullptr, *d_fq = nullptr, *d_field = nullptr, *d_zpol = nullptr;
   double* d_mu_job = nullptr;
+  double* d_f_job = nullptr;      // [6][NA][3] forces of the field jobs
+  int32_t* d_f_status = nullptr;  // [U][6] status of the field jobs
   int32_t *d_status = nullptr, *d_cjob_status = nullptr, *d_cjob_iters = nullptr;
   int32_t *d_fjob_status = nullptr, *d_fjob_iters = nullptr;
   unsigned long long* d_counters = nullptr;
@@ -94,6 +99,7 @@ struct cavdftb_ctx {
   float* d_sg_norm = nullptr;    // [2][N_NORM]
   double sg_thr = 0.05;
   bool sg_ready = false;
+  int32_t fallback_mode = CAVDFTB_BORN_FD;  // exact route for the units the surrogate hands back
   double* d_sg_feat = nullptr;    // [NA][32]
   double* d_sg_frames = nullptr;  // [NA][9]
   float* d_sg_x = nullptr;        // [NA][32], rows of species O then H
@@ -266,7 +272,7 @@ int eval_fd(cavdftb_ctx* c, const double* pos, double h, double* born, const int
     SccArgs a = base_args(c, pos);
     const int32_t* job0 = b.d_fd_job0;
     if (unit_flag) {
-      hipError_t e = launch_fd_compact(b.n_units, b.d_units, c->d_unit_off, unit_flag, b.d_fb_job_unit,
+      hipError_t e = launch_fd_compact(b.n_units, b.d_units, c->d_unit_off, unit_flag, 0, b.d_fb_job_unit,
                                        b.d_fb_job_disp, b.d_fb_job0, b.d_fb_n, c->stream);
       if (e != hipSuccess) return hip_fail(c, e, "fallback compaction");
       a.job_unit = b.d_fb_job_unit;
@@ -292,6 +298,48 @@ int eval_fd(cavdftb_ctx* c, const double* pos, double h, double* born, const int
     if (e != hipSuccess) return hip_fail(c, e, "born fd assemble");
   }
   return CAVDFTB_OK;
+}
+
+// field-perturbed SCCs (six per unit) for the Born charges from the Maxwell
+// relation; needs eval_center first.  With unit_flag, only the flagged units.
+int eval_field(cavdftb_ctx* c, const double* pos, double e_field, double* born, const int32_t* unit_flag = nullptr) {
+  for (const Bucket& b : c->buckets) {
+    SccArgs a = base_args(c, pos);
+    if (unit_flag) {
+      hipError_t e = launch_fd_compact(b.n_units, b.d_units, c->d_unit_off, unit_flag, 1, b.d_fb_job_unit,
+                                       b.d_fb_job_disp, b.d_fb_job0, b.d_fb_n, c->stream);
+      if (e != hipSuccess) return hip_fail(c, e, "fallback compaction");
+      a.job_unit = b.d_fb_job_unit;
+      a.job_disp = b.d_fb_job_disp;
+      a.n_jobs_dev = b.d_fb_n;
+    } else {
+      a.job_unit = b.d_ff_job_unit;
+      a.job_disp = b.d_ff_job_disp;
+    }
+    a.n_jobs = 6 * b.n_units;  // capacity; the device count bounds the compacted list
+    a.fd_h = e_field;
+    a.f_job = c->d_f_job;
+    a.f_status = c->d_f_status;
+    a.job_status = c->d_fjob_status + b.fjob0;  // 6 n_units <= the bucket's displaced-job slots
+    a.job_iters = c->d_fjob_iters + b.fjob0;
+    a.flags = JF_FORCES | JF_WARM_C | JF_WARM_DQ | (c->keep_hist ? JF_WARM_HIST : 0);
+    int rc = run_scc(c, b, a);
+    if (rc) return rc;
+  }
+  hipError_t e = launch_born_field_assemble(c->NA, c->d_atom_unit, c->d_unit_off, c->d_f_job, e_field, c->pol,
+                                            c->d_f_status, unit_flag, born, c->d_zpol, c->d_status, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "born field assemble");
+  return CAVDFTB_OK;
+}
+
+// exact Born charges by the route of mode (displacements or field)
+int eval_exact(cavdftb_ctx* c, int mode, const double* pos, double h, double* born, const int32_t* unit_flag = nullptr) {
+  return mode == CAVDFTB_BORN_FIELD ? eval_field(c, pos, h, born, unit_flag) : eval_fd(c, pos, h, born, unit_flag);
+}
+
+bool born_mode_ok(int mode) {
+  return mode == CAVDFTB_BORN_MULLIKEN || mode == CAVDFTB_BORN_FD || mode == CAVDFTB_BORN_SURROGATE ||
+         mode == CAVDFTB_BORN_FIELD;
 }
 
 // surrogate Born charges at pos into born (ensemble mean, acoustic sum imposed),
@@ -343,12 +391,12 @@ int matter_stage(cavdftb_ctx* c, const double* r, int born_mode, double h) {
   int rc = eval_center(c, r, true, true);
   if (rc) return rc;
   hipError_t e;
-  if (born_mode == CAVDFTB_BORN_FD) {
-    rc = eval_fd(c, r, h, nullptr);
+  if (born_mode == CAVDFTB_BORN_FD || born_mode == CAVDFTB_BORN_FIELD) {
+    rc = eval_exact(c, born_mode, r, h, nullptr);
     if (rc) return rc;
   } else if (born_mode == CAVDFTB_BORN_SURROGATE) {
     rc = sg_infer(c, r, c->d_born);
-    if (rc == CAVDFTB_OK) rc = eval_fd(c, r, h, c->d_born, c->d_unit_flag);
+    if (rc == CAVDFTB_OK) rc = eval_exact(c, c->fallback_mode, r, h, c->d_born, c->d_unit_flag);
     if (rc) return rc;
     e = launch_zpol_from_born(c->NA, c->d_born, c->pol, c->d_zpol, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "zpol");
@@ -566,6 +614,8 @@ int cavdftb_create(const cavdftb_params* params, const cavdftb_layout* L, void* 
     CK(dalloc(c, &b.d_fd_job_disp, b.n_fd_jobs));
     CK(dalloc(c, &b.d_fd_unit, b.n_units));
     CK(dalloc(c, &b.d_fd_job0, b.n_units));
+    CK(dalloc(c, &b.d_ff_job_unit, 6 * (size_t)b.n_units));
+    CK(dalloc(c, &b.d_ff_job_disp, 6 * (size_t)b.n_units));
     CK(dalloc(c, &b.d_fb_job_unit, b.n_fd_jobs));
     CK(dalloc(c, &b.d_fb_job_disp, b.n_fd_jobs));
     CK(dalloc(c, &b.d_fb_job0, b.n_units));
@@ -574,12 +624,24 @@ int cavdftb_create(const cavdftb_params* params, const cavdftb_layout* L, void* 
     CK(hipMemcpy(b.d_fd_job_disp, jdisp.data(), jdisp.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     CK(hipMemcpy(b.d_fd_unit, fdu.data(), fdu.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     CK(hipMemcpy(b.d_fd_job0, fdj0.data(), fdj0.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    {
+      std::vector<int32_t> fu, fd;
+      for (int u : bunits[k])
+        for (int code = 0; code < 6; ++code) {
+          fu.push_back(u);
+          fd.push_back(-2 - code);
+        }
+      CK(hipMemcpy(b.d_ff_job_unit, fu.data(), fu.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+      CK(hipMemcpy(b.d_ff_job_disp, fd.data(), fd.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    }
     c->buckets.push_back(b);
   }
   c->n_fd_total = fj;
   CK(dalloc(c, &c->d_mu_job, (size_t)fj * 3));
   CK(dalloc(c, &c->d_fjob_status, fj));
   CK(dalloc(c, &c->d_fjob_iters, fj));
+  CK(dalloc(c, &c->d_f_job, 18 * (size_t)NA));
+  CK(dalloc(c, &c->d_f_status, 6 * (size_t)U));
   hipLaunchKernelGGL(ws_identity_kernel, dim3(U), dim3(256), 0, c->stream, c->d_ws_C, c->d_ws_off, c->d_unit_off,
                      c->d_species, U, 0);
   CK(hipGetLastError());
@@ -661,8 +723,7 @@ int cavdftb_born_charges(cavdftb_ctx* ctx, const double* pos, int32_t mode, doub
   if (!ctx) return CAVDFTB_EINVAL;
   if (!pos || !born || (ens_std && mode != CAVDFTB_BORN_SURROGATE))
     return fail(ctx, CAVDFTB_EINVAL, "born_charges: bad pointer arguments");
-  if (mode != CAVDFTB_BORN_MULLIKEN && mode != CAVDFTB_BORN_FD && mode != CAVDFTB_BORN_SURROGATE)
-    return fail(ctx, CAVDFTB_EINVAL, "born_charges: unknown mode");
+  if (!born_mode_ok(mode)) return fail(ctx, CAVDFTB_EINVAL, "born_charges: unknown mode");
   if (mode != CAVDFTB_BORN_MULLIKEN && !(h > 0.0)) return fail(ctx, CAVDFTB_EINVAL, "born_charges: need h > 0");
   if (mode == CAVDFTB_BORN_SURROGATE && !ctx->sg_ready)
     return fail(ctx, CAVDFTB_EINVAL, "born_charges: no surrogate set (cavdftb_set_surrogate)");
@@ -672,12 +733,12 @@ int cavdftb_born_charges(cavdftb_ctx* ctx, const double* pos, int32_t mode, doub
   if (mode == CAVDFTB_BORN_MULLIKEN) {
     hipError_t e = launch_born_mulliken(ctx->d_charges, ctx->NA, born, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "born mulliken");
-  } else if (mode == CAVDFTB_BORN_FD) {
-    rc = eval_fd(ctx, pos, h, born);
+  } else if (mode == CAVDFTB_BORN_FD || mode == CAVDFTB_BORN_FIELD) {
+    rc = eval_exact(ctx, mode, pos, h, born);
     if (rc) return rc;
   } else {
     rc = sg_infer(ctx, pos, born);
-    if (rc == CAVDFTB_OK) rc = eval_fd(ctx, pos, h, born, ctx->d_unit_flag);
+    if (rc == CAVDFTB_OK) rc = eval_exact(ctx, ctx->fallback_mode, pos, h, born, ctx->d_unit_flag);
     if (rc) return rc;
     if (ens_std) {
       hipError_t e = hipMemcpyAsync(ens_std, ctx->d_sg_std, ctx->NA * sizeof(double), hipMemcpyDeviceToDevice,
@@ -721,6 +782,14 @@ int cavdftb_set_surrogate(cavdftb_ctx* ctx, const float* params, const float* no
   if (e != hipSuccess) return hip_fail(ctx, e, "set_surrogate copy");
   ctx->sg_thr = std_threshold;
   ctx->sg_ready = true;
+  return CAVDFTB_OK;
+}
+
+int cavdftb_set_fallback(cavdftb_ctx* ctx, int32_t mode) {
+  if (!ctx) return CAVDFTB_EINVAL;
+  if (mode != CAVDFTB_BORN_FD && mode != CAVDFTB_BORN_FIELD)
+    return fail(ctx, CAVDFTB_EINVAL, "set_fallback: mode must be CAVDFTB_BORN_FD or CAVDFTB_BORN_FIELD");
+  ctx->fallback_mode = mode;
   return CAVDFTB_OK;
 }
 
@@ -812,8 +881,7 @@ int cavdftb_step(cavdftb_ctx* ctx, double* r, double* p, double* qm, double* pm,
   if (!ctx) return CAVDFTB_EINVAL;
   if (!r || !p || (ctx->M > 0 && (!qm || !pm)) || n_steps < 0 || !(dt > 0.0))
     return fail(ctx, CAVDFTB_EINVAL, "step: bad arguments");
-  if (born_mode != CAVDFTB_BORN_MULLIKEN && born_mode != CAVDFTB_BORN_FD && born_mode != CAVDFTB_BORN_SURROGATE)
-    return fail(ctx, CAVDFTB_EINVAL, "step: unknown born mode");
+  if (!born_mode_ok(born_mode)) return fail(ctx, CAVDFTB_EINVAL, "step: unknown born mode");
   if (born_mode != CAVDFTB_BORN_MULLIKEN && !(h_fd > 0.0)) return fail(ctx, CAVDFTB_EINVAL, "step: need h_fd > 0");
   if (born_mode == CAVDFTB_BORN_SURROGATE && !ctx->sg_ready)
     return fail(ctx, CAVDFTB_EINVAL, "step: no surrogate set (cavdftb_set_surrogate)");

@@ -34,11 +34,12 @@ struct SccArgs {
   const int32_t* unit_off;  // [n_units+1]
   const int8_t* species;    // [n_atoms]
   const int32_t* job_unit;  // [n_jobs]
-  const int32_t* job_disp;  // [n_jobs] or nullptr; -1 = none, else (atom*3+dir)*2 + (step<0)
+  const int32_t* job_disp;  // [n_jobs] or nullptr; -1 = undisplaced, >= 0: displaced job
+                            // (atom*3+dir)*2 + (step<0); <= -2: field job -2 - (dir*2 + (field<0))
   const int32_t* unit_mask; // [n_units] or nullptr: jobs of units with mask 0 are skipped
   int32_t n_jobs;
   const int32_t* n_jobs_dev; // if set, the job count is read from device memory (compacted job lists)
-  double fd_h;
+  double fd_h;              // displacement (bohr) of displaced jobs, field (a.u.) of field jobs
   const int64_t* ws_off;    // [n_units] offset of the unit's stored basis in ws_C (doubles)
   double* ws_C;             // stored MO bases, NMAX x NMAX per unit of the bucket
   double* ws_dq;            // [n_atoms] stored charges (electron excess)
@@ -53,7 +54,9 @@ struct SccArgs {
   double* forces;           // [n_atoms][3] or nullptr
   double* charges;          // [n_atoms] or nullptr
   double* dipole;           // [n_units][3] or nullptr (written for undisplaced jobs)
-  double* mu_job;           // [n_jobs][3] or nullptr (written for displaced jobs)
+  double* mu_job;           // [n_jobs][3] or nullptr (written for displaced and field jobs)
+  double* f_job;            // [6][n_atoms][3] or nullptr: forces of the field jobs, by field code
+  int32_t* f_status;        // [n_units][6] or nullptr: status of the field jobs, by field code
   int32_t* status;          // [n_units] (undisplaced jobs) or nullptr
   int32_t* job_status;      // [n_jobs] or nullptr
   int32_t* job_iters;       // [n_jobs] or nullptr
@@ -94,6 +97,10 @@ hipError_t launch_init_photons(const CavArgs& c, const double* F, double* qm, do
 hipError_t launch_born_mulliken(const double* charges, int n_atoms, double* born, hipStream_t s);
 hipError_t launch_zpol_mulliken(const double* charges, const double pol[3], int n_atoms, double* zpol,
                                 hipStream_t s);
+hipError_t launch_born_field_assemble(int n_atoms, const int32_t* atom_unit, const int32_t* unit_off,
+                                      const double* f_job, double e, const double pol[3], const int32_t* f_status,
+                                      const int32_t* unit_mask, double* born, double* zpol, int32_t* status,
+                                      hipStream_t s);
 hipError_t launch_born_fd_assemble(const int32_t* unit_off, const int32_t* fd_unit, const int32_t* fd_job0,
                                    int n_fd_units, const double* mu_job, double h, const double pol[3],
                                    const int32_t* job_status, const int32_t* unit_mask, double* born, double* zpol,
@@ -132,6 +139,7 @@ hipError_t launch_sg_asr_flag(int n_units, const int32_t* unit_off, double* born
                               int32_t* flag, unsigned long long* n_flagged, hipStream_t s);
 hipError_t launch_zpol_from_born(int n, const double* born, const double pol[3], double* zp, hipStream_t s);
 hipError_t launch_fd_compact(int n_units_b, const int32_t* units_b, const int32_t* unit_off, const int32_t* flag,
-                             int32_t* job_unit, int32_t* job_disp, int32_t* job0, int32_t* n_jobs, hipStream_t s);
+                             int field, int32_t* job_unit, int32_t* job_disp, int32_t* job0, int32_t* n_jobs,
+                             hipStream_t s);
 
 }  // namespace cavdftb

@@ -131,6 +131,38 @@ __global__ __launch_bounds__(256) void born_fd_kernel(const int32_t* __restrict_
   }
 }
 
+// one thread per atom: Z[A][al][b] = (F_Ab(+e e_al) - F_Ab(-e e_al)) / 2e from the
+// forces of the six field jobs of the atom's unit (Maxwell relation d mu_al / d R_Ab
+// = d F_Ab / d field_al); the unit's first atom ORs the field-job status into the
+// unit status.
+__global__ __launch_bounds__(kNT) void born_field_kernel(int n, const int32_t* __restrict__ atom_unit,
+                                                         const int32_t* __restrict__ unit_off,
+                                                         const double* __restrict__ f_job, double e, double e0,
+                                                         double e1, double e2, const int32_t* __restrict__ f_status,
+                                                         const int32_t* __restrict__ mask,
+                                                         double* __restrict__ born, double* __restrict__ zpol,
+                                                         int32_t* __restrict__ status) {
+  const int i = blockIdx.x * kNT + threadIdx.x;
+  if (i >= n) return;
+  const int u = atom_unit[i];
+  if (mask && !mask[u]) return;
+  double Z[3][3];
+  for (int al = 0; al < 3; ++al)
+    for (int b = 0; b < 3; ++b)
+      Z[al][b] = (f_job[((int64_t)(2 * al) * n + i) * 3 + b] - f_job[((int64_t)(2 * al + 1) * n + i) * 3 + b]) /
+                 (2.0 * e);
+  if (born)
+    for (int al = 0; al < 3; ++al)
+      for (int b = 0; b < 3; ++b) born[(int64_t)i * 9 + al * 3 + b] = Z[al][b];
+  if (zpol)
+    for (int b = 0; b < 3; ++b) zpol[(int64_t)i * 3 + b] = e0 * Z[0][b] + e1 * Z[1][b] + e2 * Z[2][b];
+  if (status && f_status && i == unit_off[u]) {
+    int st = status[u];
+    for (int c = 0; c < 6; ++c) st |= f_status[(int64_t)u * 6 + c];
+    status[u] = st;
+  }
+}
+
 // OR the displaced-job status into the unit status, one thread per fd unit
 __global__ __launch_bounds__(kNT) void born_fd_status_kernel(const int32_t* __restrict__ unit_off,
                                                              const int32_t* __restrict__ fd_unit,
@@ -299,6 +331,15 @@ hipError_t launch_born_fd_assemble(const int32_t* unit_off, const int32_t* fd_un
     e = hipGetLastError();
   }
   return e;
+}
+
+hipError_t launch_born_field_assemble(int n_atoms, const int32_t* atom_unit, const int32_t* unit_off,
+                                      const double* f_job, double e, const double pol[3], const int32_t* f_status,
+                                      const int32_t* unit_mask, double* born, double* zpol, int32_t* status,
+                                      hipStream_t s) {
+  hipLaunchKernelGGL(born_field_kernel, dim3(nblk(n_atoms)), dim3(kNT), 0, s, n_atoms, atom_unit, unit_off, f_job, e,
+                     pol[0], pol[1], pol[2], f_status, unit_mask, born, zpol, status);
+  return hipGetLastError();
 }
 
 hipError_t launch_kick_drift(int n_atoms, const int32_t* atom_unit, const double* inv_mass, const double* forces,

@@ -336,6 +336,7 @@ struct Shared {
   int n, nocc, na, notpd;
   int bcount, bhead, sweeps, pad;
   double homo, lumo;
+  double fld[3];  // uniform external field of the job (zero except for field jobs)
 };
 
 
@@ -388,6 +389,7 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
       continue;
     }
     const int disp = a.job_disp ? a.job_disp[job] : -1;
+    const int fcode = disp <= -2 ? -2 - disp : -1;  // field job: dir*2 + (field < 0)
     const int a0 = a.unit_off[u];
     const int na = a.unit_off[u + 1] - a0;
     const int d_atom = disp >= 0 ? (disp >> 1) / 3 : -1;
@@ -396,7 +398,7 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
     // Broyden history: the unit's own store for undisplaced jobs (read-write),
     // a workgroup copy of it for displaced jobs (read-only use of the store)
     double* hst = a.hist ? a.hist + a.hist_off[u] : nullptr;  // [count, head, Gram H*H, dF H*NMAX, U H*NMAX]
-    const bool own_hist = hst && disp < 0 && (a.flags & JF_STORE_HIST);
+    const bool own_hist = hst && disp == -1 && (a.flags & JF_STORE_HIST);
     double* bDF = own_hist ? hst + 2 + kMaxHist * kMaxHist : sDF;
     double* bU = bDF + kMaxHist * NMAX;
 
@@ -434,6 +436,8 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
         sh.bhead = (int)hst[1];
       }
       sh.sweeps = 0;
+      for (int g = 0; g < 3; ++g) sh.fld[g] = 0.0;
+      if (fcode >= 0) sh.fld[fcode >> 1] = (fcode & 1) ? -a.fd_h : a.fd_h;
     }
     __syncthreads();
     const int n = sh.n, nocc = sh.nocc;
@@ -542,9 +546,9 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
     double res_prev = INFINITY;  // no charge residual known before the first iteration
     if (status == 0) {
       for (it = 1; it <= a.max_iter; ++it) {
-        // V = gamma Dq_in (gamma symmetric: column walk is coalesced)
+        // V = gamma Dq_in + field . R (gamma symmetric: column walk is coalesced)
         for (int t = tid; t < na; t += NT) {
-          double v = 0.0;
+          double v = sh.fld[0] * sPos[t * 3] + sh.fld[1] * sPos[t * 3 + 1] + sh.fld[2] * sPos[t * 3 + 2];
           for (int c = 0; c < na; ++c) v += gG[c * NMAX + t] * sDqIn[c];
           sV[t] = v;
         }
@@ -814,20 +818,20 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
     if (tid < 3) {
       double m = 0.0;
       for (int t = 0; t < na; ++t) m -= sDqOut[t] * sPos[t * 3 + tid];
-      if (disp >= 0) {
+      if (disp != -1) {
         if (a.mu_job) a.mu_job[(int64_t)job * 3 + tid] = m;
       } else if (a.dipole) {
         a.dipole[(int64_t)u * 3 + tid] = m;
       }
     }
-    if (disp < 0) {
+    if (disp == -1) {
       for (int t = tid; t < na; t += NT)
         if (a.charges) a.charges[a0 + t] = -sDqOut[t];
     }
-    if ((a.flags & JF_FORCES) && disp < 0) {
-      // V from the output charges; W = 2 C_occ eps C_occ^T into sA
+    if ((a.flags & JF_FORCES) && disp < 0) {  // undisplaced and field jobs
+      // V from the output charges (with the field potential); W = 2 C_occ eps C_occ^T into sA
       for (int t = tid; t < na; t += NT) {
-        double v = 0.0;
+        double v = sh.fld[0] * sPos[t * 3] + sh.fld[1] * sPos[t * 3 + 1] + sh.fld[2] * sPos[t * 3 + 2];
         for (int c = 0; c < na; ++c) v += gG[c * NMAX + t] * sDqOut[c];
         sV[t] = v;
       }
@@ -838,8 +842,12 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
       double ebp = 0.0;
       for (int i = rgrp; i < n; i += RG)
         for (int j = lane; j < n; j += 64) ebp += sT[i * LD + j] * gH0[i * NMAX + j];
+      // 1/2 Dq gamma Dq + Dq (field . R): V already holds the field potential once
       double ecp = 0.0;
-      for (int t = tid; t < na; t += NT) ecp += 0.5 * sDqOut[t] * sV[t];
+      for (int t = tid; t < na; t += NT) {
+        const double vx = sh.fld[0] * sPos[t * 3] + sh.fld[1] * sPos[t * 3 + 1] + sh.fld[2] * sPos[t * 3 + 2];
+        ecp += 0.5 * sDqOut[t] * (sV[t] + vx);
+      }
       // pair forces: task (A, part) sums g(A,B) over its B's
       constexpr int SPLIT = (NT / NMAX) > 0 ? NT / NMAX : 1;
       double erp = 0.0;
@@ -862,21 +870,25 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
           const double radial_g = sDqOut[A] * sDqOut[B] * dgm - P.rep_alpha[pt] * vrep;
           for (int g = 0; g < 3; ++g) fa[g] += radial_g * d[g] / r;
         }
+        if (part == 0)  // direct force of the field on the atom's excess charge
+          for (int g = 0; g < 3; ++g) fa[g] -= sDqOut[A] * sh.fld[g];
       }
       __syncthreads();  // sF may alias sX
       for (int g = 0; g < 3; ++g) sF[tid * 3 + g] = fa[g];
       const double etot = block_sum<NT>(ebp + ecp + erp, sRed);  // contains the barrier for sF
+      double* fo = disp == -1 ? a.forces : (a.f_job ? a.f_job + (int64_t)fcode * a.n_atoms * 3 : nullptr);
       for (int t = tid; t < na; t += NT) {
         for (int g = 0; g < 3; ++g) {
           double f = 0.0;
           for (int pp = 0; pp < SPLIT; ++pp) f += sF[(t * SPLIT + pp) * 3 + g];
-          if (a.forces) a.forces[(int64_t)(a0 + t) * 3 + g] = f;
+          if (fo) fo[(int64_t)(a0 + t) * 3 + g] = f;
         }
       }
-      if (tid == 0 && a.energy) a.energy[u] = etot;
+      if (tid == 0 && a.energy && disp == -1) a.energy[u] = etot;
     }
     if (tid == 0) {
-      if (disp < 0 && a.status) a.status[u] = status;
+      if (disp == -1 && a.status) a.status[u] = status;
+      if (fcode >= 0 && a.f_status) a.f_status[(int64_t)u * 6 + fcode] = status;
       if (a.job_status) a.job_status[job] = status;
       if (a.job_iters) a.job_iters[job] = it;
       if (a.counters) {

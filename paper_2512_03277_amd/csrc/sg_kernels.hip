@@ -473,11 +473,12 @@ __global__ __launch_bounds__(NT) void zpol_from_born_kernel(int n, const double*
     zp[a * 3 + b] = e0 * born[(int64_t)a * 9 + b] + e1 * born[(int64_t)a * 9 + 3 + b] + e2 * born[(int64_t)a * 9 + 6 + b];
 }
 
-// compact the displaced-job list of the flagged units of one bucket, in unit
-// order (one workgroup; block scan over chunks of NT units)
+// compact the displaced-job (or field-job) list of the flagged units of one
+// bucket, in unit order (one workgroup; block scan over chunks of NT units)
 __global__ __launch_bounds__(NT) void fd_compact_kernel(int n_units_b, const int32_t* __restrict__ units_b,
                                                         const int32_t* __restrict__ unit_off,
-                                                        const int32_t* __restrict__ flag, int32_t* __restrict__ job_unit,
+                                                        const int32_t* __restrict__ flag, int field,
+                                                        int32_t* __restrict__ job_unit,
                                                         int32_t* __restrict__ job_disp, int32_t* __restrict__ job0,
                                                         int32_t* __restrict__ n_jobs) {
   __shared__ int scan[NT];
@@ -490,7 +491,7 @@ __global__ __launch_bounds__(NT) void fd_compact_kernel(int n_units_b, const int
     if (w < n_units_b) {
       u = units_b[w];
       na = unit_off[u + 1] - unit_off[u];
-      cnt = flag[u] ? 6 * na : 0;
+      cnt = flag[u] ? (field ? 6 : 6 * na) : 0;
     }
     scan[threadIdx.x] = cnt;
     __syncthreads();
@@ -505,7 +506,7 @@ __global__ __launch_bounds__(NT) void fd_compact_kernel(int n_units_b, const int
       job0[w] = cnt ? start : -1;
       for (int j = 0; j < cnt; ++j) {
         job_unit[start + j] = u;
-        job_disp[start + j] = j;  // (atom*3 + dir)*2 + sign, in order
+        job_disp[start + j] = field ? -2 - j : j;  // field: -2 - (dir*2 + sign); else (atom*3 + dir)*2 + sign
       }
     }
     __syncthreads();
@@ -590,9 +591,10 @@ hipError_t launch_sg_asr_flag(int n_units, const int32_t* unit_off, double* born
   return hipGetLastError();
 }
 hipError_t launch_fd_compact(int n_units_b, const int32_t* units_b, const int32_t* unit_off, const int32_t* flag,
-                             int32_t* job_unit, int32_t* job_disp, int32_t* job0, int32_t* n_jobs, hipStream_t s) {
-  hipLaunchKernelGGL(fd_compact_kernel, dim3(1), dim3(NT), 0, s, n_units_b, units_b, unit_off, flag, job_unit, job_disp,
-                     job0, n_jobs);
+                             int field, int32_t* job_unit, int32_t* job_disp, int32_t* job0, int32_t* n_jobs,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(fd_compact_kernel, dim3(1), dim3(NT), 0, s, n_units_b, units_b, unit_off, flag, field, job_unit,
+                     job_disp, job0, n_jobs);
   return hipGetLastError();
 }
 

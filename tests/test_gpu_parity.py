@@ -12,7 +12,7 @@ from cavgen import make_params, make_system, mode_comb
 from cavgen.systems import CAVITY_LENGTH
 from oracle import cavity as ocav
 from oracle import md as omd
-from oracle.born import born_fd
+from oracle.born import born_fd, born_field
 from oracle.scc import eval_units, scc_unit
 
 pytestmark = pytest.mark.gpu
@@ -192,6 +192,52 @@ def test_born_fd_parity_and_sum_rule(params):
         assert np.max(np.abs(Z[a0:a1].sum(0))) < 1e-5
 
 
+def test_born_field_parity(params):
+    # Maxwell-relation route against the oracle's field route, and against the
+    # displacement route within the two finite-difference errors
+    s = subsystem(make_system(5, n_units=6), [0, 1, 5])
+    ctx = make_ctx(params, s)
+    born = torch.zeros(ctx.n_atoms, 3, 3, dtype=torch.float64, device=DEV)
+    born_d = torch.zeros_like(born)
+    st = torch.zeros(ctx.n_units, dtype=torch.int32, device=DEV)
+    ctx.born_charges(_t(s["pos"]), cd.BORN_FIELD, 1e-4, born, st)
+    ctx.born_charges(_t(s["pos"]), cd.BORN_FD, 1e-3, born_d)
+    ctx.sync()
+    Z, Zd = born.cpu().numpy(), born_d.cpu().numpy()
+    assert np.all(st.cpu().numpy() == 0)
+    off = s["unit_off"]
+    for u in range(ctx.n_units):
+        a0, a1 = off[u], off[u + 1]
+        c = scc_unit(params, s["species"][a0:a1], s["pos"][a0:a1], tol=1e-12)
+        Zr, stf = born_field(params, s["species"][a0:a1], s["pos"][a0:a1], e=1e-4, tol=1e-12, dq_center=c["dq"])
+        assert stf == 0
+        # force bar 1e-9 x max|F| over a field step of 2e-4 a.u.
+        assert np.max(np.abs(Z[a0:a1] - Zr)) <= 1e-7
+    assert np.max(np.abs(Z - Zd)) <= 1e-5
+
+
+def test_born_field_across_orbital_buckets(params):
+    # units of several orbital buckets in one call: every atom's tensor is written
+    s = subsystem(make_system(4, n_units=64), list(range(0, 64, 9)))
+    ctx = make_ctx(params, s)
+    born = torch.full((ctx.n_atoms, 3, 3), float("nan"), dtype=torch.float64, device=DEV)
+    st = torch.zeros(ctx.n_units, dtype=torch.int32, device=DEV)
+    ctx.born_charges(_t(s["pos"]), cd.BORN_FIELD, 1e-4, born, st)
+    ctx.sync()
+    Z = born.cpu().numpy()
+    good = st.cpu().numpy() == 0
+    off = s["unit_off"]
+    for u in np.nonzero(good)[0]:
+        a0, a1 = off[u], off[u + 1]
+        assert np.all(np.isfinite(Z[a0:a1]))
+        assert np.max(np.abs(Z[a0:a1].sum(0))) < 1e-5        # acoustic sum rule of the exact tensor
+    u = int(np.nonzero(good)[0][-1])
+    a0, a1 = off[u], off[u + 1]
+    c = scc_unit(params, s["species"][a0:a1], s["pos"][a0:a1], tol=1e-12)
+    Zr, _ = born_field(params, s["species"][a0:a1], s["pos"][a0:a1], e=1e-4, tol=1e-12, dq_center=c["dq"])
+    assert np.max(np.abs(Z[a0:a1] - Zr)) <= 1e-7
+
+
 def test_born_mulliken_is_charge_identity(params):
     s = make_system(1)
     ctx = make_ctx(params, s)
@@ -279,6 +325,27 @@ def test_md_step_exact_born_parity(params):
     st, _ = _oracle_md(params, s, "fd", 2)
     assert _rel(r, st["r"]) <= 1e-9 and _rel(p, st["p"]) <= 1e-8
     assert _rel(qm, st["q"]) <= 1e-8 and _rel(pm, st["pm"]) <= 1e-8
+
+
+def test_md_step_field_born_parity(params):
+    s = subsystem(make_system(1), [0, 3])
+    ctx = make_ctx(params, s)
+    masses = params["mass"][s["species"]]
+    r = _t(s["pos"])
+    p = _t(s["vel"] * masses[:, None])
+    qm = torch.zeros(ctx.n_modes, dtype=torch.float64, device=DEV)
+    pm = torch.zeros_like(qm)
+    ctx.init_photons(r, qm, pm)
+    ctx.step(r, p, qm, pm, 2, s["dt"], cd.BORN_FIELD, 1e-4)
+    assert ctx.sync() == 0
+    be = omd.DFTBBackend(params, s["species"], s["unit_off"], born="field", tol=1e-12, h=1e-4)
+    cav = omd.Cavity(s["omega"], s["k"], s["theta"], s["lam"], s["unit_x"], s["pol"])
+    atom_unit = np.repeat(np.arange(len(s["unit_off"]) - 1), np.diff(s["unit_off"]))
+    st = omd.init_state(be, cav, s["pos"], s["vel"] * masses[:, None], masses, atom_unit)
+    for _ in range(2):
+        omd.step(st, be, cav, s["dt"])
+    assert _rel(r.cpu().numpy(), st["r"]) <= 1e-9 and _rel(p.cpu().numpy(), st["p"]) <= 1e-8
+    assert _rel(qm.cpu().numpy(), st["q"]) <= 1e-8 and _rel(pm.cpu().numpy(), st["pm"]) <= 1e-8
 
 
 def test_status_flags(params):

@@ -4,7 +4,7 @@ Bars: descriptors and frames abs 1e-12; network outputs and gradients within
 1e-3 of the largest value of each tensor (BF16 operands on both sides; the
 oracle accumulates in FP64, the kernels in FP32, so a BF16 rounding can flip);
 Born tensors through the full surrogate path within 1e-3 of max |Z|; the
-fallback path equals exact finite differences bitwise.
+fallback path equals the exact route (displacements or field) bitwise.
 """
 import numpy as np
 import pytest
@@ -145,23 +145,57 @@ def test_surrogate_born_matches_oracle_prediction(params):
     assert ctx.read_counters()["surrogate_fallback_units"] == 0
 
 
-def test_fallback_reproduces_exact_finite_differences(params):
+@pytest.mark.parametrize("route,h", [(cd.BORN_FD, 1e-3), (cd.BORN_FIELD, 1e-4)])
+def test_fallback_reproduces_exact_route(params, route, h):
     s = make_system(5, n_units=6)
     _, _, P, N = _random_ensemble(3)
     ctx = cd.context_from_system(params, s)
     ctx.set_scc(1e-12, 300, 0.2)
     ctx.set_surrogate(P.view(-1), N.view(-1), 0.0)      # threshold 0: every unit falls back
+    ctx.set_fallback(route)
     pos = _t(s["pos"])
     Zs = torch.empty(ctx.n_atoms, 9, dtype=torch.float64, device=DEV)
     Zf = torch.empty_like(Zs)
-    ctx.born_charges(pos, cd.BORN_SURROGATE, 1e-3, Zs)
+    ctx.born_charges(pos, cd.BORN_SURROGATE, h, Zs)
     ctx.reset_warm_start()
-    ctx.born_charges(pos, cd.BORN_SURROGATE, 1e-3, Zs)
+    ctx.born_charges(pos, cd.BORN_SURROGATE, h, Zs)
     ctx.reset_warm_start()
-    ctx.born_charges(pos, cd.BORN_FD, 1e-3, Zf)
+    ctx.born_charges(pos, route, h, Zf)
     ctx.sync()
     assert torch.equal(Zs, Zf)
     assert ctx.read_counters()["surrogate_fallback_units"] == 2 * ctx.n_units
+
+
+def test_partial_fallback_keeps_surrogate_units(params):
+    # threshold at the median unit spread: flagged units take the exact field route,
+    # the others keep the surrogate tensors, both bitwise
+    s = make_system(5, n_units=12)
+    _, _, P, N = _random_ensemble(5)
+    pos = _t(s["pos"])
+    out = {}
+    for name, thr, mode in (("sg", 1e30, cd.BORN_SURROGATE), ("ex", 0.0, cd.BORN_FIELD), ("mix", None, cd.BORN_SURROGATE)):
+        ctx = cd.context_from_system(params, s)
+        ctx.set_scc(1e-12, 300, 0.2)
+        if thr is None:
+            thr = float(np.median(spread))
+        ctx.set_surrogate(P.view(-1), N.view(-1), thr)
+        ctx.set_fallback(cd.BORN_FIELD)
+        Z = torch.empty(ctx.n_atoms, 9, dtype=torch.float64, device=DEV)
+        sd = torch.zeros(ctx.n_atoms, dtype=torch.float64, device=DEV) if mode == cd.BORN_SURROGATE else None
+        ctx.born_charges(pos, mode, 1e-4, Z, ens_std=sd)
+        ctx.sync()
+        out[name] = Z.cpu().numpy()
+        if name == "sg":
+            sdn = sd.cpu().numpy()
+            spread = np.array([sdn[s["unit_off"][u]:s["unit_off"][u + 1]].max() for u in range(ctx.n_units)])
+        if name == "mix":
+            n_fb = ctx.read_counters()["surrogate_fallback_units"]
+    flagged = spread > np.median(spread)
+    assert 0 < flagged.sum() < len(flagged) and n_fb == flagged.sum()
+    for u in range(len(flagged)):
+        a0, a1 = s["unit_off"][u], s["unit_off"][u + 1]
+        ref = out["ex"] if flagged[u] else out["sg"]
+        assert np.array_equal(out["mix"][a0:a1], ref[a0:a1]), u
 
 
 def test_surrogate_md_steps_run_and_stay_finite(params):
