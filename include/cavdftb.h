@@ -78,7 +78,7 @@ typedef struct cavdftb_params {
   double sk[7][4];
   double onsite[2][2]; /* [species][l]: O {eps_s, eps_p}, H {eps_s, unused} */
   double hubbard_u[2]; /* U_O, U_H (hartree); gamma uses tau = 16 U / 5 */
-  double q0[2];        /* neutral valence populations: O 6, H 1 */
+  double q0[2];        /* neutral valence populations: O 6, H 1 (create: CAVDFTB_EINVAL outside [0, 8] and [0, 2]) */
   double rep_a[3];
   double rep_alpha[3];
   double mass[2]; /* nuclear masses (electron masses) */
@@ -260,7 +260,9 @@ typedef struct cavdftb_counters {
   double scc_kernel_ms;
   int64_t scc_launches;
   int64_t jacobi_sweeps;             /* Jacobi sweeps summed over all SCC iterations of all jobs */
-  int64_t surrogate_fallback_units;  /* units recomputed by finite differences in surrogate mode */
+  int64_t surrogate_fallback_units;  /* units recomputed by the exact route in surrogate mode */
+  int64_t jacobi_iterations;         /* SCC iterations that diagonalised by full Jacobi (the others took
+                                        one occupied-virtual rotation of the previous basis) */
 } cavdftb_counters;
 int cavdftb_enable_timing(cavdftb_ctx* ctx, int32_t enable);
 int cavdftb_read_counters(cavdftb_ctx* ctx, cavdftb_counters* out);

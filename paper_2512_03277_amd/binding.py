@@ -40,7 +40,7 @@ class Layout(ctypes.Structure):
 class Counters(ctypes.Structure):
     _fields_ = [("scc_jobs", ctypes.c_int64), ("scc_iterations", ctypes.c_int64), ("scc_flops", _c_d),
                 ("scc_kernel_ms", _c_d), ("scc_launches", ctypes.c_int64), ("jacobi_sweeps", ctypes.c_int64),
-                ("surrogate_fallback_units", ctypes.c_int64)]
+                ("surrogate_fallback_units", ctypes.c_int64), ("jacobi_iterations", ctypes.c_int64)]
 
 
 SYMBOLS = {

@@ -433,6 +433,10 @@ int cavdftb_create(const cavdftb_params* params, const cavdftb_layout* L, void* 
   memcpy(c->prm.sk, params->sk, sizeof(c->prm.sk));
   memcpy(c->prm.onsite, params->onsite, sizeof(c->prm.onsite));
   memcpy(c->prm.U, params->hubbard_u, sizeof(c->prm.U));
+  if (!(params->q0[0] >= 0.0 && params->q0[0] <= 8.0 && params->q0[1] >= 0.0 && params->q0[1] <= 2.0)) {
+    delete c;  // neutral valence populations must fit the minimal basis (O: 4 orbitals, H: 1)
+    return CAVDFTB_EINVAL;
+  }
   memcpy(c->prm.q0, params->q0, sizeof(c->prm.q0));
   memcpy(c->prm.rep_a, params->rep_a, sizeof(c->prm.rep_a));
   memcpy(c->prm.rep_alpha, params->rep_alpha, sizeof(c->prm.rep_alpha));
@@ -956,10 +960,11 @@ int cavdftb_read_counters(cavdftb_ctx* ctx, cavdftb_counters* out) {
   out->scc_kernel_ms = ctx->t_ms;
   out->scc_launches = ctx->launches;
   out->jacobi_sweeps = (int64_t)h[3];
-  unsigned long long h4 = 0;
-  e = hipMemcpy(&h4, ctx->d_counters + 4, sizeof(h4), hipMemcpyDeviceToHost);
+  unsigned long long h45[2] = {0, 0};
+  e = hipMemcpy(h45, ctx->d_counters + 4, sizeof(h45), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(ctx, e, "counters copy");
-  out->surrogate_fallback_units = (int64_t)h4;
+  out->surrogate_fallback_units = (int64_t)h45[0];
+  out->jacobi_iterations = (int64_t)h45[1];
   return CAVDFTB_OK;
 }
 

@@ -60,7 +60,7 @@ struct SccArgs {
   int32_t* status;          // [n_units] (undisplaced jobs) or nullptr
   int32_t* job_status;      // [n_jobs] or nullptr
   int32_t* job_iters;       // [n_jobs] or nullptr
-  unsigned long long* counters;  // [3]: jobs, iterations, algorithmic flops
+  unsigned long long* counters;  // [8]: jobs, iterations, algorithmic flops, Jacobi sweeps, surrogate fallback units, Jacobi iterations
   double tol;
   int32_t max_iter;
   double alpha;

@@ -32,6 +32,19 @@ namespace {
 constexpr int kMaxSweeps = 30;
 constexpr double kJacobiThr = 1.0e-14;  // off-diagonal threshold (hartree)
 constexpr double kGapMin = 1.0e-6;
+// warm orthonormalisation: Newton-Schulz from max|C0^T S C0 - I| <= kNsStart
+constexpr double kNsStart = 0.1;
+constexpr double kNsTol = 1.0e-15;
+constexpr int kNsMaxSteps = 8;
+// occupied-virtual step: used while the occupied columns of X stay separated
+// from the virtual ones (diagonal gap > kOvGap), the coupling is small
+// (max |A_ov| < kOvAngle gap) and the within-block couplings are small
+// (max |A_oo|, |A_vv| off the diagonal < kOvOff gap); else full Jacobi
+constexpr double kOvGap = 0.02;
+constexpr double kOvAngle = 0.1;
+constexpr double kOvOff = 0.2;
+constexpr double kOvNorm = 1.0e-2;  // bound on ||L||_F^2 for the Neumann series of (I + L^T L)^{-1}
+constexpr int kSylvester = 2;       // even: the final K lands in the first slot
 
 // ---------------------------------------------------------------- SK rules
 __device__ __forceinline__ void radial(const DevParams& P, int t, double r, double& h, double& s, double& hp,
@@ -199,34 +212,62 @@ __device__ void gamma_pair(double ua, double ub, double r, double& g, double& dg
 }
 
 // ---------------------------------------------------------------- block helpers
+// Reductions: butterfly within each 64-lane wave (cross-lane shuffles, fixed
+// order), then the per-wave partials through LDS in wave order.  Every thread
+// gets the result; the trailing barrier lets red be reused at once.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
 template <int NT>
 __device__ double block_sum(double v, double* red) {
-  const int t = threadIdx.x;
-  red[t] = v;
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
+  double r = red[0];
 #pragma unroll
-  for (int s = NT / 2; s > 0; s >>= 1) {
-    if (t < s) red[t] += red[t + s];
-    __syncthreads();
-  }
-  const double r = red[0];
+  for (int w = 1; w < NT / 64; ++w) r += red[w];
   __syncthreads();
   return r;
 }
 
 template <int NT>
 __device__ double block_max(double v, double* red) {
-  const int t = threadIdx.x;
-  red[t] = v;
+  v = wave_max(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
+  double r = red[0];
 #pragma unroll
-  for (int s = NT / 2; s > 0; s >>= 1) {
-    if (t < s) red[t] = fmax(red[t], red[t + s]);
-    __syncthreads();
-  }
-  const double r = red[0];
+  for (int w = 1; w < NT / 64; ++w) r = fmax(r, red[w]);
   __syncthreads();
   return r;
+}
+
+// K maxima at once (v updated in place)
+template <int NT, int K>
+__device__ void block_max_n(double (&v)[K], double* red) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = wave_max(v[k]);
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int k = 0; k < K; ++k) red[k * (NT / 64) + (threadIdx.x >> 6)] = v[k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double r = red[k * (NT / 64)];
+#pragma unroll
+    for (int w = 1; w < NT / 64; ++w) r = fmax(r, red[k * (NT / 64) + w]);
+    v[k] = r;
+  }
+  __syncthreads();
 }
 
 // Working-matrix layout: NMAX x LD doubles, LD = NMAX + 1 so that a column
@@ -334,7 +375,7 @@ __device__ __forceinline__ int rr_index(int s, int r, int m) { return s == 0 ? 0
 
 struct Shared {
   int n, nocc, na, notpd;
-  int bcount, bhead, sweeps, pad;
+  int bcount, bhead, sweeps, jac_iters;
   double homo, lumo;
   double fld[3];  // uniform external field of the job (zero except for field jobs)
 };
@@ -354,7 +395,7 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
   __shared__ double sFbuf[F_IN_X ? 1 : 3 * NT];
   __shared__ double sPos[NMAX * 3];
   __shared__ double sDqIn[NMAX], sDqOut[NMAX], sV[NMAX], sQ0[NMAX], sEig[NMAX], sW[NMAX], sQorb[NMAX];
-  __shared__ int sOrbAtom[NMAX], sAtomOff[NMAX + 1], sSp[NMAX], sOcc[NMAX];
+  __shared__ int sOrbAtom[NMAX], sAtomOff[NMAX + 1], sSp[NMAX], sOcc[NMAX], sRank[NMAX];
   __shared__ double sRed[NT];
   __shared__ int sRp[2][HALF], sRq[2][HALF];
   __shared__ double sRc[2][HALF], sRs[2][HALF], sRt[2][HALF];
@@ -376,7 +417,6 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
   double* sX = GM ? sU + kMaxHist * NMAX : lX;
   double* sA = GM ? sX + NMAX * LD : lA;
   double* sT = GM ? sA + NMAX * LD : lT;
-  double* sF = F_IN_X ? sX : sFbuf;
 
   const int n_jobs = a.n_jobs_dev ? *a.n_jobs_dev : a.n_jobs;
   for (int job = blockIdx.x; job < n_jobs; job += gridDim.x) {
@@ -436,6 +476,7 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
         sh.bhead = (int)hst[1];
       }
       sh.sweeps = 0;
+      sh.jac_iters = 0;
       for (int g = 0; g < 3; ++g) sh.fld[g] = 0.0;
       if (fcode >= 0) sh.fld[fcode >> 1] = (fcode & 1) ? -a.fd_h : a.fd_h;
     }
@@ -495,8 +536,13 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
     }
     __syncthreads();
 
-    // ---- S-orthonormal starting basis X = C0 R^{-1}, M = C0^T S C0 = R^T R
+    // ---- S-orthonormal starting basis X.  Warm: M = C0^T S C0 of the stored
+    // basis C0; when M is close to I, Newton-Schulz steps X <- X (3I - M)/2
+    // (quadratic convergence to the symmetric orthonormalisation C0 M^{-1/2},
+    // which keeps the column order and the near-eigenvector property);
+    // otherwise, and for the cold start X = I, Cholesky M = R^T R and X = C0 R^{-1}.
     const bool warm = (a.flags & JF_WARM_C) != 0;
+    bool use_chol = true;
     if (warm) {
       const double* wc = a.ws_C + a.ws_off[u];
       for (int i = rgrp; i < n; i += RG)
@@ -509,6 +555,35 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
       __syncthreads();
       gemm<NMAX, NT, true>(sX, sT, sA, n);  // M = C0^T S C0
       __syncthreads();
+      double e = 0.0;
+      for (int i = rgrp; i < n; i += RG)
+        for (int j = lane; j < n; j += 64) e = fmax(e, fabs(sA[i * LD + j] - (i == j ? 1.0 : 0.0)));
+      e = block_max<NT>(e, sRed);
+      if (e <= kNsStart) {  // false for a non-finite M
+        use_chol = false;
+        for (int k = 0; k < kNsMaxSteps && e > kNsTol; ++k) {
+          for (int i = rgrp; i < n; i += RG)
+            for (int j = lane; j < n; j += 64) sA[i * LD + j] = (i == j ? 1.5 : 0.0) - 0.5 * sA[i * LD + j];
+          __syncthreads();
+          gemm<NMAX, NT, false>(sX, sA, sT, n);  // X (3I - M) / 2
+          __syncthreads();
+          double* tmp = sX;
+          sX = sT;
+          sT = tmp;
+          if (0.75 * e * e < kNsTol * 1e-2) break;  // the next M would be I to rounding
+          for (int i = rgrp; i < n; i += RG)
+            for (int j = lane; j < n; j += 64) sA[i * LD + j] = gS[i * NMAX + j];
+          __syncthreads();
+          gemm<NMAX, NT, false>(sA, sX, sT, n);  // S X
+          __syncthreads();
+          gemm<NMAX, NT, true>(sX, sT, sA, n);  // M = X^T S X
+          __syncthreads();
+          e = 0.0;
+          for (int i = rgrp; i < n; i += RG)
+            for (int j = lane; j < n; j += 64) e = fmax(e, fabs(sA[i * LD + j] - (i == j ? 1.0 : 0.0)));
+          e = block_max<NT>(e, sRed);
+        }
+      }
     } else {
       for (int i = rgrp; i < n; i += RG)
         for (int j = lane; j < n; j += 64) {
@@ -518,7 +593,7 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
       __syncthreads();
     }
     // right-looking Cholesky of M fused with the solve X R = C0
-    for (int k = 0; k < n; ++k) {
+    for (int k = 0; use_chol && k < n; ++k) {
       const double dkk = sA[k * LD + k];
       const double rkk = dkk > 0.0 ? sqrt(dkk) : 1.0;
       if (tid == 0 && !(dkk > 0.0)) sh.notpd |= 1;
@@ -541,6 +616,11 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
     }
     int status = 0;
     if (sh.notpd) status |= (sh.notpd & 2) ? CAVDFTB_ST_NAN : CAVDFTB_ST_NOT_PD;
+    for (int i = tid; i < n; i += NT) {
+      sW[i] = i < nocc ? 2.0 : 0.0;
+      sOcc[i] = i;
+    }
+    bool ordered = warm;  // stored bases keep the occupied orbitals first
 
     int it = 0;
     double res_prev = INFINITY;  // no charge residual known before the first iteration
@@ -571,7 +651,140 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
             }
         __syncthreads();
 
-        // ---- cyclic parallel Jacobi on A, rotations accumulated into X
+        // ---- occupied-virtual step.  With the occupied columns first, rotate X by
+        // the exactly orthogonal Cayley transform U = (I + B)(I - B)^{-1},
+        // B = [[0, L], [-L^T, 0]], L = K / 2, where K (n_occ x n_v) solves the
+        // first-order decoupling condition K A_vv - A_oo K = A_ov (Jacobi sweeps
+        // on the Sylvester equation from K = A_ov / (d_v - d_o)).  Then
+        //   X_occ <- X_occ - Z K^T - 2 X_v Y^T,  X_v <- X_v + 2 Z + 2 X_v (G - I),
+        // G = (I + L^T L)^{-1} (Neumann series), Y = L G, Z = X_occ Y.
+        const int nv = n - nocc;
+        bool use_ov = false;
+        double kmax = 0.0;
+        if (ordered && nocc > 0 && nv > 0 && 2 * nv <= n) {  // K ping-pong needs 2 n_v <= n
+          double st[4] = {0.0, 0.0, -INFINITY, -INFINITY};  // off-block, ov, max d_o, -min d_v
+          for (int i = rgrp; i < n; i += RG)
+            for (int j = lane; j < n; j += 64) {
+              const double v = sA[i * LD + j];
+              if (i == j) {
+                if (i < nocc) st[2] = fmax(st[2], v);
+                else st[3] = fmax(st[3], -v);
+              } else if ((i < nocc) == (j < nocc)) {
+                st[0] = fmax(st[0], fabs(v));
+              } else {
+                st[1] = fmax(st[1], fabs(v));
+              }
+            }
+          block_max_n<NT, 4>(st, sRed);
+          const double gap = -st[3] - st[2];
+          use_ov = gap > kOvGap && st[1] < kOvAngle * gap && st[0] < kOvOff * gap;
+          double lf2 = 0.0;  // ||L||_F^2
+          if (use_ov) {
+            const int nk = nocc * nv;
+            for (int e = tid; e < nk; e += NT) {
+              const int i = e / nv, c = e - i * nv;
+              sT[i * LD + c] = sA[i * LD + nocc + c] / (sA[(nocc + c) * LD + nocc + c] - sA[i * LD + i]);
+            }
+            __syncthreads();
+            for (int sw = 0; sw < kSylvester; ++sw) {
+              const int src = (sw & 1) ? nv : 0, dst = (sw & 1) ? 0 : nv;
+              double km = 0.0, k2 = 0.0;
+              for (int e = tid; e < nk; e += NT) {
+                const int i = e / nv, c = e - i * nv;
+                double r = sA[i * LD + nocc + c];
+                for (int b = 0; b < nv; ++b) r -= sT[i * LD + src + b] * sA[(nocc + b) * LD + nocc + c];
+                for (int j = 0; j < nocc; ++j) r += sA[i * LD + j] * sT[j * LD + src + c];
+                const double kn = sT[i * LD + src + c] + r / (sA[(nocc + c) * LD + nocc + c] - sA[i * LD + i]);
+                sT[i * LD + dst + c] = kn;
+                km = fmax(km, fabs(kn));
+                k2 += kn * kn;
+              }
+              if (sw == kSylvester - 1) {
+                double v2[2] = {km, k2};
+                block_max_n<NT, 2>(v2, sRed);  // orders the writes of K as well
+                kmax = v2[0];
+                lf2 = 0.25 * block_sum<NT>(k2, sRed);
+                if (!(kmax < INFINITY)) lf2 = INFINITY;
+              } else {
+                __syncthreads();
+              }
+            }
+            use_ov = lf2 <= kOvNorm;
+          }
+          if (use_ov) {
+            // M = L^T L -> sA rows [0,nv) cols [0,nv); term_0 = I -> sA rows [nv,2nv) cols [0,nv);
+            // G = I -> sT rows [nocc, n) cols [0, nv)
+            for (int e = tid; e < nv * nv; e += NT) {
+              const int c = e / nv, b = e - c * nv;
+              double m = 0.0;
+              for (int i = 0; i < nocc; ++i) m += sT[i * LD + c] * sT[i * LD + b];
+              sA[c * LD + b] = 0.25 * m;
+              sA[(nv + c) * LD + b] = (c == b) ? 1.0 : 0.0;
+              sT[(nocc + c) * LD + b] = (c == b) ? 1.0 : 0.0;
+            }
+            __syncthreads();
+            // Neumann terms term_k = -M term_{k-1}, G += term_k, until ||L||_F^{2(k+1)} < 1e-17
+            int src = 0;
+            for (double bound = lf2; bound > 1.0e-17; bound *= lf2) {
+              const int dst = nv - src;
+              for (int e = tid; e < nv * nv; e += NT) {
+                const int c = e / nv, b = e - c * nv;
+                double t = 0.0;
+                for (int d = 0; d < nv; ++d) t -= sA[c * LD + d] * sA[(nv + d) * LD + src + b];
+                sA[(nv + c) * LD + dst + b] = t;
+                sT[(nocc + c) * LD + b] += t;
+              }
+              __syncthreads();
+              src = dst;
+            }
+            // Y = L G -> sT rows [0,nocc) cols [nv, 2nv)
+            for (int e = tid; e < nocc * nv; e += NT) {
+              const int i = e / nv, c = e - i * nv;
+              double y = 0.0;
+              for (int b = 0; b < nv; ++b) y += sT[i * LD + b] * sT[(nocc + b) * LD + c];
+              sT[i * LD + nv + c] = 0.5 * y;
+            }
+            __syncthreads();
+            // Z = X_occ Y -> sA cols [0, nv)
+            for (int e = tid; e < n * nv; e += NT) {
+              const int r = e / nv, c = e - r * nv;
+              double z = 0.0;
+              for (int i = 0; i < nocc; ++i) z += sX[r * LD + i] * sT[i * LD + nv + c];
+              sA[r * LD + c] = z;
+            }
+            __syncthreads();
+            // X_occ in place; new X_v -> sA cols [nv, 2nv)
+            for (int r = rgrp; r < n; r += RG)
+              for (int c = lane; c < n; c += 64) {
+                if (c < nocc) {
+                  double x = sX[r * LD + c];
+                  for (int b = 0; b < nv; ++b)
+                    x -= sA[r * LD + b] * sT[c * LD + b] + 2.0 * sX[r * LD + nocc + b] * sT[c * LD + nv + b];
+                  sX[r * LD + c] = x;
+                } else {
+                  const int cv = c - nocc;
+                  double x = sX[r * LD + c] + 2.0 * sA[r * LD + cv];
+                  for (int b = 0; b < nv; ++b)
+                    x += 2.0 * sX[r * LD + nocc + b] * (sT[(nocc + b) * LD + cv] - (b == cv ? 1.0 : 0.0));
+                  sA[r * LD + nv + cv] = x;
+                }
+              }
+            __syncthreads();
+            for (int r = rgrp; r < n; r += RG)
+              for (int c = lane; c < nv; c += 64) sX[r * LD + nocc + c] = sA[r * LD + nv + c];
+            __syncthreads();
+            if (tid == 0) {
+              sh.homo = st[2];
+              sh.lumo = -st[3];
+            }
+          }
+        }
+
+        // ---- cyclic parallel Jacobi on A, rotations accumulated into X; then
+        // the columns of X are sorted by eigenvalue (occupied first)
+        if (!use_ov) {
+        kmax = 0.0;
+        if (tid == 0) sh.jac_iters += 1;
         const int half = n / 2;
         double thr = kJacobiThr;
         for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
@@ -667,7 +880,6 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
           }
         }
 
-        // ---- aufbau occupation from the eigenvalues on the diagonal
         for (int i = tid; i < n; i += NT) sEig[i] = sA[i * LD + i];
         __syncthreads();
         for (int i = tid; i < n; i += NT) {
@@ -677,12 +889,23 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
             const double lj = sEig[j];
             rank += (lj < li || (lj == li && j < i)) ? 1 : 0;
           }
-          sW[i] = rank < nocc ? 2.0 : 0.0;
-          if (rank < nocc) sOcc[rank] = i;
+          sRank[i] = rank;
+          sQorb[rank] = li;
           if (rank == nocc - 1) sh.homo = li;
           if (rank == nocc) sh.lumo = li;
         }
         __syncthreads();
+        for (int r = rgrp; r < n; r += RG)
+          for (int c = lane; c < n; c += 64) sT[r * LD + sRank[c]] = sX[r * LD + c];
+        for (int i = tid; i < n; i += NT) sEig[i] = sQorb[i];
+        __syncthreads();
+        double* tmp = sX;
+        sX = sT;
+        sT = tmp;
+        ordered = true;
+        }  // full Jacobi
+
+        // ---- aufbau: the first n_occ columns of X are the occupied orbitals
         // ---- P = 2 C_occ C_occ^T into sT ; Mulliken charges (P, S symmetric: column sums)
         gemm_xwxt<NMAX, NT>(sX, sW, sOcc, nocc, n, sT);
         __syncthreads();
@@ -701,7 +924,7 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
           res = (dlt == dlt) ? fmax(res, dlt) : INFINITY;
         }
         res = block_max<NT>(res, sRed);
-        if (res < a.tol) break;  // block-uniform
+        if (res < a.tol && kmax < 10.0 * a.tol) break;  // block-uniform
         if (!(res < INFINITY)) {
           status |= CAVDFTB_ST_NAN;
           break;
@@ -829,15 +1052,22 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
         if (a.charges) a.charges[a0 + t] = -sDqOut[t];
     }
     if ((a.flags & JF_FORCES) && disp < 0) {  // undisplaced and field jobs
-      // V from the output charges (with the field potential); W = 2 C_occ eps C_occ^T into sA
+      // W = 2 C_occ diag(eps_occ) C_occ^T = 1/2 P H P with H of the last iteration
+      // (sV still holds its V; X_occ spans the occupied eigenspace, so no
+      // eigenvalues are needed).  X is free after the basis store above.
+      for (int i = rgrp; i < n; i += RG)
+        for (int j = lane; j < n; j += 64)
+          sA[i * LD + j] = 0.5 * (gH0[i * NMAX + j] + 0.5 * gS[i * NMAX + j] * (sV[sOrbAtom[i]] + sV[sOrbAtom[j]]));
+      __syncthreads();
+      gemm<NMAX, NT, false>(sA, sT, sX, n);  // (H / 2) P
+      __syncthreads();
+      gemm<NMAX, NT, false>(sT, sX, sA, n);  // W = P (H / 2) P
+      // V from the output charges (with the field potential)
       for (int t = tid; t < na; t += NT) {
         double v = sh.fld[0] * sPos[t * 3] + sh.fld[1] * sPos[t * 3 + 1] + sh.fld[2] * sPos[t * 3 + 2];
         for (int c = 0; c < na; ++c) v += gG[c * NMAX + t] * sDqOut[c];
         sV[t] = v;
       }
-      for (int i = tid; i < n; i += NT) sQorb[i] = sW[i] * sEig[i];  // occupation x eigenvalue
-      __syncthreads();
-      gemm_xwxt<NMAX, NT>(sX, sQorb, sOcc, nocc, n, sA);
       __syncthreads();
       double ebp = 0.0;
       for (int i = rgrp; i < n; i += RG)
@@ -873,7 +1103,8 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
         if (part == 0)  // direct force of the field on the atom's excess charge
           for (int g = 0; g < 3; ++g) fa[g] -= sDqOut[A] * sh.fld[g];
       }
-      __syncthreads();  // sF may alias sX
+      __syncthreads();  // sF may alias the X buffer
+      double* sF = F_IN_X ? sX : sFbuf;
       for (int g = 0; g < 3; ++g) sF[tid * 3 + g] = fa[g];
       const double etot = block_sum<NT>(ebp + ecp + erp, sRed);  // contains the barrier for sF
       double* fo = disp == -1 ? a.forces : (a.f_job ? a.f_job + (int64_t)fcode * a.n_atoms * 3 : nullptr);
@@ -899,6 +1130,7 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
         atomicAdd(&a.counters[1], (unsigned long long)it);
         atomicAdd(&a.counters[2], per_it * (unsigned long long)it + per_geo);
         atomicAdd(&a.counters[3], (unsigned long long)sh.sweeps);
+        atomicAdd(&a.counters[5], (unsigned long long)sh.jac_iters);
       }
     }
     __syncthreads();
