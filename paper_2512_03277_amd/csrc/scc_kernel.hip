@@ -44,7 +44,7 @@ constexpr double kOvGap = 0.02;
 constexpr double kOvAngle = 0.1;
 constexpr double kOvOff = 0.2;
 constexpr double kOvNorm = 1.0e-2;  // bound on ||L||_F^2 for the Neumann series of (I + L^T L)^{-1}
-constexpr int kSylvester = 2;       // even: the final K lands in the first slot
+constexpr int kSylvester = 2;       // Jacobi sweeps on the Sylvester equation
 
 // ---------------------------------------------------------------- SK rules
 __device__ __forceinline__ void radial(const DevParams& P, int t, double r, double& h, double& s, double& hp,
@@ -251,6 +251,21 @@ __device__ double block_max(double v, double* red) {
   return r;
 }
 
+// value of v held by lane k of the wave (k uniform)
+__device__ __forceinline__ double lane_bcast(double v, int k) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), k);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), k);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// orders the LDS accesses of one wave across this point (no workgroup barrier)
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 // K maxima at once (v updated in place)
 template <int NT, int K>
 __device__ void block_max_n(double (&v)[K], double* red) {
@@ -288,30 +303,58 @@ struct Cfg {
   static_assert(TM * G == NMAX, "tile mismatch");
 };
 
-// C = op(A) B over the leading n x n block (op = transpose when TA); only the
-// n x n block of C is written, its zero padding is left untouched.
-template <int NMAX, int NT, bool TA>
-__device__ void gemm(const double* __restrict__ A, const double* __restrict__ B, double* __restrict__ C, int n) {
+// C[r][c] = scale sum_{k < kd} opA(r, k) opB(k, c) for r < nr, c < nc, with
+// opA(r, k) = A[r][k] (TA: A[k][r]) and opB(k, c) = B[k][c] (TB: B[c][k]); only
+// that block of C is written.  The k loop is unrolled by four with all loads of
+// a step issued before its multiply-adds (LDS latency is the bound at these
+// sizes); the summation order over k is the plain sequential one.
+template <int NMAX, int NT, bool TA, bool TB>
+__device__ void gemm_g(const double* __restrict__ A, const double* __restrict__ B, double* __restrict__ C, int nr,
+                       int nc, int kd, double scale) {
   constexpr int G = Cfg<NMAX, NT>::G, TMB = Cfg<NMAX, NT>::TMB, BLK = Cfg<NMAX, NT>::BLK, LD = Cfg<NMAX, NT>::LD;
+  constexpr bool FULL = (Cfg<NMAX, NT>::TM % TMB) == 0;  // every block row / column index < NMAX
   const int tx = threadIdx.x % G, ty = threadIdx.x / G;
-  for (int bi = 0; bi < n; bi += BLK)
-    for (int bj = 0; bj < n; bj += BLK) {
+  for (int bi = 0; bi < nr; bi += BLK)
+    for (int bj = 0; bj < nc; bj += BLK) {
+      int row[TMB], col[TMB];
+#pragma unroll
+      for (int r = 0; r < TMB; ++r) {
+        row[r] = bi + ty + G * r;
+        col[r] = bj + tx + G * r;
+        if (!FULL) {
+          row[r] = row[r] < NMAX ? row[r] : NMAX - 1;  // clamped rows/columns are computed, never stored
+          col[r] = col[r] < NMAX ? col[r] : NMAX - 1;
+        }
+      }
       double acc[TMB][TMB];
 #pragma unroll
       for (int r = 0; r < TMB; ++r)
 #pragma unroll
         for (int c = 0; c < TMB; ++c) acc[r][c] = 0.0;
-      for (int k = 0; k < n; ++k) {
+      constexpr int UK = TMB >= 4 ? 2 : 4;  // k unroll within the register budget
+      int k = 0;
+      for (; k + UK <= kd; k += UK) {
+        double av[UK][TMB], bv[UK][TMB];
+#pragma unroll
+        for (int u = 0; u < UK; ++u)
+#pragma unroll
+          for (int r = 0; r < TMB; ++r) {
+            av[u][r] = TA ? A[(k + u) * LD + row[r]] : A[row[r] * LD + k + u];
+            bv[u][r] = TB ? B[col[r] * LD + k + u] : B[(k + u) * LD + col[r]];
+          }
+#pragma unroll
+        for (int u = 0; u < UK; ++u)
+#pragma unroll
+          for (int r = 0; r < TMB; ++r)
+#pragma unroll
+            for (int c = 0; c < TMB; ++c) acc[r][c] = fma(av[u][r], bv[u][c], acc[r][c]);
+      }
+      for (; k < kd; ++k) {
         double av[TMB], bv[TMB];
 #pragma unroll
         for (int r = 0; r < TMB; ++r) {
-          const int row = bi + ty + G * r;
-          av[r] = row < NMAX ? (TA ? A[k * LD + row] : A[row * LD + k]) : 0.0;
-        }
-#pragma unroll
-        for (int c = 0; c < TMB; ++c) {
-          const int col = bj + tx + G * c;
-          bv[c] = col < NMAX ? B[k * LD + col] : 0.0;
+          av[r] = TA ? A[k * LD + row[r]] : A[row[r] * LD + k];
+          bv[r] = TB ? B[col[r] * LD + k] : B[k * LD + col[r]];
         }
 #pragma unroll
         for (int r = 0; r < TMB; ++r)
@@ -322,52 +365,49 @@ __device__ void gemm(const double* __restrict__ A, const double* __restrict__ B,
       for (int r = 0; r < TMB; ++r)
 #pragma unroll
         for (int c = 0; c < TMB; ++c) {
-          const int row = bi + ty + G * r, col = bj + tx + G * c;
-          if (row < n && col < n) C[row * LD + col] = acc[r][c];
+          const int rr = bi + ty + G * r, cc = bj + tx + G * c;
+          if (rr < nr && cc < nc) C[rr * LD + cc] = scale * acc[r][c];
         }
     }
 }
 
-// C = X diag(w) X^T restricted to the columns listed in idx[0..m)
-template <int NMAX, int NT>
-__device__ void gemm_xwxt(const double* __restrict__ X, const double* __restrict__ w, const int* __restrict__ idx,
-                          int m, int n, double* __restrict__ C) {
-  constexpr int G = Cfg<NMAX, NT>::G, TMB = Cfg<NMAX, NT>::TMB, BLK = Cfg<NMAX, NT>::BLK, LD = Cfg<NMAX, NT>::LD;
-  const int tx = threadIdx.x % G, ty = threadIdx.x / G;
-  for (int bi = 0; bi < n; bi += BLK)
-    for (int bj = 0; bj < n; bj += BLK) {
-      double acc[TMB][TMB];
+// C = op(A) B over the leading n x n block (op = transpose when TA)
+template <int NMAX, int NT, bool TA>
+__device__ __forceinline__ void gemm(const double* __restrict__ A, const double* __restrict__ B,
+                                     double* __restrict__ C, int n) {
+  gemm_g<NMAX, NT, TA, false>(A, B, C, n, n, n, 1.0);
+}
+
+// sum_{k < len} a[k sa] b[k sb], loads issued four at a time, sequential order
+__device__ __forceinline__ double dotp(const double* __restrict__ a, int sa, const double* __restrict__ b, int sb,
+                                       int len) {
+  double s = 0.0;
+  int k = 0;
+  for (; k + 4 <= len; k += 4) {
+    double x[4], y[4];
 #pragma unroll
-      for (int r = 0; r < TMB; ++r)
-#pragma unroll
-        for (int c = 0; c < TMB; ++c) acc[r][c] = 0.0;
-      for (int kk = 0; kk < m; ++kk) {
-        const int k = idx[kk];
-        const double wk = w[k];
-        double av[TMB], bv[TMB];
-#pragma unroll
-        for (int r = 0; r < TMB; ++r) {
-          const int row = bi + ty + G * r;
-          av[r] = row < NMAX ? X[row * LD + k] * wk : 0.0;
-        }
-#pragma unroll
-        for (int c = 0; c < TMB; ++c) {
-          const int col = bj + tx + G * c;
-          bv[c] = col < NMAX ? X[col * LD + k] : 0.0;
-        }
-#pragma unroll
-        for (int r = 0; r < TMB; ++r)
-#pragma unroll
-          for (int c = 0; c < TMB; ++c) acc[r][c] = fma(av[r], bv[c], acc[r][c]);
-      }
-#pragma unroll
-      for (int r = 0; r < TMB; ++r)
-#pragma unroll
-        for (int c = 0; c < TMB; ++c) {
-          const int row = bi + ty + G * r, col = bj + tx + G * c;
-          if (row < n && col < n) C[row * LD + col] = acc[r][c];
-        }
+    for (int u = 0; u < 4; ++u) {
+      x[u] = a[(k + u) * sa];
+      y[u] = b[(k + u) * sb];
     }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s = fma(x[u], y[u], s);
+  }
+  for (; k < len; ++k) s = fma(a[k * sa], b[k * sb], s);
+  return s;
+}
+
+// e = q w + r (0 <= r < w) without an integer division: float reciprocal and one correction
+__device__ __forceinline__ void split_idx(int e, int w, float inv_w, int& q, int& r) {
+  q = (int)(((float)e + 0.5f) * inv_w);
+  r = e - q * w;
+  if (r < 0) {
+    --q;
+    r += w;
+  } else if (r >= w) {
+    ++q;
+    r -= w;
+  }
 }
 
 // index held by slot s in round r of the circle (round-robin) ordering of m indices
@@ -394,8 +434,8 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
   __shared__ double lT[GM ? 1 : NMAX * LD];
   __shared__ double sFbuf[F_IN_X ? 1 : 3 * NT];
   __shared__ double sPos[NMAX * 3];
-  __shared__ double sDqIn[NMAX], sDqOut[NMAX], sV[NMAX], sQ0[NMAX], sEig[NMAX], sW[NMAX], sQorb[NMAX];
-  __shared__ int sOrbAtom[NMAX], sAtomOff[NMAX + 1], sSp[NMAX], sOcc[NMAX], sRank[NMAX];
+  __shared__ double sDqIn[NMAX], sDqOut[NMAX], sV[NMAX], sQ0[NMAX], sEig[NMAX], sQorb[NMAX];
+  __shared__ int sOrbAtom[NMAX], sAtomOff[NMAX + 1], sSp[NMAX], sRank[NMAX];
   __shared__ double sRed[NT];
   __shared__ int sRp[2][HALF], sRq[2][HALF];
   __shared__ double sRc[2][HALF], sRs[2][HALF], sRt[2][HALF];
@@ -616,10 +656,6 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
     }
     int status = 0;
     if (sh.notpd) status |= (sh.notpd & 2) ? CAVDFTB_ST_NAN : CAVDFTB_ST_NOT_PD;
-    for (int i = tid; i < n; i += NT) {
-      sW[i] = i < nocc ? 2.0 : 0.0;
-      sOcc[i] = i;
-    }
     bool ordered = warm;  // stored bases keep the occupied orbitals first
 
     int it = 0;
@@ -628,9 +664,8 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
       for (it = 1; it <= a.max_iter; ++it) {
         // V = gamma Dq_in + field . R (gamma symmetric: column walk is coalesced)
         for (int t = tid; t < na; t += NT) {
-          double v = sh.fld[0] * sPos[t * 3] + sh.fld[1] * sPos[t * 3 + 1] + sh.fld[2] * sPos[t * 3 + 2];
-          for (int c = 0; c < na; ++c) v += gG[c * NMAX + t] * sDqIn[c];
-          sV[t] = v;
+          const double v = sh.fld[0] * sPos[t * 3] + sh.fld[1] * sPos[t * 3 + 1] + sh.fld[2] * sPos[t * 3 + 2];
+          sV[t] = v + dotp(gG + t, NMAX, sDqIn, 1, na);
         }
         __syncthreads();
         // H = H0 + 1/2 S o (V_a + V_b) into sA
@@ -679,21 +714,25 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
           const double gap = -st[3] - st[2];
           use_ov = gap > kOvGap && st[1] < kOvAngle * gap && st[0] < kOvOff * gap;
           double lf2 = 0.0;  // ||L||_F^2
+          const float inv_nv = 1.0f / (float)(nv > 0 ? nv : 1);
           if (use_ov) {
+            // slots of K: columns [0, nv) and [nv, 2 nv) of sT; the last sweep writes the first
             const int nk = nocc * nv;
+            const int s0 = (kSylvester & 1) ? nv : 0;
             for (int e = tid; e < nk; e += NT) {
-              const int i = e / nv, c = e - i * nv;
-              sT[i * LD + c] = sA[i * LD + nocc + c] / (sA[(nocc + c) * LD + nocc + c] - sA[i * LD + i]);
+              int i, c;
+              split_idx(e, nv, inv_nv, i, c);
+              sT[i * LD + s0 + c] = sA[i * LD + nocc + c] / (sA[(nocc + c) * LD + nocc + c] - sA[i * LD + i]);
             }
             __syncthreads();
             for (int sw = 0; sw < kSylvester; ++sw) {
-              const int src = (sw & 1) ? nv : 0, dst = (sw & 1) ? 0 : nv;
+              const int src = ((kSylvester - sw) & 1) ? nv : 0, dst = nv - src;
               double km = 0.0, k2 = 0.0;
               for (int e = tid; e < nk; e += NT) {
-                const int i = e / nv, c = e - i * nv;
-                double r = sA[i * LD + nocc + c];
-                for (int b = 0; b < nv; ++b) r -= sT[i * LD + src + b] * sA[(nocc + b) * LD + nocc + c];
-                for (int j = 0; j < nocc; ++j) r += sA[i * LD + j] * sT[j * LD + src + c];
+                int i, c;
+                split_idx(e, nv, inv_nv, i, c);
+                const double r = sA[i * LD + nocc + c] - dotp(sT + i * LD + src, 1, sA + nocc * LD + nocc + c, LD, nv) +
+                                 dotp(sA + i * LD, 1, sT + src + c, LD, nocc);
                 const double kn = sT[i * LD + src + c] + r / (sA[(nocc + c) * LD + nocc + c] - sA[i * LD + i]);
                 sT[i * LD + dst + c] = kn;
                 km = fmax(km, fabs(kn));
@@ -715,10 +754,9 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
             // M = L^T L -> sA rows [0,nv) cols [0,nv); term_0 = I -> sA rows [nv,2nv) cols [0,nv);
             // G = I -> sT rows [nocc, n) cols [0, nv)
             for (int e = tid; e < nv * nv; e += NT) {
-              const int c = e / nv, b = e - c * nv;
-              double m = 0.0;
-              for (int i = 0; i < nocc; ++i) m += sT[i * LD + c] * sT[i * LD + b];
-              sA[c * LD + b] = 0.25 * m;
+              int c, b;
+              split_idx(e, nv, inv_nv, c, b);
+              sA[c * LD + b] = 0.25 * dotp(sT + c, LD, sT + b, LD, nocc);
               sA[(nv + c) * LD + b] = (c == b) ? 1.0 : 0.0;
               sT[(nocc + c) * LD + b] = (c == b) ? 1.0 : 0.0;
             }
@@ -728,9 +766,9 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
             for (double bound = lf2; bound > 1.0e-17; bound *= lf2) {
               const int dst = nv - src;
               for (int e = tid; e < nv * nv; e += NT) {
-                const int c = e / nv, b = e - c * nv;
-                double t = 0.0;
-                for (int d = 0; d < nv; ++d) t -= sA[c * LD + d] * sA[(nv + d) * LD + src + b];
+                int c, b;
+                split_idx(e, nv, inv_nv, c, b);
+                const double t = -dotp(sA + c * LD, 1, sA + nv * LD + src + b, LD, nv);
                 sA[(nv + c) * LD + dst + b] = t;
                 sT[(nocc + c) * LD + b] += t;
               }
@@ -739,34 +777,28 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
             }
             // Y = L G -> sT rows [0,nocc) cols [nv, 2nv)
             for (int e = tid; e < nocc * nv; e += NT) {
-              const int i = e / nv, c = e - i * nv;
-              double y = 0.0;
-              for (int b = 0; b < nv; ++b) y += sT[i * LD + b] * sT[(nocc + b) * LD + c];
-              sT[i * LD + nv + c] = 0.5 * y;
+              int i, c;
+              split_idx(e, nv, inv_nv, i, c);
+              sT[i * LD + nv + c] = 0.5 * dotp(sT + i * LD, 1, sT + nocc * LD + c, LD, nv);
             }
             __syncthreads();
             // Z = X_occ Y -> sA cols [0, nv)
             for (int e = tid; e < n * nv; e += NT) {
-              const int r = e / nv, c = e - r * nv;
-              double z = 0.0;
-              for (int i = 0; i < nocc; ++i) z += sX[r * LD + i] * sT[i * LD + nv + c];
-              sA[r * LD + c] = z;
+              int r, c;
+              split_idx(e, nv, inv_nv, r, c);
+              sA[r * LD + c] = dotp(sX + r * LD, 1, sT + nv + c, LD, nocc);
             }
             __syncthreads();
             // X_occ in place; new X_v -> sA cols [nv, 2nv)
             for (int r = rgrp; r < n; r += RG)
               for (int c = lane; c < n; c += 64) {
                 if (c < nocc) {
-                  double x = sX[r * LD + c];
-                  for (int b = 0; b < nv; ++b)
-                    x -= sA[r * LD + b] * sT[c * LD + b] + 2.0 * sX[r * LD + nocc + b] * sT[c * LD + nv + b];
-                  sX[r * LD + c] = x;
+                  sX[r * LD + c] = sX[r * LD + c] - dotp(sA + r * LD, 1, sT + c * LD, 1, nv) -
+                                   2.0 * dotp(sX + r * LD + nocc, 1, sT + c * LD + nv, 1, nv);
                 } else {
-                  const int cv = c - nocc;
-                  double x = sX[r * LD + c] + 2.0 * sA[r * LD + cv];
-                  for (int b = 0; b < nv; ++b)
-                    x += 2.0 * sX[r * LD + nocc + b] * (sT[(nocc + b) * LD + cv] - (b == cv ? 1.0 : 0.0));
-                  sA[r * LD + nv + cv] = x;
+                  const int cv = c - nocc;  // X_v (G - I) = X_v G - X_v
+                  sA[r * LD + nv + cv] = 2.0 * dotp(sX + r * LD + nocc, 1, sT + nocc * LD + cv, LD, nv) -
+                                         sX[r * LD + c] + 2.0 * sA[r * LD + cv];
                 }
               }
             __syncthreads();
@@ -906,19 +938,19 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
         }  // full Jacobi
 
         // ---- aufbau: the first n_occ columns of X are the occupied orbitals
-        // ---- P = 2 C_occ C_occ^T into sT ; Mulliken charges (P, S symmetric: column sums)
-        gemm_xwxt<NMAX, NT>(sX, sW, sOcc, nocc, n, sT);
+        // ---- P = 2 C_occ C_occ^T into sT; Mulliken populations (P S)_ii = sum_j P_ji S_ji
+        // (P, S symmetric) as RG partial sums over j = rgrp (mod RG) in sA rows [0, RG)
+        gemm_g<NMAX, NT, false, true>(sX, sX, sT, n, n, nocc, 2.0);
         __syncthreads();
-        for (int i = tid; i < n; i += NT) {
-          double q = 0.0;
-          for (int j = 0; j < n; ++j) q += sT[j * LD + i] * gS[j * NMAX + i];
-          sQorb[i] = q;
-        }
+        for (int i = lane; i < n; i += 64)
+          sA[rgrp * LD + i] = dotp(sT + rgrp * LD + i, RG * LD, gS + rgrp * NMAX + i, RG * NMAX, (n - rgrp + RG - 1) / RG);
         __syncthreads();
         double res = 0.0;
         for (int t = tid; t < na; t += NT) {
           double q = 0.0;
-          for (int o = sAtomOff[t]; o < sAtomOff[t + 1]; ++o) q += sQorb[o];
+          for (int o = sAtomOff[t]; o < sAtomOff[t + 1]; ++o)
+#pragma unroll
+            for (int g = 0; g < RG; ++g) q += sA[g * LD + o];
           sDqOut[t] = q - sQ0[t];
           const double dlt = fabs(sDqOut[t] - sDqIn[t]);
           res = (dlt == dlt) ? fmax(res, dlt) : INFINITY;
@@ -940,67 +972,103 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
             part += df * df;
           }
           const double nrm = sqrt(block_sum<NT>(part, sRed));
-          if (nrm > 1.0e-300) {
-            slot_new = sh.bcount < kMaxHist ? sh.bcount : sh.bhead;
-            const double inrm = 1.0 / nrm;
-            for (int t = tid; t < na; t += NT) {
-              const double df = ((sDqOut[t] - sDqIn[t]) - bFp[t]) * inrm;
+          if (nrm > 1.0e-300) slot_new = sh.bcount < kMaxHist ? sh.bcount : sh.bhead;
+          const double inrm = slot_new >= 0 ? 1.0 / nrm : 0.0;
+          // new history pair; each thread then overwrites only the entries it read
+          for (int t = tid; t < na; t += NT) {
+            const double f = sDqOut[t] - sDqIn[t];
+            if (slot_new >= 0) {
+              const double df = (f - bFp[t]) * inrm;
               bDF[slot_new * NMAX + t] = df;
               bU[slot_new * NMAX + t] = a.alpha * df + (sDqIn[t] - bXp[t]) * inrm;
             }
-            __syncthreads();
-            if (tid == 0) {
-              if (sh.bcount < kMaxHist)
-                sh.bcount += 1;
-              else
-                sh.bhead = (sh.bhead + 1) % kMaxHist;
-            }
+            bXp[t] = sDqIn[t];
+            bFp[t] = f;
           }
-        }
-        for (int t = tid; t < na; t += NT) {
-          bXp[t] = sDqIn[t];
-          bFp[t] = sDqOut[t] - sDqIn[t];
+          __syncthreads();
+          if (tid == 0 && slot_new >= 0) {
+            if (sh.bcount < kMaxHist)
+              sh.bcount += 1;
+            else
+              sh.bhead = (sh.bhead + 1) % kMaxHist;
+          }
+        } else {
+          for (int t = tid; t < na; t += NT) {
+            bXp[t] = sDqIn[t];
+            bFp[t] = sDqOut[t] - sDqIn[t];
+          }
         }
         __syncthreads();
         const int m = sh.bcount;
         if (m > 0) {
-          // refresh the Gram row of the new slot, and c = dF . f
-          for (int k = tid; k < 2 * m; k += NT) {
-            const int kk = k < m ? k : k - m;
-            double s = 0.0;
-            if (k < m) {
-              if (slot_new >= 0) {
-                for (int t = 0; t < na; ++t) s += bDF[slot_new * NMAX + t] * bDF[kk * NMAX + t];
-                sBa[slot_new * kMaxHist + kk] = s;
-                sBa[kk * kMaxHist + slot_new] = s;
+          // Gram row of the new slot and c = dF . f: wave rgrp takes the dot products
+          // k = rgrp, rgrp + RG, ... (lanes over atoms); the history loads of a group of
+          // eight are all issued before the reductions
+          constexpr int KG = 8;
+          for (int k0 = rgrp; k0 < 2 * m; k0 += KG * RG) {
+            double sd[KG];
+#pragma unroll
+            for (int q = 0; q < KG; ++q) {
+              const int k = k0 + q * RG;
+              sd[q] = 0.0;
+              if (k < 2 * m && (k >= m || slot_new >= 0)) {
+                const int kk = k < m ? k : k - m;
+                const double* other = k < m ? bDF + slot_new * NMAX : bFp;
+                for (int t = lane; t < na; t += 64) sd[q] = fma(bDF[kk * NMAX + t], other[t], sd[q]);
               }
-            } else {
-              for (int t = 0; t < na; ++t) s += bDF[kk * NMAX + t] * bFp[t];
-              sBc[kk] = s;
+            }
+#pragma unroll
+            for (int q = 0; q < KG; ++q) {
+              const int k = k0 + q * RG;
+              const double v = wave_sum(sd[q]);
+              if (lane == 0 && k < 2 * m && (k >= m || slot_new >= 0)) {
+                if (k < m) {
+                  sBa[slot_new * kMaxHist + k] = v;
+                  sBa[k * kMaxHist + slot_new] = v;
+                } else {
+                  sBc[k - m] = v;
+                }
+              }
             }
           }
           __syncthreads();
-          for (int e = tid; e < m * (m + 1); e += NT) {
-            const int i = e / (m + 1), j = e % (m + 1);
-            sBm[i * (kMaxHist + 1) + j] =
-                j < m ? sBa[i * kMaxHist + j] + (i == j ? a.w0 * a.w0 : 0.0) : sBc[i];
+          // (w0^2 I + a) g = c by Gauss-Jordan in the first wave: lane l holds row l of the
+          // system padded to kMaxHist x kMaxHist with the identity (right-hand side in the
+          // last register); pivot rows are broadcast with readlane, no LDS traffic
+          if (tid < 64) {
+            int lt = tid;
+            asm volatile("" : "+v"(lt));  // keep the per-lane compares below inside this block
+            const double* ba = sBa + (lt < kMaxHist ? lt : 0) * kMaxHist;
+            const bool live = lt < m;
+            double row[kMaxHist + 1];
+#pragma unroll
+            for (int j = 0; j < kMaxHist; ++j) {
+              const double v = ba[j];
+              row[j] = (live && j < m) ? v + (lt == j ? a.w0 * a.w0 : 0.0) : (lt == j ? 1.0 : 0.0);
+            }
+            row[kMaxHist] = live ? sBc[lt] : 0.0;
+            for (int k = 0; k < m; ++k) {  // pivots beyond m are identity rows: nothing to eliminate
+              double rk = 0.0;  // row[k] without dynamic register indexing
+#pragma unroll
+              for (int j = 0; j < kMaxHist; ++j) rk = j == k ? row[j] : rk;
+              // broadcast outside any branch: lane k must hold rk when it is read
+              const double pk = lane_bcast(rk, k);
+              const double f = lt == k ? 0.0 : rk / pk;
+#pragma unroll
+              for (int j = 0; j <= kMaxHist; ++j) row[j] = fma(-f, lane_bcast(row[j], k), row[j]);
+            }
+            double rd = 1.0;
+#pragma unroll
+            for (int j = 0; j < kMaxHist; ++j) rd = j == lt ? row[j] : rd;
+            if (live) sBg[lt] = row[kMaxHist] / rd;
           }
-          __syncthreads();
-          // Gauss-Jordan on the SPD system (w0^2 I + a) g = c, one row per thread
-          for (int k = 0; k < m; ++k) {
-            double f = 0.0;
-            if (tid < m && tid != k) f = sBm[tid * (kMaxHist + 1) + k] / sBm[k * (kMaxHist + 1) + k];
-            __syncthreads();
-            if (tid < m && tid != k)
-              for (int j = k; j <= m; ++j) sBm[tid * (kMaxHist + 1) + j] -= f * sBm[k * (kMaxHist + 1) + j];
-            __syncthreads();
-          }
-          if (tid < m) sBg[tid] = sBm[tid * (kMaxHist + 1) + m] / sBm[tid * (kMaxHist + 1) + tid];
           __syncthreads();
         }
         for (int t = tid; t < na; t += NT) {
           double x = sDqIn[t] + a.alpha * bFp[t];
-          for (int k = 0; k < m; ++k) x -= sBg[k] * bU[k * NMAX + t];
+#pragma unroll
+          for (int k = 0; k < kMaxHist; ++k)
+            if (k < m) x = fma(-sBg[k], bU[k * NMAX + t], x);
           sDqIn[t] = x;
         }
         __syncthreads();
@@ -1064,9 +1132,8 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
       gemm<NMAX, NT, false>(sT, sX, sA, n);  // W = P (H / 2) P
       // V from the output charges (with the field potential)
       for (int t = tid; t < na; t += NT) {
-        double v = sh.fld[0] * sPos[t * 3] + sh.fld[1] * sPos[t * 3 + 1] + sh.fld[2] * sPos[t * 3 + 2];
-        for (int c = 0; c < na; ++c) v += gG[c * NMAX + t] * sDqOut[c];
-        sV[t] = v;
+        const double v = sh.fld[0] * sPos[t * 3] + sh.fld[1] * sPos[t * 3 + 1] + sh.fld[2] * sPos[t * 3 + 2];
+        sV[t] = v + dotp(gG + t, NMAX, sDqOut, 1, na);
       }
       __syncthreads();
       double ebp = 0.0;
