@@ -266,6 +266,25 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
+// v[0] <- block max, v[1] <- block sum (nw = waves per block)
+__device__ __forceinline__ void block_max_sum(double (&v)[2], double* red, int nw) {
+  v[0] = wave_max(v[0]);
+  v[1] = wave_sum(v[1]);
+  if ((threadIdx.x & 63) == 0) {
+    red[threadIdx.x >> 6] = v[0];
+    red[nw + (threadIdx.x >> 6)] = v[1];
+  }
+  __syncthreads();
+  double mx = red[0], sm = red[nw];
+  for (int w = 1; w < nw; ++w) {
+    mx = fmax(mx, red[w]);
+    sm += red[nw + w];
+  }
+  v[0] = mx;
+  v[1] = sm;
+  __syncthreads();
+}
+
 // K maxima at once (v updated in place)
 template <int NT, int K>
 __device__ void block_max_n(double (&v)[K], double* red) {
@@ -303,16 +322,20 @@ struct Cfg {
   static_assert(TM * G == NMAX, "tile mismatch");
 };
 
-// C[r][c] = scale sum_{k < kd} opA(r, k) opB(k, c) for r < nr, c < nc, with
-// opA(r, k) = A[r][k] (TA: A[k][r]) and opB(k, c) = B[k][c] (TB: B[c][k]); only
-// that block of C is written.  The k loop is unrolled by four with all loads of
-// a step issued before its multiply-adds (LDS latency is the bound at these
-// sizes); the summation order over k is the plain sequential one.
-template <int NMAX, int NT, bool TA, bool TB>
-__device__ void gemm_g(const double* __restrict__ A, const double* __restrict__ B, double* __restrict__ C, int nr,
-                       int nc, int kd, double scale) {
+// Register-blocked product over the leading nr x nc block:
+//   acc(r, c) = sum_{k < kd} opA(r, k) opB(k, c) + s2 sum_{k < kd2} A2[r][k] B2[k][c]
+// with opA(r, k) = A[r][k] (TA: A[k][r]) and opB(k, c) = B[k][c] (TB: B[c][k]);
+// epi(r, c, acc) consumes each element (the same thread owns (r, c) for equal nr,
+// nc, so consecutive products can chain through it without a barrier).  The k
+// loops are unrolled with all loads of a step issued before its multiply-adds
+// (LDS latency is the bound at these sizes); the order over k is sequential.
+template <int NMAX, int NT, bool TA, bool TB, class Epi>
+__device__ void gemm_e(const double* __restrict__ A, const double* __restrict__ B, int kd,
+                       const double* __restrict__ A2, const double* __restrict__ B2, int kd2, double s2, int nr,
+                       int nc, Epi epi) {
   constexpr int G = Cfg<NMAX, NT>::G, TMB = Cfg<NMAX, NT>::TMB, BLK = Cfg<NMAX, NT>::BLK, LD = Cfg<NMAX, NT>::LD;
   constexpr bool FULL = (Cfg<NMAX, NT>::TM % TMB) == 0;  // every block row / column index < NMAX
+  constexpr int UK = TMB >= 4 ? 2 : 4;                   // k unroll within the register budget
   const int tx = threadIdx.x % G, ty = threadIdx.x / G;
   for (int bi = 0; bi < nr; bi += BLK)
     for (int bj = 0; bj < nc; bj += BLK) {
@@ -331,7 +354,6 @@ __device__ void gemm_g(const double* __restrict__ A, const double* __restrict__ 
       for (int r = 0; r < TMB; ++r)
 #pragma unroll
         for (int c = 0; c < TMB; ++c) acc[r][c] = 0.0;
-      constexpr int UK = TMB >= 4 ? 2 : 4;  // k unroll within the register budget
       int k = 0;
       for (; k + UK <= kd; k += UK) {
         double av[UK][TMB], bv[UK][TMB];
@@ -361,14 +383,35 @@ __device__ void gemm_g(const double* __restrict__ A, const double* __restrict__ 
 #pragma unroll
           for (int c = 0; c < TMB; ++c) acc[r][c] = fma(av[r], bv[c], acc[r][c]);
       }
+      for (k = 0; k < kd2; ++k) {
+        double av[TMB], bv[TMB];
+#pragma unroll
+        for (int r = 0; r < TMB; ++r) {
+          av[r] = A2[row[r] * LD + k];
+          bv[r] = s2 * B2[k * LD + col[r]];
+        }
+#pragma unroll
+        for (int r = 0; r < TMB; ++r)
+#pragma unroll
+          for (int c = 0; c < TMB; ++c) acc[r][c] = fma(av[r], bv[c], acc[r][c]);
+      }
 #pragma unroll
       for (int r = 0; r < TMB; ++r)
 #pragma unroll
         for (int c = 0; c < TMB; ++c) {
           const int rr = bi + ty + G * r, cc = bj + tx + G * c;
-          if (rr < nr && cc < nc) C[rr * LD + cc] = scale * acc[r][c];
+          if (rr < nr && cc < nc) epi(rr, cc, acc[r][c]);
         }
     }
+}
+
+// C[r][c] = scale sum_{k < kd} opA(r, k) opB(k, c) over the leading nr x nc block
+template <int NMAX, int NT, bool TA, bool TB>
+__device__ __forceinline__ void gemm_g(const double* __restrict__ A, const double* __restrict__ B,
+                                       double* __restrict__ C, int nr, int nc, int kd, double scale) {
+  constexpr int LD = Cfg<NMAX, NT>::LD;
+  gemm_e<NMAX, NT, TA, TB>(A, B, kd, A, B, 0, 0.0, nr, nc,
+                           [=](int r, int c, double v) { C[r * LD + c] = scale * v; });
 }
 
 // C = op(A) B over the leading n x n block (op = transpose when TA)
@@ -697,6 +740,9 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
         bool use_ov = false;
         double kmax = 0.0;
         if (ordered && nocc > 0 && nv > 0 && 2 * nv <= n) {  // K ping-pong needs 2 n_v <= n
+          // one pass over A: block statistics, and K0 = A_ov / (d_v - d_o) into its slot of sT
+          // (slots: columns [0, nv) and [nv, 2 nv) of sT; the last Sylvester sweep writes the first)
+          const int s0 = (kSylvester & 1) ? nv : 0;
           double st[4] = {0.0, 0.0, -INFINITY, -INFINITY};  // off-block, ov, max d_o, -min d_v
           for (int i = rgrp; i < n; i += RG)
             for (int j = lane; j < n; j += 64) {
@@ -708,41 +754,32 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
                 st[0] = fmax(st[0], fabs(v));
               } else {
                 st[1] = fmax(st[1], fabs(v));
+                if (i < nocc) sT[i * LD + s0 + j - nocc] = v / (sA[j * LD + j] - sA[i * LD + i]);
               }
             }
-          block_max_n<NT, 4>(st, sRed);
+          block_max_n<NT, 4>(st, sRed);  // also orders the K0 writes
           const double gap = -st[3] - st[2];
           use_ov = gap > kOvGap && st[1] < kOvAngle * gap && st[0] < kOvOff * gap;
           double lf2 = 0.0;  // ||L||_F^2
-          const float inv_nv = 1.0f / (float)(nv > 0 ? nv : 1);
           if (use_ov) {
-            // slots of K: columns [0, nv) and [nv, 2 nv) of sT; the last sweep writes the first
-            const int nk = nocc * nv;
-            const int s0 = (kSylvester & 1) ? nv : 0;
-            for (int e = tid; e < nk; e += NT) {
-              int i, c;
-              split_idx(e, nv, inv_nv, i, c);
-              sT[i * LD + s0 + c] = sA[i * LD + nocc + c] / (sA[(nocc + c) * LD + nocc + c] - sA[i * LD + i]);
-            }
-            __syncthreads();
+            // Jacobi sweeps on K A_vv - A_oo K = A_ov:  K <- K + (A_ov - K A_vv + A_oo K) / D
             for (int sw = 0; sw < kSylvester; ++sw) {
               const int src = ((kSylvester - sw) & 1) ? nv : 0, dst = nv - src;
               double km = 0.0, k2 = 0.0;
-              for (int e = tid; e < nk; e += NT) {
-                int i, c;
-                split_idx(e, nv, inv_nv, i, c);
-                const double r = sA[i * LD + nocc + c] - dotp(sT + i * LD + src, 1, sA + nocc * LD + nocc + c, LD, nv) +
-                                 dotp(sA + i * LD, 1, sT + src + c, LD, nocc);
-                const double kn = sT[i * LD + src + c] + r / (sA[(nocc + c) * LD + nocc + c] - sA[i * LD + i]);
-                sT[i * LD + dst + c] = kn;
-                km = fmax(km, fabs(kn));
-                k2 += kn * kn;
-              }
+              gemm_e<NMAX, NT, false, false>(
+                  sA, sT + src, nocc, sT + src, sA + nocc * LD + nocc, nv, -1.0, nocc, nv,
+                  [&](int i, int c, double r) {
+                    const double kn = sT[i * LD + src + c] +
+                                      (sA[i * LD + nocc + c] + r) / (sA[(nocc + c) * LD + nocc + c] - sA[i * LD + i]);
+                    sT[i * LD + dst + c] = kn;
+                    km = fmax(km, fabs(kn));
+                    k2 = fma(kn, kn, k2);
+                  });
               if (sw == kSylvester - 1) {
                 double v2[2] = {km, k2};
-                block_max_n<NT, 2>(v2, sRed);  // orders the writes of K as well
+                block_max_sum(v2, sRed, NT / 64);  // orders the writes of K as well
                 kmax = v2[0];
-                lf2 = 0.25 * block_sum<NT>(k2, sRed);
+                lf2 = 0.25 * v2[1];
                 if (!(kmax < INFINITY)) lf2 = INFINITY;
               } else {
                 __syncthreads();
@@ -751,59 +788,42 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
             use_ov = lf2 <= kOvNorm;
           }
           if (use_ov) {
-            // M = L^T L -> sA rows [0,nv) cols [0,nv); term_0 = I -> sA rows [nv,2nv) cols [0,nv);
-            // G = I -> sT rows [nocc, n) cols [0, nv)
-            for (int e = tid; e < nv * nv; e += NT) {
-              int c, b;
-              split_idx(e, nv, inv_nv, c, b);
-              sA[c * LD + b] = 0.25 * dotp(sT + c, LD, sT + b, LD, nocc);
-              sA[(nv + c) * LD + b] = (c == b) ? 1.0 : 0.0;
-              sT[(nocc + c) * LD + b] = (c == b) ? 1.0 : 0.0;
-            }
+            // M = L^T L -> sA rows [0, nv); G_1 = I - M -> sT rows [nocc, n), columns [0, nv)
+            gemm_e<NMAX, NT, true, false>(sT, sT, nocc, sT, sT, 0, 0.0, nv, nv, [&](int c, int b, double v) {
+              const double mm = 0.25 * v;
+              sA[c * LD + b] = mm;
+              sT[(nocc + c) * LD + b] = (c == b ? 1.0 : 0.0) - mm;
+            });
             __syncthreads();
-            // Neumann terms term_k = -M term_{k-1}, G += term_k, until ||L||_F^{2(k+1)} < 1e-17
-            int src = 0;
-            for (double bound = lf2; bound > 1.0e-17; bound *= lf2) {
-              const int dst = nv - src;
-              for (int e = tid; e < nv * nv; e += NT) {
-                int c, b;
-                split_idx(e, nv, inv_nv, c, b);
-                const double t = -dotp(sA + c * LD, 1, sA + nv * LD + src + b, LD, nv);
-                sA[(nv + c) * LD + dst + b] = t;
-                sT[(nocc + c) * LD + b] += t;
-              }
+            // Horner steps G_j = I - M G_{j-1} (column blocks 0 / nv of sT rows [nocc, n))
+            // until the remainder ||M||^{j+1} <= ||L||_F^{2(j+1)} is below 1e-17
+            int gsrc = 0;
+            for (double bound = lf2 * lf2; bound > 1.0e-17; bound *= lf2) {
+              const int gdst = nv - gsrc;
+              gemm_e<NMAX, NT, false, false>(sA, sT + nocc * LD + gsrc, nv, sA, sA, 0, 0.0, nv, nv,
+                                             [&](int c, int b, double v) {
+                                               sT[(nocc + c) * LD + gdst + b] = (c == b ? 1.0 : 0.0) - v;
+                                             });
               __syncthreads();
-              src = dst;
+              gsrc = gdst;
             }
-            // Y = L G -> sT rows [0,nocc) cols [nv, 2nv)
-            for (int e = tid; e < nocc * nv; e += NT) {
-              int i, c;
-              split_idx(e, nv, inv_nv, i, c);
-              sT[i * LD + nv + c] = 0.5 * dotp(sT + i * LD, 1, sT + nocc * LD + c, LD, nv);
-            }
+            const double* Gm = sT + nocc * LD + gsrc;
+            // Y2 = K G -> sT rows [0, nocc), columns [nv, 2 nv)
+            gemm_e<NMAX, NT, false, false>(sT, Gm, nv, sT, sT, 0, 0.0, nocc, nv,
+                                           [&](int i, int c, double v) { sT[i * LD + nv + c] = v; });
             __syncthreads();
-            // Z = X_occ Y -> sA cols [0, nv)
-            for (int e = tid; e < n * nv; e += NT) {
-              int r, c;
-              split_idx(e, nv, inv_nv, r, c);
-              sA[r * LD + c] = dotp(sX + r * LD, 1, sT + nv + c, LD, nocc);
-            }
-            __syncthreads();
-            // X_occ in place; new X_v -> sA cols [nv, 2nv)
+            // Z = X_occ Y2 / 2 -> sA columns [0, nv); copy of X_v -> sA columns [nv, 2 nv)
+            gemm_e<NMAX, NT, false, false>(sX, sT + nv, nocc, sX, sX, 0, 0.0, n, nv,
+                                           [&](int r, int c, double v) { sA[r * LD + c] = 0.5 * v; });
             for (int r = rgrp; r < n; r += RG)
-              for (int c = lane; c < n; c += 64) {
-                if (c < nocc) {
-                  sX[r * LD + c] = sX[r * LD + c] - dotp(sA + r * LD, 1, sT + c * LD, 1, nv) -
-                                   2.0 * dotp(sX + r * LD + nocc, 1, sT + c * LD + nv, 1, nv);
-                } else {
-                  const int cv = c - nocc;  // X_v (G - I) = X_v G - X_v
-                  sA[r * LD + nv + cv] = 2.0 * dotp(sX + r * LD + nocc, 1, sT + nocc * LD + cv, LD, nv) -
-                                         sX[r * LD + c] + 2.0 * sA[r * LD + cv];
-                }
-              }
+              for (int c = lane; c < nv; c += 64) sA[r * LD + nv + c] = sX[r * LD + nocc + c];
             __syncthreads();
-            for (int r = rgrp; r < n; r += RG)
-              for (int c = lane; c < nv; c += 64) sX[r * LD + nocc + c] = sA[r * LD + nv + c];
+            // X_occ -= [Z | X_v] [K | Y2]^T ;  X_v <- 2 X_v G + 2 Z - X_v
+            gemm_e<NMAX, NT, false, true>(sA, sT, 2 * nv, sA, sA, 0, 0.0, n, nocc,
+                                          [&](int r, int c, double v) { sX[r * LD + c] -= v; });
+            gemm_e<NMAX, NT, false, false>(sA + nv, Gm, nv, sA, sA, 0, 0.0, n, nv, [&](int r, int c, double v) {
+              sX[r * LD + nocc + c] = 2.0 * v + 2.0 * sA[r * LD + c] - sA[r * LD + nv + c];
+            });
             __syncthreads();
             if (tid == 0) {
               sh.homo = st[2];
