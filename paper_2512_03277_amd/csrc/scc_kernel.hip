@@ -45,6 +45,7 @@ constexpr double kOvAngle = 0.1;
 constexpr double kOvOff = 0.2;
 constexpr double kOvNorm = 1.0e-2;  // bound on ||L||_F^2 for the Neumann series of (I + L^T L)^{-1}
 constexpr int kSylvester = 2;       // Jacobi sweeps on the Sylvester equation
+constexpr bool kMatrixCores = true; // dense products on the FP64 matrix cores (NMAX % 16 == 0)
 
 // ---------------------------------------------------------------- SK rules
 __device__ __forceinline__ void radial(const DevParams& P, int t, double r, double& h, double& s, double& hp,
@@ -330,24 +331,21 @@ struct Cfg {
 // loops are unrolled with all loads of a step issued before its multiply-adds
 // (LDS latency is the bound at these sizes); the order over k is sequential.
 template <int NMAX, int NT, bool TA, bool TB, class Epi>
-__device__ void gemm_e(const double* __restrict__ A, const double* __restrict__ B, int kd,
+__device__ void gemm_v(const double* __restrict__ A, const double* __restrict__ B, int kd,
                        const double* __restrict__ A2, const double* __restrict__ B2, int kd2, double s2, int nr,
                        int nc, Epi epi) {
   constexpr int G = Cfg<NMAX, NT>::G, TMB = Cfg<NMAX, NT>::TMB, BLK = Cfg<NMAX, NT>::BLK, LD = Cfg<NMAX, NT>::LD;
-  constexpr bool FULL = (Cfg<NMAX, NT>::TM % TMB) == 0;  // every block row / column index < NMAX
-  constexpr int UK = TMB >= 4 ? 2 : 4;                   // k unroll within the register budget
+  constexpr int UK = TMB >= 4 ? 2 : 4;  // k unroll within the register budget
   const int tx = threadIdx.x % G, ty = threadIdx.x / G;
   for (int bi = 0; bi < nr; bi += BLK)
     for (int bj = 0; bj < nc; bj += BLK) {
+      // rows / columns past the logical nr x nc block are clamped onto its last row /
+      // column: every read stays inside the operands, the extra results are not stored
       int row[TMB], col[TMB];
 #pragma unroll
       for (int r = 0; r < TMB; ++r) {
-        row[r] = bi + ty + G * r;
-        col[r] = bj + tx + G * r;
-        if (!FULL) {
-          row[r] = row[r] < NMAX ? row[r] : NMAX - 1;  // clamped rows/columns are computed, never stored
-          col[r] = col[r] < NMAX ? col[r] : NMAX - 1;
-        }
+        row[r] = min(bi + ty + G * r, nr - 1);
+        col[r] = min(bj + tx + G * r, nc - 1);
       }
       double acc[TMB][TMB];
 #pragma unroll
@@ -405,12 +403,68 @@ __device__ void gemm_e(const double* __restrict__ A, const double* __restrict__ 
     }
 }
 
+// The same product on the FP64 matrix cores (v_mfma_f64_16x16x4): 16 x 16 output
+// tiles dealt round-robin to the waves, four k per instruction.  Lane l feeds
+// A[t_r + l % 16][k0 + l / 16] and B[k0 + l / 16][t_c + l % 16] and receives
+// C[t_r + l / 16 + 4 i][t_c + l % 16] in accumulator i.  Rows, columns and k past
+// the logical operands read as zero (no access outside them); the extra results
+// are never passed to epi.
+typedef double mfma_acc4 __attribute__((ext_vector_type(4)));
+template <int NMAX, int NT, bool TA, bool TB, class Epi>
+__device__ void gemm_m(const double* __restrict__ A, const double* __restrict__ B, int kd,
+                       const double* __restrict__ A2, const double* __restrict__ B2, int kd2, double s2, int nr,
+                       int nc, Epi epi) {
+  static_assert(NMAX % 16 == 0, "matrix-core tiles need NMAX % 16 == 0");
+  constexpr int LD = Cfg<NMAX, NT>::LD;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int tr = (nr + 15) >> 4, tcn = (nc + 15) >> 4;
+  for (int t = wave; t < tr * tcn; t += NT / 64) {
+    const int r0 = (t / tcn) * 16, c0 = (t % tcn) * 16;
+    mfma_acc4 acc = {0.0, 0.0, 0.0, 0.0};
+    const int ra = r0 + li, cb = c0 + li;
+    const bool rin = ra < nr, cin = cb < nc;
+    for (int k0 = 0; k0 < kd; k0 += 4) {
+      const int k = k0 + lk;
+      const bool kin = k < kd;
+      const double av = (kin && rin) ? (TA ? A[k * LD + ra] : A[ra * LD + k]) : 0.0;
+      const double bv = (kin && cin) ? (TB ? B[cb * LD + k] : B[k * LD + cb]) : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+    }
+    for (int k0 = 0; k0 < kd2; k0 += 4) {
+      const int k = k0 + lk;
+      const bool kin = k < kd2;
+      const double av = (kin && rin) ? A2[ra * LD + k] : 0.0;
+      const double bv = (kin && cin) ? s2 * B2[k * LD + cb] : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int rr = r0 + lk + 4 * i, cc = c0 + li;
+      if (rr < nr && cc < nc) epi(rr, cc, acc[i]);
+    }
+  }
+}
+
+// small products (the occupied-virtual step) on the matrix cores where the tiles fit
+// the buffers, else on the vector units; the n x n products stay on the vector units
+// (gemm_g), which measured faster for them at these sizes
+template <int NMAX, int NT, bool TA, bool TB, class Epi>
+__device__ __forceinline__ void gemm_e(const double* __restrict__ A, const double* __restrict__ B, int kd,
+                                       const double* __restrict__ A2, const double* __restrict__ B2, int kd2,
+                                       double s2, int nr, int nc, Epi epi) {
+  if constexpr (kMatrixCores && NMAX % 16 == 0)
+    gemm_m<NMAX, NT, TA, TB>(A, B, kd, A2, B2, kd2, s2, nr, nc, epi);
+  else
+    gemm_v<NMAX, NT, TA, TB>(A, B, kd, A2, B2, kd2, s2, nr, nc, epi);
+}
+
 // C[r][c] = scale sum_{k < kd} opA(r, k) opB(k, c) over the leading nr x nc block
 template <int NMAX, int NT, bool TA, bool TB>
 __device__ __forceinline__ void gemm_g(const double* __restrict__ A, const double* __restrict__ B,
                                        double* __restrict__ C, int nr, int nc, int kd, double scale) {
   constexpr int LD = Cfg<NMAX, NT>::LD;
-  gemm_e<NMAX, NT, TA, TB>(A, B, kd, A, B, 0, 0.0, nr, nc,
+  gemm_v<NMAX, NT, TA, TB>(A, B, kd, A, B, 0, 0.0, nr, nc,
                            [=](int r, int c, double v) { C[r * LD + c] = scale * v; });
 }
 
