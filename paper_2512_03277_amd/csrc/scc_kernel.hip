@@ -1083,12 +1083,20 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
             double sd[KG];
 #pragma unroll
             for (int q = 0; q < KG; ++q) {
+              // loads are unconditional (always inside the history block) so that they issue
+              // together; unused products are masked afterwards
               const int k = k0 + q * RG;
-              sd[q] = 0.0;
-              if (k < 2 * m && (k >= m || slot_new >= 0)) {
-                const int kk = k < m ? k : k - m;
-                const double* other = k < m ? bDF + slot_new * NMAX : bFp;
+              const bool use = k < 2 * m && (k >= m || slot_new >= 0);
+              const int kk = k < m ? k : (k - m < kMaxHist ? k - m : 0);
+              const double* other = (k < m && slot_new >= 0) ? bDF + slot_new * NMAX : bFp;
+              if constexpr (NMAX <= 64) {
+                const int t = lane < NMAX ? lane : 0;
+                const double x = bDF[kk * NMAX + t], y = other[t];
+                sd[q] = (use && lane < na) ? x * y : 0.0;
+              } else {
+                sd[q] = 0.0;
                 for (int t = lane; t < na; t += 64) sd[q] = fma(bDF[kk * NMAX + t], other[t], sd[q]);
+                if (!use) sd[q] = 0.0;
               }
             }
 #pragma unroll
@@ -1121,15 +1129,17 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
               row[j] = (live && j < m) ? v + (lt == j ? a.w0 * a.w0 : 0.0) : (lt == j ? 1.0 : 0.0);
             }
             row[kMaxHist] = live ? sBc[lt] : 0.0;
-            for (int k = 0; k < m; ++k) {  // pivots beyond m are identity rows: nothing to eliminate
-              double rk = 0.0;  // row[k] without dynamic register indexing
+            // pivots beyond m are identity rows: nothing to eliminate.  Columns left of the
+            // pivot are already zero in the pivot row and are skipped.
 #pragma unroll
-              for (int j = 0; j < kMaxHist; ++j) rk = j == k ? row[j] : rk;
-              // broadcast outside any branch: lane k must hold rk when it is read
-              const double pk = lane_bcast(rk, k);
-              const double f = lt == k ? 0.0 : rk / pk;
+            for (int k = 0; k < kMaxHist; ++k) {
+              if (k < m) {
+                // broadcast outside any lane-dependent branch: lane k must hold row[k] when read
+                const double pk = lane_bcast(row[k], k);
+                const double f = lt == k ? 0.0 : row[k] / pk;
 #pragma unroll
-              for (int j = 0; j <= kMaxHist; ++j) row[j] = fma(-f, lane_bcast(row[j], k), row[j]);
+                for (int j = k + 1; j <= kMaxHist; ++j) row[j] = fma(-f, lane_bcast(row[j], k), row[j]);
+              }
             }
             double rd = 1.0;
 #pragma unroll
@@ -1140,9 +1150,16 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
         }
         for (int t = tid; t < na; t += NT) {
           double x = sDqIn[t] + a.alpha * bFp[t];
+          constexpr int UG = kMaxHist / 2;  // history loads issued in two groups, unconditionally
 #pragma unroll
-          for (int k = 0; k < kMaxHist; ++k)
-            if (k < m) x = fma(-sBg[k], bU[k * NMAX + t], x);
+          for (int k0 = 0; k0 < kMaxHist; k0 += UG) {
+            double uv[UG];
+#pragma unroll
+            for (int q = 0; q < UG; ++q) uv[q] = bU[(k0 + q) * NMAX + t];
+#pragma unroll
+            for (int q = 0; q < UG; ++q)
+              if (k0 + q < m) x = fma(-sBg[k0 + q], uv[q], x);
+          }
           sDqIn[t] = x;
         }
         __syncthreads();
