@@ -536,6 +536,7 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
   __shared__ double sRed[NT];
   __shared__ int sRp[2][HALF], sRq[2][HALF];
   __shared__ double sRc[2][HALF], sRs[2][HALF], sRt[2][HALF];
+  __shared__ double lDF[kMaxHist * NMAX];  // Broyden dF history of the job (LDS copy)
   __shared__ double sBa[kMaxHist * kMaxHist], sBm[kMaxHist * (kMaxHist + 1)], sBc[kMaxHist], sBg[kMaxHist];
   __shared__ Shared sh;
 
@@ -576,8 +577,11 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
     // a workgroup copy of it for displaced jobs (read-only use of the store)
     double* hst = a.hist ? a.hist + a.hist_off[u] : nullptr;  // [count, head, Gram H*H, dF H*NMAX, U H*NMAX]
     const bool own_hist = hst && disp == -1 && (a.flags & JF_STORE_HIST);
-    double* bDF = own_hist ? hst + 2 + kMaxHist * kMaxHist : sDF;
-    double* bU = bDF + kMaxHist * NMAX;
+    // dF vectors in LDS (written through to the unit's store when it is owned), U
+    // vectors in the store (owned) or in the workgroup copy
+    double* bDF = lDF;
+    double* gDF = own_hist ? hst + 2 + kMaxHist * kMaxHist : nullptr;
+    double* bU = own_hist ? hst + 2 + kMaxHist * kMaxHist + kMaxHist * NMAX : sU;
 
     // ---- load atoms, clear the working matrices
     for (int t = tid; t < na; t += NT) {
@@ -632,11 +636,10 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
     {
       const int m0 = sh.bcount;
       for (int e = tid; e < m0 * kMaxHist; e += NT) sBa[e] = hst[2 + e];
-      if (!own_hist)
-        for (int e = tid; e < m0 * NMAX; e += NT) {
-          bDF[e] = hst[2 + kMaxHist * kMaxHist + e];
-          bU[e] = hst[2 + kMaxHist * kMaxHist + kMaxHist * NMAX + e];
-        }
+      for (int e = tid; e < m0 * NMAX; e += NT) {
+        bDF[e] = hst[2 + kMaxHist * kMaxHist + e];
+        if (!own_hist) bU[e] = hst[2 + kMaxHist * kMaxHist + kMaxHist * NMAX + e];
+      }
     }
 
     // ---- H0, S (global scratch) and gamma
@@ -770,6 +773,7 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
           for (int j = lane; j < n; j += 64)
             sA[i * LD + j] = gH0[i * NMAX + j] + 0.5 * gS[i * NMAX + j] * (sV[sOrbAtom[i]] + sV[sOrbAtom[j]]);
         __syncthreads();
+
         gemm<NMAX, NT, false>(sA, sX, sT, n);  // T = H X
         __syncthreads();
         gemm<NMAX, NT, true>(sX, sT, sA, n);  // A = X^T H X
@@ -1054,10 +1058,12 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
             if (slot_new >= 0) {
               const double df = (f - bFp[t]) * inrm;
               bDF[slot_new * NMAX + t] = df;
+              if (gDF) gDF[slot_new * NMAX + t] = df;
               bU[slot_new * NMAX + t] = a.alpha * df + (sDqIn[t] - bXp[t]) * inrm;
             }
             bXp[t] = sDqIn[t];
             bFp[t] = f;
+            sQorb[t] = f;  // LDS copy of the residual for the dot products below
           }
           __syncthreads();
           if (tid == 0 && slot_new >= 0) {
@@ -1070,50 +1076,30 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
           for (int t = tid; t < na; t += NT) {
             bXp[t] = sDqIn[t];
             bFp[t] = sDqOut[t] - sDqIn[t];
+            sQorb[t] = bFp[t];
           }
         }
         __syncthreads();
         const int m = sh.bcount;
         if (m > 0) {
-          // Gram row of the new slot and c = dF . f: wave rgrp takes the dot products
-          // k = rgrp, rgrp + RG, ... (lanes over atoms); the history loads of a group of
-          // eight are all issued before the reductions
-          constexpr int KG = 8;
-          for (int k0 = rgrp; k0 < 2 * m; k0 += KG * RG) {
-            double sd[KG];
-#pragma unroll
-            for (int q = 0; q < KG; ++q) {
-              // loads are unconditional (always inside the history block) so that they issue
-              // together; unused products are masked afterwards
-              const int k = k0 + q * RG;
-              const bool use = k < 2 * m && (k >= m || slot_new >= 0);
-              const int kk = k < m ? k : (k - m < kMaxHist ? k - m : 0);
-              const double* other = (k < m && slot_new >= 0) ? bDF + slot_new * NMAX : bFp;
-              if constexpr (NMAX <= 64) {
-                const int t = lane < NMAX ? lane : 0;
-                const double x = bDF[kk * NMAX + t], y = other[t];
-                sd[q] = (use && lane < na) ? x * y : 0.0;
+          // Gram row of the new slot and c = dF . f: lane k of the first wave takes dot
+          // product k whole (no cross-lane reduction); the solve below runs in the same
+          // wave, ordered by a wave-level barrier only
+          if (tid < 64) {
+            const int k = tid;
+            if (k < 2 * m && (k >= m || slot_new >= 0)) {
+              const int kk = k < m ? k : k - m;
+              const double* y = k < m ? bDF + slot_new * NMAX : sQorb;
+              const double sd = dotp(bDF + kk * NMAX, 1, y, 1, na);
+              if (k < m) {
+                sBa[slot_new * kMaxHist + kk] = sd;
+                sBa[kk * kMaxHist + slot_new] = sd;
               } else {
-                sd[q] = 0.0;
-                for (int t = lane; t < na; t += 64) sd[q] = fma(bDF[kk * NMAX + t], other[t], sd[q]);
-                if (!use) sd[q] = 0.0;
+                sBc[kk] = sd;
               }
             }
-#pragma unroll
-            for (int q = 0; q < KG; ++q) {
-              const int k = k0 + q * RG;
-              const double v = wave_sum(sd[q]);
-              if (lane == 0 && k < 2 * m && (k >= m || slot_new >= 0)) {
-                if (k < m) {
-                  sBa[slot_new * kMaxHist + k] = v;
-                  sBa[k * kMaxHist + slot_new] = v;
-                } else {
-                  sBc[k - m] = v;
-                }
-              }
-            }
+            wave_sync();
           }
-          __syncthreads();
           // (w0^2 I + a) g = c by Gauss-Jordan in the first wave: lane l holds row l of the
           // system padded to kMaxHist x kMaxHist with the identity (right-hand side in the
           // last register); pivot rows are broadcast with readlane, no LDS traffic
