@@ -7,7 +7,8 @@ replacement on the GPU with the library's own kernels:
   1. geometries from Mulliken-path cavity MD of 8-water clusters, plus
      sub-clusters of 1..7 waters cut from them (the surrogate is used on
      units of 1..8 waters);
-  2. exact finite-difference Born labels (cavdftb_born_charges, mode FD);
+  2. exact Born labels (cavdftb_born_charges: the force response to a uniform
+     field, six SCCs per unit; or central differences of the dipole);
   3. descriptors, local frames and local-frame targets (sg_features,
      sg_to_local), standardisation statistics (sg_moments, sg_prep);
   4. per species and ensemble member: bootstrap resample, minibatch Adam on the
@@ -70,10 +71,12 @@ def sub_clusters(system, pos, rng):
     return out
 
 
-def exact_born(params, system, pos_list, h=1e-3, tol=1e-10):
-    """Finite-difference Born charges and Mulliken charges for each position set
-    (device tensors [n_atoms, 3]); returns (born [n_snap, n_atoms, 9],
-    charges [n_snap, n_atoms], bad-unit count)."""
+def exact_born(params, system, pos_list, route="field", tol=1e-10):
+    """Exact Born charges (route "field": force response to a uniform field of
+    1e-4 a.u.; "fd": central differences of the dipole, h = 1e-3 bohr) and
+    Mulliken charges for each position set (device tensors [n_atoms, 3]);
+    returns (born [n_snap, n_atoms, 9], charges [n_snap, n_atoms], bad-unit count)."""
+    mode, h = (B.BORN_FIELD, 1e-4) if route == "field" else (B.BORN_FD, 1e-3)
     torch = _torch()
     dev = torch.device("cuda:0")
     ctx = B.context_from_system(params, system)
@@ -84,7 +87,7 @@ def exact_born(params, system, pos_list, h=1e-3, tol=1e-10):
     bad = 0
     for k, pos in enumerate(pos_list):
         ctx.eval_units(pos.contiguous(), charges=q[k], unit_status=st)
-        ctx.born_charges(pos.contiguous(), B.BORN_FD, h, out[k], st)
+        ctx.born_charges(pos.contiguous(), mode, h, out[k], st)
         bad += int((st != 0).sum())
     ctx.sync()
     ctx.close()
@@ -165,11 +168,11 @@ def train_network(feat, targ, norm, rng, epochs=40, batch=512, lr=2e-3, lr_final
     step = 0
     last = None
     for ep in range(epochs):
-        perm = sample[rng.permutation(N)]
+        perm = torch.tensor(sample[rng.permutation(N)].astype(np.int32), device=dev)  # one upload per epoch
         lr_ep = lr * (lr_final / lr) ** (ep / max(epochs - 1, 1))
         tot = torch.zeros(1, dtype=torch.float32, device=dev)
         for b in range(nb):
-            idx = torch.tensor(perm[b * batch:(b + 1) * batch].astype(np.int32), device=dev)
+            idx = perm[b * batch:(b + 1) * batch]
             B.sg_gather(x_all, idx, batch, B.SG_N_IN, xb)
             B.sg_gather(t_all, idx, batch, B.SG_N_OUT, tb)
             B.sg_forward(w, xb, batch, yb, act)
@@ -235,7 +238,8 @@ def evaluate(params_sg, norm_sg, params, system, pos_list, born_exact, h=1e-3, t
             "max_ensemble_std": max(max_std), "fallback_units": cnt_fallback}
 
 
-def build_training_set(params, n_units=1024, n_train=16, n_val=4, stride=10, n_sub=4, seed=0, log=None):
+def build_training_set(params, n_units=1024, n_train=16, n_val=4, stride=10, n_sub=4, seed=0, log=None,
+                       route="field"):
     """Geometries, exact labels and features for training and validation (time
     blocks: the validation snapshots come after the training ones)."""
     from cavgen import make_system
@@ -246,7 +250,7 @@ def build_training_set(params, n_units=1024, n_train=16, n_val=4, stride=10, n_s
     if log:
         log(f"sampled {n_train + n_val} snapshots of {n_units} units in {time.time() - t0:.1f} s")
     t0 = time.time()
-    born, charges, bad = exact_born(params, s, list(snaps))
+    born, charges, bad = exact_born(params, s, list(snaps), route=route)
     if log:
         log(f"exact Born labels: {len(snaps)} x {n_units} units in {time.time() - t0:.1f} s ({bad} bad units)")
     sub_pos, sub_sys = [], []
@@ -259,7 +263,7 @@ def build_training_set(params, n_units=1024, n_train=16, n_val=4, stride=10, n_s
     torch = _torch()
     for ss in sub_sys:
         p = [torch.tensor(ss["pos"], device=snaps.device)]
-        bz, qz, _ = exact_born(params, ss, p)
+        bz, qz, _ = exact_born(params, ss, p, route=route)
         f2, t2 = features_and_targets(params, ss, p, bz, qz)
         for sp in (0, 1):
             fe_t[sp] = torch.cat([fe_t[sp], f2[sp]])
@@ -276,6 +280,9 @@ def main(argv=None):
     ap.add_argument("--train-snapshots", type=int, default=16)
     ap.add_argument("--val-snapshots", type=int, default=4)
     ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--stride", type=int, default=10, help="MD steps between training snapshots")
+    ap.add_argument("--sub", type=int, default=4, help="snapshots also cut into 1..7-water sub-clusters")
+    ap.add_argument("--route", choices=["field", "fd"], default="field", help="exact route of the labels")
     ap.add_argument("--dump", default=None, help="also save a sample of the training rows (npz) for inspection")
     ap.add_argument("--no-train", action="store_true")
     ap.add_argument("--out", default=os.path.join(os.path.dirname(os.path.abspath(__file__)), "data",
@@ -287,7 +294,7 @@ def main(argv=None):
     def log(msg):
         print(msg, flush=True)
     data = build_training_set(params, n_units=args.units, n_train=args.train_snapshots, n_val=args.val_snapshots,
-                              log=log)
+                              stride=args.stride, n_sub=args.sub, log=log, route=args.route)
     fe, ta = data["train"]
     log(f"training atoms: O {fe[0].shape[0]}, H {fe[1].shape[0]}")
     if args.dump:
