@@ -119,14 +119,22 @@ int cavdftb_destroy(cavdftb_ctx* ctx);
 int cavdftb_set_scc(cavdftb_ctx* ctx, double tol, int32_t max_iter, double mix_alpha);
 
 /* Solver tuning (results are unchanged to within the SCC tolerance):
- *   jacobi_res_factor (default 1e-3): inside the SCC loop the Jacobi
- *     eigensolver stops once every off-diagonal element of the rotated
- *     Hamiltonian is below max(1e-14, jacobi_res_factor x previous charge
- *     residual); 0 means always 1e-14 (hartree).
+ *   jacobi_res_factor (default 1e-3): in SCC iterations that diagonalise by
+ *     full Jacobi, the eigensolver stops once every off-diagonal element of the
+ *     rotated Hamiltonian is below max(1e-14, jacobi_res_factor x previous
+ *     charge residual); 0 means always 1e-14 (hartree).
  *   keep_mixer_history (default 1): a unit's Broyden history survives between
  *     its evaluations (MD steps) and seeds its displaced finite-difference SCCs.
  * Returns CAVDFTB_EINVAL outside 0 <= jacobi_res_factor <= 1. */
 int cavdftb_set_tuning(cavdftb_ctx* ctx, double jacobi_res_factor, int32_t keep_mixer_history);
+
+/* Launch schedule of the SCC kernel.  job_queue != 0 (default): workgroups take
+ * the next job from a device queue, each bucket's units ordered largest first
+ * (longest-processing-time order); 0: a fixed stride over the job list.
+ * max_wg_per_cu > 0 caps the resident workgroups per CU of every bucket (at most
+ * what create sized the scratch for); 0 restores that maximum.  Results do not
+ * depend on either setting. */
+int cavdftb_set_schedule(cavdftb_ctx* ctx, int32_t job_queue, int32_t max_wg_per_cu);
 
 /* Warm start: when enabled (default 1) each unit evaluation starts from the
  * charges, the molecular-orbital basis and the mixer history its previous

@@ -56,6 +56,7 @@ SYMBOLS = {
     "cavdftb_init_photons": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "cavdftb_set_surrogate": (ctypes.c_int, [_vp, _vp, _vp, _c_d]),
     "cavdftb_set_fallback": (ctypes.c_int, [_vp, ctypes.c_int32]),
+    "cavdftb_set_schedule": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32]),
     "cavdftb_sg_features": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "cavdftb_sg_prep": (ctypes.c_int, [_vp, _vp, _c_i32, _c_i32, _vp, _vp, _vp]),
     "cavdftb_sg_forward": (ctypes.c_int, [_vp, _vp, _c_i32, _vp, _vp, _vp]),
@@ -187,6 +188,9 @@ class Context:
     def set_tuning(self, jacobi_res_factor=1e-3, keep_mixer_history=True):
         self._check(self.lib.cavdftb_set_tuning(self.ctx, float(jacobi_res_factor), int(bool(keep_mixer_history))),
                     "set_tuning")
+
+    def set_schedule(self, job_queue=True, max_wg_per_cu=0):
+        self._check(self.lib.cavdftb_set_schedule(self.ctx, int(bool(job_queue)), int(max_wg_per_cu)), "set_schedule")
 
     def set_warm_start(self, enable):
         self._check(self.lib.cavdftb_set_warm_start(self.ctx, int(bool(enable))), "set_warm_start")

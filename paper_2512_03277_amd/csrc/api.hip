@@ -4,6 +4,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <string>
 #include <utility>
@@ -40,7 +41,8 @@ int bucket_of(int n) {
 struct Bucket {
   int nmax = 0;
   int n_units = 0;
-  int n_wg = 0;
+  int n_wg = 0;         // workgroups of a launch (<= n_cu * per_cu_max)
+  int per_cu_max = 1;   // resident workgroups per CU the scratch was sized for
   int64_t scratch_per_wg = 0;
   int32_t* d_units = nullptr;  // center jobs: unit list
   int cjob0 = 0;               // offset of this bucket's center jobs in the center job arrays
@@ -94,6 +96,9 @@ struct cavdftb_ctx {
   int32_t *d_status = nullptr, *d_cjob_status = nullptr, *d_cjob_iters = nullptr;
   int32_t *d_fjob_status = nullptr, *d_fjob_iters = nullptr;
   unsigned long long* d_counters = nullptr;
+  unsigned int* d_job_counter = nullptr;  // job queue of the SCC launches (one launch at a time per stream)
+  int dynamic_jobs = 1;
+  int n_cu = 256;
   // learned Born-charge surrogate
   float* d_sg_params = nullptr;  // [2][members][N_PARAM]
   float* d_sg_norm = nullptr;    // [2][N_NORM]
@@ -202,6 +207,7 @@ SccArgs base_args(cavdftb_ctx* c, const double* pos) {
   a.hist_off = c->d_hist_off;
   a.jac_factor = c->jac_factor;
   a.counters = c->d_counters;
+  a.job_counter = c->dynamic_jobs ? c->d_job_counter : nullptr;
   a.tol = c->tol;
   a.max_iter = c->max_iter;
   a.alpha = c->alpha;
@@ -481,6 +487,7 @@ int cavdftb_create(const cavdftb_params* params, const cavdftb_layout* L, void* 
   hipGetDevice(&dev);
   hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
   if (n_cu <= 0) n_cu = 256;
+  c->n_cu = n_cu;
 
   const int* nmaxs = kBucketNmax;
   std::vector<int64_t> ws_off(U), hist_off(U);
@@ -495,6 +502,9 @@ int cavdftb_create(const cavdftb_params* params, const cavdftb_layout* L, void* 
     hist_off[u] = hist_total;
     hist_total += hist_doubles(nm);
   }
+  // largest units first in every bucket (longest-processing-time order for the job queue)
+  for (auto& v : bunits)
+    std::stable_sort(v.begin(), v.end(), [&](int x, int y) { return n_orb[x] > n_orb[y]; });
   hipError_t e = hipSuccess;
 #define CK(x)                                  \
   do {                                         \
@@ -562,6 +572,7 @@ int cavdftb_create(const cavdftb_params* params, const cavdftb_layout* L, void* 
     CK(hipMemcpy(c->d_n_sp, c->n_sp, 2 * sizeof(int32_t), hipMemcpyHostToDevice));
   }
   CK(dalloc(c, &c->d_counters, 8));
+  CK(dalloc(c, &c->d_job_counter, 1));
   CK(hipMemcpy(c->d_unit_off, c->h_unit_off.data(), (U + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
   CK(hipMemcpy(c->d_species, L->species, NA, hipMemcpyHostToDevice));
   CK(hipMemcpy(c->d_unit_x, L->unit_x, U * sizeof(double), hipMemcpyHostToDevice));
@@ -595,6 +606,7 @@ int cavdftb_create(const cavdftb_params* params, const cavdftb_layout* L, void* 
     b.scratch_per_wg = scc_scratch_per_wg(b.nmax);
     int per_cu = scc_blocks_per_cu(b.nmax);
     if (b.nmax > 64 && per_cu > 2) per_cu = 2;  // global-scratch buckets: bound the cache footprint
+    b.per_cu_max = per_cu;
     b.n_wg = n_cu * per_cu;
     CK(dalloc(c, &b.d_units, b.n_units));
     CK(hipMemcpy(b.d_units, bunits[k].data(), b.n_units * sizeof(int32_t), hipMemcpyHostToDevice));
@@ -678,6 +690,17 @@ int cavdftb_set_tuning(cavdftb_ctx* ctx, double jacobi_res_factor, int32_t keep_
     return fail(ctx, CAVDFTB_EINVAL, "set_tuning: need 0 <= jacobi_res_factor <= 1");
   ctx->jac_factor = jacobi_res_factor;
   ctx->keep_hist = keep_mixer_history ? 1 : 0;
+  return CAVDFTB_OK;
+}
+
+int cavdftb_set_schedule(cavdftb_ctx* ctx, int32_t job_queue, int32_t max_wg_per_cu) {
+  if (!ctx) return CAVDFTB_EINVAL;
+  if (max_wg_per_cu < 0) return fail(ctx, CAVDFTB_EINVAL, "set_schedule: need max_wg_per_cu >= 0");
+  ctx->dynamic_jobs = job_queue ? 1 : 0;
+  for (Bucket& b : ctx->buckets) {
+    const int per = max_wg_per_cu > 0 && max_wg_per_cu < b.per_cu_max ? max_wg_per_cu : b.per_cu_max;
+    b.n_wg = ctx->n_cu * per;
+  }
   return CAVDFTB_OK;
 }
 

@@ -39,6 +39,7 @@ struct SccArgs {
   const int32_t* unit_mask; // [n_units] or nullptr: jobs of units with mask 0 are skipped
   int32_t n_jobs;
   const int32_t* n_jobs_dev; // if set, the job count is read from device memory (compacted job lists)
+  unsigned int* job_counter; // if set, jobs are taken from a queue (reset to 0 before the launch)
   double fd_h;              // displacement (bohr) of displaced jobs, field (a.u.) of field jobs
   const int64_t* ws_off;    // [n_units] offset of the unit's stored basis in ws_C (doubles)
   double* ws_C;             // stored MO bases, NMAX x NMAX per unit of the bucket

@@ -447,8 +447,9 @@ __device__ void gemm_m(const double* __restrict__ A, const double* __restrict__ 
 }
 
 // small products (the occupied-virtual step) on the matrix cores where the tiles fit
-// the buffers, else on the vector units; the n x n products stay on the vector units
-// (gemm_g), which measured faster for them at these sizes
+// the buffers, else on the vector units; the n x n products (gemm_g) stay on the
+// vector units for LDS-resident matrices, which measured faster there, and use the
+// matrix cores when the matrices live in global scratch
 template <int NMAX, int NT, bool TA, bool TB, class Epi>
 __device__ __forceinline__ void gemm_e(const double* __restrict__ A, const double* __restrict__ B, int kd,
                                        const double* __restrict__ A2, const double* __restrict__ B2, int kd2,
@@ -464,8 +465,11 @@ template <int NMAX, int NT, bool TA, bool TB>
 __device__ __forceinline__ void gemm_g(const double* __restrict__ A, const double* __restrict__ B,
                                        double* __restrict__ C, int nr, int nc, int kd, double scale) {
   constexpr int LD = Cfg<NMAX, NT>::LD;
-  gemm_v<NMAX, NT, TA, TB>(A, B, kd, A, B, 0, 0.0, nr, nc,
-                           [=](int r, int c, double v) { C[r * LD + c] = scale * v; });
+  auto st = [=](int r, int c, double v) { C[r * LD + c] = scale * v; };
+  if constexpr (kMatrixCores && Cfg<NMAX, NT>::GM)  // operands in L2: fewer loads per flop on the matrix cores
+    gemm_m<NMAX, NT, TA, TB>(A, B, kd, A, B, 0, 0.0, nr, nc, st);
+  else
+    gemm_v<NMAX, NT, TA, TB>(A, B, kd, A, B, 0, 0.0, nr, nc, st);
 }
 
 // C = op(A) B over the leading n x n block (op = transpose when TA)
@@ -513,6 +517,7 @@ __device__ __forceinline__ int rr_index(int s, int r, int m) { return s == 0 ? 0
 struct Shared {
   int n, nocc, na, notpd;
   int bcount, bhead, sweeps, jac_iters;
+  int next_job, pad2;
   double homo, lumo;
   double fld[3];  // uniform external field of the job (zero except for field jobs)
 };
@@ -557,7 +562,16 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
   double* sT = GM ? sA + NMAX * LD : lT;
 
   const int n_jobs = a.n_jobs_dev ? *a.n_jobs_dev : a.n_jobs;
-  for (int job = blockIdx.x; job < n_jobs; job += gridDim.x) {
+  // job queue: with a counter, each workgroup takes the next job when it is free
+  // (the lists are ordered largest unit first), else a fixed stride over the list
+  auto next_job = [&](int j) -> int {
+    if (!a.job_counter) return j + gridDim.x;
+    __syncthreads();  // every thread has read the previous job index
+    if (tid == 0) sh.next_job = (int)atomicAdd(a.job_counter, 1u);
+    __syncthreads();
+    return sh.next_job;
+  };
+  for (int job = a.job_counter ? next_job(-1) : blockIdx.x; job < n_jobs; job = next_job(job)) {
     const int u = a.job_unit[job];
     if (a.unit_mask && !a.unit_mask[u]) {  // block-uniform skip (fallback launches)
       if (tid == 0) {
@@ -1287,8 +1301,17 @@ int64_t scc_scratch_per_wg(int nmax) {
   return 3LL * nmax * nmax + (2LL + 2LL * kMaxHist) * nmax + (nmax > 64 ? 3LL * nmax * (nmax + 1) : 0);
 }
 
+__global__ void reset_counter_kernel(unsigned int* c) {
+  if (threadIdx.x == 0) c[0] = 0u;
+}
+
 template <int NMAX, int NT>
 static hipError_t launch_t(int n_wg, const SccArgs& args, hipStream_t stream) {
+  if (args.job_counter) {  // a kernel, not a memset: the step may be captured in a graph
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, stream, args.job_counter);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL((scc_kernel<NMAX, NT>), dim3(n_wg), dim3(NT), 0, stream, args);
   return hipGetLastError();
 }

@@ -32,7 +32,7 @@ def _torch():
 
 
 # ---------------------------------------------------------------- data
-def md_snapshots(params, system, n_snap, stride, warm=10, dt=None, tol=1e-8):
+def md_snapshots(params, system, n_snap, stride, warm=10, dt=None, tol=1e-8, log=None):
     """Positions (device tensor [n_snap, n_atoms, 3]) every `stride` steps of
     Mulliken-path cavity MD after `warm` steps."""
     torch = _torch()
@@ -48,9 +48,13 @@ def md_snapshots(params, system, n_snap, stride, warm=10, dt=None, tol=1e-8):
     dt = system["dt"] if dt is None else dt
     ctx.step(r, p, qm, pm, warm, dt)
     out = torch.empty(n_snap, ctx.n_atoms, 3, dtype=torch.float64, device=dev)
+    t0 = time.time()
     for k in range(n_snap):
         ctx.step(r, p, qm, pm, stride, dt)
         out[k].copy_(r)
+        if log and (k % 16 == 15 or k == n_snap - 1):
+            ctx.sync()
+            log(f"  snapshot {k + 1}/{n_snap} ({time.time() - t0:.1f} s)")
     ctx.sync()
     ctx.close()
     return out
@@ -71,11 +75,13 @@ def sub_clusters(system, pos, rng):
     return out
 
 
-def exact_born(params, system, pos_list, route="field", tol=1e-10):
+def exact_born(params, system, pos_list, route="field", tol=1e-10, log=None):
     """Exact Born charges (route "field": force response to a uniform field of
     1e-4 a.u.; "fd": central differences of the dipole, h = 1e-3 bohr) and
     Mulliken charges for each position set (device tensors [n_atoms, 3]);
-    returns (born [n_snap, n_atoms, 9], charges [n_snap, n_atoms], bad-unit count)."""
+    returns (born [n_snap, n_atoms, 9], charges [n_snap, n_atoms], good
+    [n_snap, n_atoms] (bool: the atom's unit evaluated with status 0), bad-unit
+    count)."""
     mode, h = (B.BORN_FIELD, 1e-4) if route == "field" else (B.BORN_FD, 1e-3)
     torch = _torch()
     dev = torch.device("cuda:0")
@@ -84,20 +90,28 @@ def exact_born(params, system, pos_list, route="field", tol=1e-10):
     out = torch.empty(len(pos_list), ctx.n_atoms, 9, dtype=torch.float64, device=dev)
     q = torch.empty(len(pos_list), ctx.n_atoms, dtype=torch.float64, device=dev)
     st = torch.zeros(ctx.n_units, dtype=torch.int32, device=dev)
+    st2 = torch.zeros_like(st)
+    counts = torch.tensor(np.diff(system["unit_off"]).astype(np.int64), device=dev)
+    good = torch.empty(len(pos_list), ctx.n_atoms, dtype=torch.bool, device=dev)
     bad = 0
     for k, pos in enumerate(pos_list):
         ctx.eval_units(pos.contiguous(), charges=q[k], unit_status=st)
-        ctx.born_charges(pos.contiguous(), mode, h, out[k], st)
-        bad += int((st != 0).sum())
+        ctx.born_charges(pos.contiguous(), mode, h, out[k], st2)
+        ok = (st == 0) & (st2 == 0)
+        good[k] = torch.repeat_interleave(ok, counts)
+        bad += int((~ok).sum())
+        if log and (k % 16 == 15 or k == len(pos_list) - 1):
+            log(f"  labels {k + 1}/{len(pos_list)}")
     ctx.sync()
     ctx.close()
-    return out, q, bad
+    return out, q, good, bad
 
 
-def features_and_targets(params, system, pos_list, born, charges):
+def features_and_targets(params, system, pos_list, born, charges, good=None):
     """Per species: descriptor rows (FP64 [N_s, 32]) and local-frame targets,
     the correction R^T Z R - Q I to the Mulliken replacement (FP64 [N_s, 9]),
-    over all snapshots."""
+    over all snapshots; atoms of units without a clean evaluation (good False)
+    are left out."""
     torch = _torch()
     dev = torch.device("cuda:0")
     ctx = B.context_from_system(params, system)
@@ -113,6 +127,8 @@ def features_and_targets(params, system, pos_list, born, charges):
         B.sg_to_local(frames, born[k].contiguous(), charges[k].contiguous(), None, NA, zl)
         for s in (0, 1):
             m = sp == s
+            if good is not None:
+                m = m & good[k]
             feats[s].append(feat[m].clone())
             targs[s].append(zl[m].clone())
     ctx.sync()
@@ -187,7 +203,7 @@ def train_network(feat, targ, norm, rng, epochs=40, batch=512, lr=2e-3, lr_final
     return w, last
 
 
-def train_ensemble(feats, targs, seed=0, epochs=40, batch=512, log=None):
+def train_ensemble(feats, targs, seed=0, epochs=40, batch=512, lr=2e-3, log=None):
     """params [2][members][N_PARAM] and norm [2][N_NORM] (FP32 device tensors)."""
     torch = _torch()
     dev = feats[0].device
@@ -199,7 +215,7 @@ def train_ensemble(feats, targs, seed=0, epochs=40, batch=512, log=None):
         for mb in range(B.SG_MEMBERS):
             rng = np.random.default_rng(seed * 1000 + s * 10 + mb)
             t0 = time.time()
-            w, last = train_network(feats[s], targs[s], norms[s], rng, epochs=epochs, batch=batch, log=log)
+            w, last = train_network(feats[s], targs[s], norms[s], rng, epochs=epochs, batch=batch, lr=lr, log=log)
             params[s, mb] = w
             losses[(s, mb)] = last
             if log:
@@ -208,10 +224,11 @@ def train_ensemble(feats, targs, seed=0, epochs=40, batch=512, log=None):
 
 
 # ---------------------------------------------------------------- evaluation
-def evaluate(params_sg, norm_sg, params, system, pos_list, born_exact, h=1e-3, thr=1e9):
+def evaluate(params_sg, norm_sg, params, system, pos_list, born_exact, h=1e-3, thr=1e9, good=None):
     """RMSE (elementary charges, over atoms x 9 components) of the surrogate
     (fallback disabled unless thr is finite) and of the Mulliken replacement
-    Z = Q I against the exact Born charges.  Returns a dict."""
+    Z = Q I against the exact Born charges, over the atoms marked good.
+    Returns a dict."""
     torch = _torch()
     dev = torch.device("cuda:0")
     ctx = B.context_from_system(params, system)
@@ -228,9 +245,10 @@ def evaluate(params_sg, norm_sg, params, system, pos_list, born_exact, h=1e-3, t
         ctx.born_charges(pos.contiguous(), B.BORN_SURROGATE, h, zs, None, std)
         ctx.born_charges(pos.contiguous(), B.BORN_MULLIKEN, h, zm)
         ex = born_exact[k]
-        se_s += float(((zs - ex) ** 2).sum())
-        se_m += float(((zm - ex) ** 2).sum())
-        cnt += ex.numel()
+        w = good[k][:, None].to(ex.dtype) if good is not None else torch.ones_like(ex[:, :1])
+        se_s += float((((zs - ex) ** 2) * w).sum())
+        se_m += float((((zm - ex) ** 2) * w).sum())
+        cnt += int(w.sum()) * ex.shape[1]
         max_std.append(float(std.max()))
     cnt_fallback = ctx.read_counters()["surrogate_fallback_units"]
     ctx.close()
@@ -239,18 +257,18 @@ def evaluate(params_sg, norm_sg, params, system, pos_list, born_exact, h=1e-3, t
 
 
 def build_training_set(params, n_units=1024, n_train=16, n_val=4, stride=10, n_sub=4, seed=0, log=None,
-                       route="field"):
+                       route="field", workload=3):
     """Geometries, exact labels and features for training and validation (time
     blocks: the validation snapshots come after the training ones)."""
     from cavgen import make_system
     rng = np.random.default_rng(seed)
-    s = make_system(3, n_units=n_units)
+    s = make_system(workload, n_units=n_units)  # 8-water clusters (workloads 2 and 3)
     t0 = time.time()
-    snaps = md_snapshots(params, s, n_train + n_val, stride)
+    snaps = md_snapshots(params, s, n_train + n_val, stride, log=log)
     if log:
         log(f"sampled {n_train + n_val} snapshots of {n_units} units in {time.time() - t0:.1f} s")
     t0 = time.time()
-    born, charges, bad = exact_born(params, s, list(snaps), route=route)
+    born, charges, good, bad = exact_born(params, s, list(snaps), route=route, log=log)
     if log:
         log(f"exact Born labels: {len(snaps)} x {n_units} units in {time.time() - t0:.1f} s ({bad} bad units)")
     sub_pos, sub_sys = [], []
@@ -259,17 +277,18 @@ def build_training_set(params, n_units=1024, n_train=16, n_val=4, stride=10, n_s
         ss = sub_clusters(s, host[k], rng)
         sub_sys.append(ss)
         sub_pos.append(ss["pos"])
-    fe_t, ta_t = features_and_targets(params, s, list(snaps[:n_train]), born[:n_train], charges[:n_train])
+    fe_t, ta_t = features_and_targets(params, s, list(snaps[:n_train]), born[:n_train], charges[:n_train],
+                                      good[:n_train])
     torch = _torch()
     for ss in sub_sys:
         p = [torch.tensor(ss["pos"], device=snaps.device)]
-        bz, qz, _ = exact_born(params, ss, p, route=route)
-        f2, t2 = features_and_targets(params, ss, p, bz, qz)
+        bz, qz, gz, _ = exact_born(params, ss, p, route=route)
+        f2, t2 = features_and_targets(params, ss, p, bz, qz, gz)
         for sp in (0, 1):
             fe_t[sp] = torch.cat([fe_t[sp], f2[sp]])
             ta_t[sp] = torch.cat([ta_t[sp], t2[sp]])
     return {"system": s, "train": (fe_t, ta_t), "val_pos": list(snaps[n_train:]), "val_born": born[n_train:],
-            "sub_systems": sub_sys}
+            "val_good": good[n_train:], "sub_systems": sub_sys}
 
 
 def main(argv=None):
@@ -277,10 +296,13 @@ def main(argv=None):
     import os
     ap = argparse.ArgumentParser(description="train the Born-charge surrogate ensemble on the GPU")
     ap.add_argument("--units", type=int, default=1024)
+    ap.add_argument("--workload", type=int, default=3, choices=[2, 3], help="source of the 8-water clusters")
     ap.add_argument("--train-snapshots", type=int, default=16)
     ap.add_argument("--val-snapshots", type=int, default=4)
     ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--stride", type=int, default=10, help="MD steps between training snapshots")
+    ap.add_argument("--batch", type=int, default=512)
+    ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--sub", type=int, default=4, help="snapshots also cut into 1..7-water sub-clusters")
     ap.add_argument("--route", choices=["field", "fd"], default="field", help="exact route of the labels")
     ap.add_argument("--dump", default=None, help="also save a sample of the training rows (npz) for inspection")
@@ -294,7 +316,7 @@ def main(argv=None):
     def log(msg):
         print(msg, flush=True)
     data = build_training_set(params, n_units=args.units, n_train=args.train_snapshots, n_val=args.val_snapshots,
-                              stride=args.stride, n_sub=args.sub, log=log, route=args.route)
+                              stride=args.stride, n_sub=args.sub, log=log, route=args.route, workload=args.workload)
     fe, ta = data["train"]
     log(f"training atoms: O {fe[0].shape[0]}, H {fe[1].shape[0]}")
     if args.dump:
@@ -309,9 +331,9 @@ def main(argv=None):
     if args.no_train:
         return 0
     t0 = time.time()
-    psg, nsg, losses = train_ensemble(fe, ta, epochs=args.epochs, log=log)
+    psg, nsg, losses = train_ensemble(fe, ta, epochs=args.epochs, batch=args.batch, lr=args.lr, log=log)
     log(f"training took {time.time() - t0:.1f} s")
-    ev = evaluate(psg, nsg, params, data["system"], data["val_pos"], data["val_born"])
+    ev = evaluate(psg, nsg, params, data["system"], data["val_pos"], data["val_born"], good=data["val_good"])
     log(f"held-out: {ev}")
     os.makedirs(os.path.dirname(args.out), exist_ok=True)
     np.savez(args.out, params=psg.cpu().numpy(), norm=nsg.cpu().numpy(),

@@ -174,6 +174,25 @@ def test_deterministic_bitwise(params):
         assert np.array_equal(a[k], b[k]), k
 
 
+def test_schedule_does_not_change_results(params):
+    # job queue (largest units first) vs fixed stride, and fewer workgroups per CU:
+    # every job computes the same numbers wherever it runs
+    full = make_system(4, n_units=60)
+    s = subsystem(full, list(range(0, 60, 3)))
+    outs = []
+    for queue, cap in ((True, 0), (False, 0), (True, 1)):
+        ctx = make_ctx(params, s, tol=1e-10)
+        ctx.set_schedule(queue, cap)
+        outs.append(gpu_eval(ctx, s["pos"]))
+        born = torch.zeros(ctx.n_atoms, 3, 3, dtype=torch.float64, device=DEV)
+        ctx.born_charges(_t(s["pos"]), cd.BORN_FIELD, 1e-4, born)
+        ctx.sync()
+        outs[-1]["born"] = born.cpu().numpy()
+    for o in outs[1:]:
+        for k in outs[0]:
+            assert np.array_equal(outs[0][k], o[k]), k
+
+
 def test_born_fd_parity_and_sum_rule(params):
     s = subsystem(make_system(5, n_units=6), [0, 1, 5])
     ctx = make_ctx(params, s)
@@ -358,3 +377,18 @@ def test_status_flags(params):
     pos[4, 1] = np.nan
     g = gpu_eval(ctx, pos)
     assert g["status"][1] & 8 and np.all(g["status"][[0, 2, 3, 4, 5, 6, 7]] == 0)
+
+
+def test_autotune_picks_a_candidate_and_keeps_results(params):
+    from paper_2512_03277_amd import autotune
+    s = subsystem(make_system(4, n_units=24), list(range(0, 24, 2)))
+    best, res = autotune.tune(params, s, steps=1, warmup=1)
+    assert len(res) == 12 and all(ms > 0 for _, ms in res)
+    assert best in [st for st, _ in res]
+    ref = gpu_eval(make_ctx(params, s), s["pos"])
+    ctx = make_ctx(params, s)
+    autotune.apply(ctx, best)
+    g = gpu_eval(ctx, s["pos"])
+    r = eval_units(params, s["species"], s["pos"], s["unit_off"], tol=1e-12)
+    assert_parity(g, r, pos=s["pos"], unit_off=s["unit_off"])
+    assert np.max(np.abs(g["charges"] - ref["charges"])) <= 1e-10

@@ -224,5 +224,5 @@ def test_trained_network_beats_the_mulliken_replacement(params):
     fe, ta = data["train"]
     psg, nsg, losses = dsg.train_ensemble(fe, ta, epochs=12, batch=256)
     assert all(np.isfinite(v) for v in losses.values())
-    ev = dsg.evaluate(psg, nsg, params, data["system"], data["val_pos"], data["val_born"])
+    ev = dsg.evaluate(psg, nsg, params, data["system"], data["val_pos"], data["val_born"], good=data["val_good"])
     assert ev["rmse_surrogate"] < 0.8 * ev["rmse_mulliken"], ev
