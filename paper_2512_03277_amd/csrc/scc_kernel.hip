@@ -32,6 +32,7 @@ namespace {
 constexpr int kMaxSweeps = 30;
 constexpr double kJacobiThr = 1.0e-14;  // off-diagonal threshold (hartree)
 constexpr double kGapMin = 1.0e-6;
+constexpr int kStagnation = 40;  // iterations without a new smallest residual before giving up
 // warm orthonormalisation: Newton-Schulz from max|C0^T S C0 - I| <= kNsStart
 constexpr double kNsStart = 0.1;
 constexpr double kNsTol = 1.0e-15;
@@ -331,7 +332,7 @@ struct Cfg {
 // loops are unrolled with all loads of a step issued before its multiply-adds
 // (LDS latency is the bound at these sizes); the order over k is sequential.
 template <int NMAX, int NT, bool TA, bool TB, class Epi>
-__device__ void gemm_v(const double* __restrict__ A, const double* __restrict__ B, int kd,
+__device__ __forceinline__ void gemm_v(const double* __restrict__ A, const double* __restrict__ B, int kd,
                        const double* __restrict__ A2, const double* __restrict__ B2, int kd2, double s2, int nr,
                        int nc, Epi epi) {
   constexpr int G = Cfg<NMAX, NT>::G, TMB = Cfg<NMAX, NT>::TMB, BLK = Cfg<NMAX, NT>::BLK, LD = Cfg<NMAX, NT>::LD;
@@ -411,7 +412,7 @@ __device__ void gemm_v(const double* __restrict__ A, const double* __restrict__ 
 // are never passed to epi.
 typedef double mfma_acc4 __attribute__((ext_vector_type(4)));
 template <int NMAX, int NT, bool TA, bool TB, class Epi>
-__device__ void gemm_m(const double* __restrict__ A, const double* __restrict__ B, int kd,
+__device__ __forceinline__ void gemm_m(const double* __restrict__ A, const double* __restrict__ B, int kd,
                        const double* __restrict__ A2, const double* __restrict__ B2, int kd2, double s2, int nr,
                        int nc, Epi epi) {
   static_assert(NMAX % 16 == 0, "matrix-core tiles need NMAX % 16 == 0");
@@ -446,6 +447,83 @@ __device__ void gemm_m(const double* __restrict__ A, const double* __restrict__ 
   }
 }
 
+// Matrix-core product for buckets whose matrices live in global scratch (L2 /
+// Infinity Cache latency): each wave takes 2 x 2 output tiles at a time (the two
+// A fragments and two B fragments of a k-step feed four MFMAs) and issues the
+// loads of four k-steps before their MFMAs.  Same operand convention, bounds and
+// element ownership as gemm_m.
+template <int NMAX, int NT, bool TA, bool TB, class Epi>
+__device__ __forceinline__ void gemm_mg(const double* __restrict__ A, const double* __restrict__ B, int kd,
+                        const double* __restrict__ A2, const double* __restrict__ B2, int kd2, double s2, int nr,
+                        int nc, Epi epi) {
+  static_assert(NMAX % 16 == 0, "matrix-core tiles need NMAX % 16 == 0");
+  constexpr int LD = Cfg<NMAX, NT>::LD;
+  constexpr int UK = 4;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int tr = (nr + 31) >> 5, tcn = (nc + 31) >> 5;  // 32 x 32 blocks of 2 x 2 tiles
+  for (int t = wave; t < tr * tcn; t += NT / 64) {
+    const int r0 = (t / tcn) * 32, c0 = (t % tcn) * 32;
+    int ra[2], cb[2];
+    bool rin[2], cin[2];
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+      ra[g] = r0 + 16 * g + li;
+      cb[g] = c0 + 16 * g + li;
+      rin[g] = ra[g] < nr;
+      cin[g] = cb[g] < nc;
+    }
+    mfma_acc4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = (mfma_acc4){0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < kd; k0 += 4 * UK) {
+      double av[UK][2], bv[UK][2];
+#pragma unroll
+      for (int u = 0; u < UK; ++u) {
+        const int k = k0 + 4 * u + lk;
+        const bool kin = k < kd;
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+          av[u][g] = (kin && rin[g]) ? (TA ? A[k * LD + ra[g]] : A[ra[g] * LD + k]) : 0.0;
+          bv[u][g] = (kin && cin[g]) ? (TB ? B[cb[g] * LD + k] : B[k * LD + cb[g]]) : 0.0;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < UK; ++u)
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][i], bv[u][j], acc[i][j], 0, 0, 0);
+    }
+    for (int k0 = 0; k0 < kd2; k0 += 4) {
+      const int k = k0 + lk;
+      const bool kin = k < kd2;
+      double av[2], bv[2];
+#pragma unroll
+      for (int g = 0; g < 2; ++g) {
+        av[g] = (kin && rin[g]) ? A2[ra[g] * LD + k] : 0.0;
+        bv[g] = (kin && cin[g]) ? s2 * B2[k * LD + cb[g]] : 0.0;
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int rr = r0 + 16 * i + lk + 4 * q, cc = c0 + 16 * j + li;
+          if (rr < nr && cc < nc) epi(rr, cc, acc[i][j][q]);
+        }
+  }
+}
+
 // small products (the occupied-virtual step) on the matrix cores where the tiles fit
 // the buffers, else on the vector units; the n x n products (gemm_g) stay on the
 // vector units for LDS-resident matrices, which measured faster there, and use the
@@ -454,7 +532,9 @@ template <int NMAX, int NT, bool TA, bool TB, class Epi>
 __device__ __forceinline__ void gemm_e(const double* __restrict__ A, const double* __restrict__ B, int kd,
                                        const double* __restrict__ A2, const double* __restrict__ B2, int kd2,
                                        double s2, int nr, int nc, Epi epi) {
-  if constexpr (kMatrixCores && NMAX % 16 == 0)
+  if constexpr (kMatrixCores && Cfg<NMAX, NT>::GM)
+    gemm_mg<NMAX, NT, TA, TB>(A, B, kd, A2, B2, kd2, s2, nr, nc, epi);
+  else if constexpr (kMatrixCores && NMAX % 16 == 0)
     gemm_m<NMAX, NT, TA, TB>(A, B, kd, A2, B2, kd2, s2, nr, nc, epi);
   else
     gemm_v<NMAX, NT, TA, TB>(A, B, kd, A2, B2, kd2, s2, nr, nc, epi);
@@ -467,7 +547,7 @@ __device__ __forceinline__ void gemm_g(const double* __restrict__ A, const doubl
   constexpr int LD = Cfg<NMAX, NT>::LD;
   auto st = [=](int r, int c, double v) { C[r * LD + c] = scale * v; };
   if constexpr (kMatrixCores && Cfg<NMAX, NT>::GM)  // operands in L2: fewer loads per flop on the matrix cores
-    gemm_m<NMAX, NT, TA, TB>(A, B, kd, A, B, 0, 0.0, nr, nc, st);
+    gemm_mg<NMAX, NT, TA, TB>(A, B, kd, A, B, 0, 0.0, nr, nc, st);
   else
     gemm_v<NMAX, NT, TA, TB>(A, B, kd, A, B, 0, 0.0, nr, nc, st);
 }
@@ -774,6 +854,8 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
 
     int it = 0;
     double res_prev = INFINITY;  // no charge residual known before the first iteration
+    double res_best = INFINITY;  // smallest residual so far and its iteration (stagnation stop)
+    int it_best = 0;
     if (status == 0) {
       for (it = 1; it <= a.max_iter; ++it) {
         // V = gamma Dq_in + field . R (gamma symmetric: column walk is coalesced)
@@ -1051,6 +1133,13 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
         if (res < a.tol && kmax < 10.0 * a.tol) break;  // block-uniform
         if (!(res < INFINITY)) {
           status |= CAVDFTB_ST_NAN;
+          break;
+        }
+        if (res < res_best) {
+          res_best = res;
+          it_best = it;
+        } else if (it - it_best >= kStagnation) {  // no new best residual for kStagnation iterations
+          status |= CAVDFTB_ST_NOT_CONVERGED;
           break;
         }
         res_prev = res;
