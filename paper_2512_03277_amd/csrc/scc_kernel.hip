@@ -59,7 +59,7 @@ __device__ __forceinline__ void radial(const DevParams& P, int t, double r, doub
 
 // Two-centre block <i on A | . | j on B> for d = R_B - R_A (nA x nB, row-major
 // with leading dimension 4).
-__device__ void sk_block(const DevParams& P, int spA, int spB, const double d[3], double H[16], double S[16]) {
+__device__ __forceinline__ void sk_block(const DevParams& P, int spA, int spB, const double d[3], double H[16], double S[16]) {
   const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
   const double ir = 1.0 / r;
   const double u[3] = {d[0] * ir, d[1] * ir, d[2] * ir};
@@ -107,85 +107,93 @@ __device__ void sk_block(const DevParams& P, int spA, int spB, const double d[3]
 }
 
 // Gradient contribution of the pair (A, B) with respect to d = R_B - R_A:
-// g += 2 sum_ij [ P_ij dH0_ij - (W_ij - 1/2 P_ij (V_A + V_B)) dS_ij ], streaming
-// over the block elements so no derivative block is kept in registers.
-__device__ void pair_band_grad(const DevParams& P, int spA, int spB, const double d[3], const double* Pm,
+// g += sum_ij [ 2 P_ij dH0_ij - 2 (W_ij - 1/2 P_ij (V_A + V_B)) dS_ij ].
+// With u = d / r and du_a / dd_k = (delta_ak - u_a u_k) / r each block reduces
+// to contractions of its weights c (the H and S weights folded together) with u:
+//   s-p, value u_b f:  sum_b c_b d(u_b f) = (f c + u (c.u)(r f' - f)) / r
+//   p-p, value u_a u_b (f_sig - f_pi) + delta_ab f_pi:
+//     sum_ab c_ab d(.) = (f_sig - f_pi) [(c + c^T) u - 2 (u^T c u) u] / r
+//                        + u [(f_sig' - f_pi') u^T c u + f_pi' tr c]
+// so a block costs one batch of weight loads per row and O(16) products.
+__device__ __forceinline__ void pair_band_grad(const DevParams& P, int spA, int spB, const double d[3], const double* Pm,
                                const double* Wm, int ld, int oA, int oB, double vab, double g[3]) {
   const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
   const double ir = 1.0 / r;
   const double u[3] = {d[0] * ir, d[1] * ir, d[2] * ir};
-  int t_ss, t_sp, t_ps;
-  if (spA == 0 && spB == 0) {
-    t_ss = 0; t_sp = 1; t_ps = 1;
-  } else if (spA == 0) {
-    t_ss = 4; t_sp = -1; t_ps = 5;
-  } else if (spB == 0) {
-    t_ss = 4; t_sp = 5; t_ps = -1;
-  } else {
-    t_ss = 6; t_sp = -1; t_ps = -1;
-  }
-  const int nA = spA == 0 ? 4 : 1, nB = spB == 0 ? 4 : 1;
+  const bool pA = spA == 0, pB = spB == 0;  // oxygen carries the p shell
+  const int t_ss = pA ? (pB ? 0 : 4) : (pB ? 4 : 6);
+  const int t_sp = pA && pB ? 1 : 5;
+  // weights of element (i, j): H 2 P_ij, S -2 W_ij + P_ij (V_A + V_B)
+  auto wt = [&](int i, int j, double& ch, double& cs) {
+    const double pij = Pm[i * ld + j];
+    ch = 2.0 * pij;
+    cs = pij * vab - 2.0 * Wm[i * ld + j];
+  };
+  double rad = 0.0;                // coefficient of u
+  double gv[3] = {0.0, 0.0, 0.0};  // remaining terms, times 1 / r
   double h, s, hp, sp;
-  // s-s: weight on dH and dS
   {
+    double ch, cs;
+    wt(oA, oB, ch, cs);
     radial(P, t_ss, r, h, s, hp, sp);
-    const double pij = Pm[oA * ld + oB];
-    const double wij = Wm[oA * ld + oB] - 0.5 * pij * vab;
-    const double rad = 2.0 * (pij * hp - wij * sp);
-    for (int k = 0; k < 3; ++k) g[k] += rad * u[k];
+    rad += ch * hp + cs * sp;
   }
-  if (nB == 4) {  // <s_A | p_B,b> = u_b V
+  if (pA || pB) {
     radial(P, t_sp, r, h, s, hp, sp);
-#pragma unroll 1
-    for (int b = 0; b < 3; ++b) {
-      const double pij = Pm[oA * ld + oB + 1 + b];
-      const double wij = Wm[oA * ld + oB + 1 + b] - 0.5 * pij * vab;
-      const double ch = 2.0 * pij, cs = -2.0 * wij;
-      for (int k = 0; k < 3; ++k) {
-        const double du = ((b == k ? 1.0 : 0.0) - u[b] * u[k]) * ir;
-        g[k] += ch * (du * h + u[b] * hp * u[k]) + cs * (du * s + u[b] * sp * u[k]);
+    const double fh = hp - h * ir, fs = sp - s * ir;
+    if (pB) {  // <s_A | p_B,b> = u_b V
+      double ch[3], cs[3];
+#pragma unroll
+      for (int b = 0; b < 3; ++b) wt(oA, oB + 1 + b, ch[b], cs[b]);
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        gv[b] += ch[b] * h + cs[b] * s;
+        rad += u[b] * (ch[b] * fh + cs[b] * fs);
+      }
+    }
+    if (pA) {  // <p_A,a | s_B> = -u_a V
+      double ch[3], cs[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) wt(oA + 1 + a, oB, ch[a], cs[a]);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        gv[a] -= ch[a] * h + cs[a] * s;
+        rad -= u[a] * (ch[a] * fh + cs[a] * fs);
       }
     }
   }
-  if (nA == 4) {  // <p_A,a | s_B> = -u_a V
-    radial(P, t_ps, r, h, s, hp, sp);
-#pragma unroll 1
-    for (int a = 0; a < 3; ++a) {
-      const double pij = Pm[(oA + 1 + a) * ld + oB];
-      const double wij = Wm[(oA + 1 + a) * ld + oB] - 0.5 * pij * vab;
-      const double ch = 2.0 * pij, cs = -2.0 * wij;
-      for (int k = 0; k < 3; ++k) {
-        const double du = ((a == k ? 1.0 : 0.0) - u[a] * u[k]) * ir;
-        g[k] -= ch * (du * h + u[a] * hp * u[k]) + cs * (du * s + u[a] * sp * u[k]);
-      }
-    }
-  }
-  if (nA == 4 && nB == 4) {  // p-p
+  if (pA && pB) {
     double hs, ss, hsp, ssp, hpi, spi, hpip, spip;
     radial(P, 2, r, hs, ss, hsp, ssp);
     radial(P, 3, r, hpi, spi, hpip, spip);
-#pragma unroll 1
-    for (int a = 0; a < 3; ++a)
-#pragma unroll 1
+    const double dh = hs - hpi, ds = ss - spi, dhp = hsp - hpip, dsp = ssp - spip;
+    double mu[3] = {0.0, 0.0, 0.0}, mtu[3] = {0.0, 0.0, 0.0};
+    double unu = 0.0, tr = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      double ch[3], cs[3];
+#pragma unroll
+      for (int b = 0; b < 3; ++b) wt(oA + 1 + a, oB + 1 + b, ch[b], cs[b]);
+#pragma unroll
       for (int b = 0; b < 3; ++b) {
-        const double pij = Pm[(oA + 1 + a) * ld + oB + 1 + b];
-        const double wij = Wm[(oA + 1 + a) * ld + oB + 1 + b] - 0.5 * pij * vab;
-        const double ch = 2.0 * pij, cs = -2.0 * wij;
-        const double dl = a == b ? 1.0 : 0.0;
-        for (int k = 0; k < 3; ++k) {
-          const double dua = ((a == k ? 1.0 : 0.0) - u[a] * u[k]) * ir;
-          const double dub = ((b == k ? 1.0 : 0.0) - u[b] * u[k]) * ir;
-          const double duu = dua * u[b] + u[a] * dub;
-          const double dH = duu * (hs - hpi) + u[a] * u[b] * (hsp - hpip) * u[k] + dl * hpip * u[k];
-          const double dS = duu * (ss - spi) + u[a] * u[b] * (ssp - spip) * u[k] + dl * spip * u[k];
-          g[k] += ch * dH + cs * dS;
-        }
+        const double m = dh * ch[b] + ds * cs[b];
+        mu[a] += m * u[b];
+        mtu[b] += m * u[a];
+        unu += u[a] * u[b] * (dhp * ch[b] + dsp * cs[b]);
+        if (a == b) tr += hpip * ch[b] + spip * cs[b];
       }
+    }
+    const double umu = u[0] * mu[0] + u[1] * mu[1] + u[2] * mu[2];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) gv[k] += mu[k] + mtu[k];
+    rad += unu + tr - 2.0 * umu * ir;
   }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) g[k] += rad * u[k] + gv[k] * ir;
 }
 
 // Elstner gamma and d gamma / dR for distinct sites.
-__device__ void gamma_pair(double ua, double ub, double r, double& g, double& dg) {
+__device__ __forceinline__ void gamma_pair(double ua, double ub, double r, double& g, double& dg) {
   const double ta = 3.2 * ua, tb = 3.2 * ub;  // 16 U / 5
   double s, ds;
   if (fabs(ta - tb) < 1e-10 * fmax(ta, tb)) {
@@ -447,81 +455,90 @@ __device__ __forceinline__ void gemm_m(const double* __restrict__ A, const doubl
   }
 }
 
-// Matrix-core product for buckets whose matrices live in global scratch (L2 /
-// Infinity Cache latency): each wave takes 2 x 2 output tiles at a time (the two
-// A fragments and two B fragments of a k-step feed four MFMAs) and issues the
-// loads of four k-steps before their MFMAs.  Same operand convention, bounds and
+// Matrix-core product with blocks of TI x TJ output tiles per wave: the TI A
+// fragments and TJ B fragments of a k-step feed TI * TJ independent MFMAs, and
+// the loads of UK k-steps are issued before their MFMAs (latency hiding for
+// LDS and for matrices in global scratch).  Same operand convention, bounds and
 // element ownership as gemm_m.
-template <int NMAX, int NT, bool TA, bool TB, class Epi>
-__device__ __forceinline__ void gemm_mg(const double* __restrict__ A, const double* __restrict__ B, int kd,
+template <int NMAX, int NT, bool TA, bool TB, int TI, int TJ, int UK, class Epi>
+__device__ __forceinline__ void gemm_mt(const double* __restrict__ A, const double* __restrict__ B, int kd,
                         const double* __restrict__ A2, const double* __restrict__ B2, int kd2, double s2, int nr,
                         int nc, Epi epi) {
   static_assert(NMAX % 16 == 0, "matrix-core tiles need NMAX % 16 == 0");
   constexpr int LD = Cfg<NMAX, NT>::LD;
-  constexpr int UK = 4;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const int tr = (nr + 31) >> 5, tcn = (nc + 31) >> 5;  // 32 x 32 blocks of 2 x 2 tiles
+  const int tr = (nr + 16 * TI - 1) / (16 * TI), tcn = (nc + 16 * TJ - 1) / (16 * TJ);
   for (int t = wave; t < tr * tcn; t += NT / 64) {
-    const int r0 = (t / tcn) * 32, c0 = (t % tcn) * 32;
-    int ra[2], cb[2];
-    bool rin[2], cin[2];
+    const int r0 = (t / tcn) * 16 * TI, c0 = (t % tcn) * 16 * TJ;
+    int ra[TI], cb[TJ];
+    bool rin[TI], cin[TJ];
 #pragma unroll
-    for (int g = 0; g < 2; ++g) {
+    for (int g = 0; g < TI; ++g) {
       ra[g] = r0 + 16 * g + li;
-      cb[g] = c0 + 16 * g + li;
       rin[g] = ra[g] < nr;
+    }
+#pragma unroll
+    for (int g = 0; g < TJ; ++g) {
+      cb[g] = c0 + 16 * g + li;
       cin[g] = cb[g] < nc;
     }
-    mfma_acc4 acc[2][2];
+    mfma_acc4 acc[TI][TJ];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < TI; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) acc[i][j] = (mfma_acc4){0.0, 0.0, 0.0, 0.0};
+      for (int j = 0; j < TJ; ++j) acc[i][j] = (mfma_acc4){0.0, 0.0, 0.0, 0.0};
     for (int k0 = 0; k0 < kd; k0 += 4 * UK) {
-      double av[UK][2], bv[UK][2];
+      double av[UK][TI], bv[UK][TJ];
 #pragma unroll
       for (int u = 0; u < UK; ++u) {
         const int k = k0 + 4 * u + lk;
         const bool kin = k < kd;
 #pragma unroll
-        for (int g = 0; g < 2; ++g) {
-          av[u][g] = (kin && rin[g]) ? (TA ? A[k * LD + ra[g]] : A[ra[g] * LD + k]) : 0.0;
-          bv[u][g] = (kin && cin[g]) ? (TB ? B[cb[g] * LD + k] : B[k * LD + cb[g]]) : 0.0;
-        }
+        for (int g = 0; g < TI; ++g) av[u][g] = (kin && rin[g]) ? (TA ? A[k * LD + ra[g]] : A[ra[g] * LD + k]) : 0.0;
+#pragma unroll
+        for (int g = 0; g < TJ; ++g) bv[u][g] = (kin && cin[g]) ? (TB ? B[cb[g] * LD + k] : B[k * LD + cb[g]]) : 0.0;
       }
 #pragma unroll
       for (int u = 0; u < UK; ++u)
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < TI; ++i)
 #pragma unroll
-          for (int j = 0; j < 2; ++j)
+          for (int j = 0; j < TJ; ++j)
             acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][i], bv[u][j], acc[i][j], 0, 0, 0);
     }
     for (int k0 = 0; k0 < kd2; k0 += 4) {
       const int k = k0 + lk;
       const bool kin = k < kd2;
-      double av[2], bv[2];
+      double av[TI], bv[TJ];
 #pragma unroll
-      for (int g = 0; g < 2; ++g) {
-        av[g] = (kin && rin[g]) ? A2[ra[g] * LD + k] : 0.0;
-        bv[g] = (kin && cin[g]) ? s2 * B2[k * LD + cb[g]] : 0.0;
-      }
+      for (int g = 0; g < TI; ++g) av[g] = (kin && rin[g]) ? A2[ra[g] * LD + k] : 0.0;
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int g = 0; g < TJ; ++g) bv[g] = (kin && cin[g]) ? s2 * B2[k * LD + cb[g]] : 0.0;
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+      for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
     }
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < TI; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
+      for (int j = 0; j < TJ; ++j)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int rr = r0 + 16 * i + lk + 4 * q, cc = c0 + 16 * j + li;
           if (rr < nr && cc < nc) epi(rr, cc, acc[i][j][q]);
         }
   }
+}
+
+// matrices in global scratch (L2 / Infinity Cache latency): 2 x 2 tiles per wave,
+// four k-steps of loads in flight
+template <int NMAX, int NT, bool TA, bool TB, class Epi>
+__device__ __forceinline__ void gemm_mg(const double* __restrict__ A, const double* __restrict__ B, int kd,
+                        const double* __restrict__ A2, const double* __restrict__ B2, int kd2, double s2, int nr,
+                        int nc, Epi epi) {
+  gemm_mt<NMAX, NT, TA, TB, 2, 2, 4>(A, B, kd, A2, B2, kd2, s2, nr, nc, epi);
 }
 
 // small products (the occupied-virtual step) on the matrix cores where the tiles fit
@@ -1325,14 +1342,15 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
         const double vx = sh.fld[0] * sPos[t * 3] + sh.fld[1] * sPos[t * 3 + 1] + sh.fld[2] * sPos[t * 3 + 2];
         ecp += 0.5 * sDqOut[t] * (sV[t] + vx);
       }
-      // pair forces: task (A, part) sums g(A,B) over its B's
-      constexpr int SPLIT = (NT / NMAX) > 0 ? NT / NMAX : 1;
+      // pair forces: task (A, part) sums g(A,B) over its B's; the NT / na
+      // parts of an atom keep every thread busy (na <= NT)
+      const int split = na > 0 && na < NT ? NT / na : 1;
       double erp = 0.0;
       double fa[3] = {0.0, 0.0, 0.0};
-      const int A = tid / SPLIT, part = tid % SPLIT;
+      const int A = tid / split, part = tid - A * split;
       if (A < na && (status & (CAVDFTB_ST_NOT_PD | CAVDFTB_ST_NAN)) == 0) {
         const int oA = sAtomOff[A];
-        for (int B = part; B < na; B += SPLIT) {
+        for (int B = part; B < na; B += split) {
           if (B == A) continue;
           const int oB = sAtomOff[B];
           double d[3];
@@ -1358,7 +1376,7 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
       for (int t = tid; t < na; t += NT) {
         for (int g = 0; g < 3; ++g) {
           double f = 0.0;
-          for (int pp = 0; pp < SPLIT; ++pp) f += sF[(t * SPLIT + pp) * 3 + g];
+          for (int pp = 0; pp < split; ++pp) f += sF[(t * split + pp) * 3 + g];
           if (fo) fo[(int64_t)(a0 + t) * 3 + g] = f;
         }
       }
