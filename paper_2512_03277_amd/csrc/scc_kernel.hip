@@ -59,7 +59,7 @@ __device__ __forceinline__ void radial(const DevParams& P, int t, double r, doub
 
 // Two-centre block <i on A | . | j on B> for d = R_B - R_A (nA x nB, row-major
 // with leading dimension 4).
-__device__ __forceinline__ void sk_block(const DevParams& P, int spA, int spB, const double d[3], double H[16], double S[16]) {
+__device__ void sk_block(const DevParams& P, int spA, int spB, const double d[3], double H[16], double S[16]) {
   const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
   const double ir = 1.0 / r;
   const double u[3] = {d[0] * ir, d[1] * ir, d[2] * ir};
@@ -115,7 +115,7 @@ __device__ __forceinline__ void sk_block(const DevParams& P, int spA, int spB, c
 //     sum_ab c_ab d(.) = (f_sig - f_pi) [(c + c^T) u - 2 (u^T c u) u] / r
 //                        + u [(f_sig' - f_pi') u^T c u + f_pi' tr c]
 // so a block costs one batch of weight loads per row and O(16) products.
-__device__ __forceinline__ void pair_band_grad(const DevParams& P, int spA, int spB, const double d[3], const double* Pm,
+__device__ void pair_band_grad(const DevParams& P, int spA, int spB, const double d[3], const double* Pm,
                                const double* Wm, int ld, int oA, int oB, double vab, double g[3]) {
   const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
   const double ir = 1.0 / r;
@@ -193,7 +193,7 @@ __device__ __forceinline__ void pair_band_grad(const DevParams& P, int spA, int 
 }
 
 // Elstner gamma and d gamma / dR for distinct sites.
-__device__ __forceinline__ void gamma_pair(double ua, double ub, double r, double& g, double& dg) {
+__device__ void gamma_pair(double ua, double ub, double r, double& g, double& dg) {
   const double ta = 3.2 * ua, tb = 3.2 * ub;  // 16 U / 5
   double s, ds;
   if (fabs(ta - tb) < 1e-10 * fmax(ta, tb)) {
@@ -641,11 +641,13 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
   __shared__ double lDF[kMaxHist * NMAX];  // Broyden dF history of the job (LDS copy)
   __shared__ double sBa[kMaxHist * kMaxHist], sBm[kMaxHist * (kMaxHist + 1)], sBc[kMaxHist], sBg[kMaxHist];
   __shared__ Shared sh;
+  __shared__ DevParams sPrm;  // LDS copy: the SK helpers never take the address of the kernel arguments
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int rgrp = tid >> 6;
-  const DevParams& P = a.prm;
+  if (tid == 0) sPrm = a.prm;
+  const DevParams& P = sPrm;
   double* scr = a.scratch + (int64_t)blockIdx.x * a.scratch_per_wg;
   double* gH0 = scr;
   double* gS = scr + NMAX * NMAX;
