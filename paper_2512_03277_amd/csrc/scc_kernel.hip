@@ -412,54 +412,15 @@ __device__ __forceinline__ void gemm_v(const double* __restrict__ A, const doubl
     }
 }
 
-// The same product on the FP64 matrix cores (v_mfma_f64_16x16x4): 16 x 16 output
-// tiles dealt round-robin to the waves, four k per instruction.  Lane l feeds
-// A[t_r + l % 16][k0 + l / 16] and B[k0 + l / 16][t_c + l % 16] and receives
-// C[t_r + l / 16 + 4 i][t_c + l % 16] in accumulator i.  Rows, columns and k past
-// the logical operands read as zero (no access outside them); the extra results
-// are never passed to epi.
 typedef double mfma_acc4 __attribute__((ext_vector_type(4)));
-template <int NMAX, int NT, bool TA, bool TB, class Epi>
-__device__ __forceinline__ void gemm_m(const double* __restrict__ A, const double* __restrict__ B, int kd,
-                       const double* __restrict__ A2, const double* __restrict__ B2, int kd2, double s2, int nr,
-                       int nc, Epi epi) {
-  static_assert(NMAX % 16 == 0, "matrix-core tiles need NMAX % 16 == 0");
-  constexpr int LD = Cfg<NMAX, NT>::LD;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int li = lane & 15, lk = lane >> 4;
-  const int tr = (nr + 15) >> 4, tcn = (nc + 15) >> 4;
-  for (int t = wave; t < tr * tcn; t += NT / 64) {
-    const int r0 = (t / tcn) * 16, c0 = (t % tcn) * 16;
-    mfma_acc4 acc = {0.0, 0.0, 0.0, 0.0};
-    const int ra = r0 + li, cb = c0 + li;
-    const bool rin = ra < nr, cin = cb < nc;
-    for (int k0 = 0; k0 < kd; k0 += 4) {
-      const int k = k0 + lk;
-      const bool kin = k < kd;
-      const double av = (kin && rin) ? (TA ? A[k * LD + ra] : A[ra * LD + k]) : 0.0;
-      const double bv = (kin && cin) ? (TB ? B[cb * LD + k] : B[k * LD + cb]) : 0.0;
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
-    }
-    for (int k0 = 0; k0 < kd2; k0 += 4) {
-      const int k = k0 + lk;
-      const bool kin = k < kd2;
-      const double av = (kin && rin) ? A2[ra * LD + k] : 0.0;
-      const double bv = (kin && cin) ? s2 * B2[k * LD + cb] : 0.0;
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int rr = r0 + lk + 4 * i, cc = c0 + li;
-      if (rr < nr && cc < nc) epi(rr, cc, acc[i]);
-    }
-  }
-}
-
-// Matrix-core product with blocks of TI x TJ output tiles per wave: the TI A
-// fragments and TJ B fragments of a k-step feed TI * TJ independent MFMAs, and
-// the loads of UK k-steps are issued before their MFMAs (latency hiding for
-// LDS and for matrices in global scratch).  Same operand convention, bounds and
-// element ownership as gemm_m.
+// The same product on the FP64 matrix cores (v_mfma_f64_16x16x4), in blocks of
+// TI x TJ output tiles of 16 x 16 per wave: the TI A fragments and TJ B
+// fragments of a k-step feed TI * TJ independent MFMAs, and the loads of UK
+// k-steps are issued before their MFMAs (latency hiding for LDS and for
+// matrices in global scratch).  Lane l feeds A[t_r + l % 16][k0 + l / 16] and
+// B[k0 + l / 16][t_c + l % 16] and receives C[t_r + l / 16 + 4 i][t_c + l % 16]
+// in accumulator i.  Rows, columns and k past the logical operands read as zero
+// (no access outside them); the extra results are never passed to epi.
 template <int NMAX, int NT, bool TA, bool TB, int TI, int TJ, int UK, class Epi>
 __device__ __forceinline__ void gemm_mt(const double* __restrict__ A, const double* __restrict__ B, int kd,
                         const double* __restrict__ A2, const double* __restrict__ B2, int kd2, double s2, int nr,
@@ -542,7 +503,8 @@ __device__ __forceinline__ void gemm_mg(const double* __restrict__ A, const doub
 }
 
 // small products (the occupied-virtual step) on the matrix cores where the tiles fit
-// the buffers, else on the vector units; the n x n products (gemm_g) stay on the
+// the buffers (one tile per wave, four k-steps of loads in flight), else on the
+// vector units; the n x n products (gemm_g) stay on the
 // vector units for LDS-resident matrices, which measured faster there, and use the
 // matrix cores when the matrices live in global scratch
 template <int NMAX, int NT, bool TA, bool TB, class Epi>
@@ -552,7 +514,7 @@ __device__ __forceinline__ void gemm_e(const double* __restrict__ A, const doubl
   if constexpr (kMatrixCores && Cfg<NMAX, NT>::GM)
     gemm_mg<NMAX, NT, TA, TB>(A, B, kd, A2, B2, kd2, s2, nr, nc, epi);
   else if constexpr (kMatrixCores && NMAX % 16 == 0)
-    gemm_m<NMAX, NT, TA, TB>(A, B, kd, A2, B2, kd2, s2, nr, nc, epi);
+    gemm_mt<NMAX, NT, TA, TB, 1, 1, 4>(A, B, kd, A2, B2, kd2, s2, nr, nc, epi);
   else
     gemm_v<NMAX, NT, TA, TB>(A, B, kd, A2, B2, kd2, s2, nr, nc, epi);
 }
@@ -593,6 +555,66 @@ __device__ __forceinline__ double dotp(const double* __restrict__ a, int sa, con
   }
   for (; k < len; ++k) s = fma(a[k * sa], b[k * sb], s);
   return s;
+}
+
+// Elementwise pass over the leading n x n block of two matrices in global
+// scratch (leading dimension NMAX): f(i, j, g1[i][j], g2[i][j]) for every
+// element, lane = column, rows dealt to the 64-lane row groups.  The loads of
+// UR rows are issued before their uses, so a pass pays one memory latency per
+// UR rows; indices are clamped into the block (no load leaves it) and clamped
+// elements are not passed to f.
+template <int NMAX, int NT, int UR = 4, class F>
+__device__ __forceinline__ void ew_global(const double* __restrict__ g1, const double* __restrict__ g2, int n, F f) {
+  constexpr int RG = NT / 64;
+  const int lane = threadIdx.x & 63, rgrp = threadIdx.x >> 6;
+  for (int j0 = 0; j0 < n; j0 += 64) {
+    const int j = j0 + lane, jc = j < n ? j : n - 1;
+    for (int i0 = rgrp; i0 < n; i0 += UR * RG) {
+      double x[UR], y[UR];
+#pragma unroll
+      for (int u = 0; u < UR; ++u) {
+        const int i = min(i0 + u * RG, n - 1);
+        x[u] = g1[i * NMAX + jc];
+        y[u] = g2[i * NMAX + jc];
+      }
+#pragma unroll
+      for (int u = 0; u < UR; ++u)
+        if (i0 + u * RG < n && j < n) f(i0 + u * RG, j, x[u], y[u]);
+    }
+  }
+}
+
+// Site potential V_t = field . R_t + sum_s gamma_ts dq_s for t < na (gamma in
+// global scratch, symmetric, leading dimension ld).  Eight lanes share a site:
+// each sums every eighth term with its loads issued four at a time, then a
+// butterfly over the eight lanes (fixed order); the group's first lane writes V.
+template <int NT>
+__device__ __forceinline__ void site_potential(const double* __restrict__ gG, int ld, const double* __restrict__ dq,
+                                               const double* __restrict__ pos, const double* fld, int na,
+                                               double* __restrict__ V) {
+  constexpr int SP = 8, UK = 4;
+  const int tid = threadIdx.x, part = tid & (SP - 1);
+  for (int t0 = 0; t0 < na; t0 += NT / SP) {
+    const int t = t0 + tid / SP;
+    const int tc = t < na ? t : na - 1;
+    double s = 0.0;
+    for (int k0 = part; k0 < na; k0 += UK * SP) {
+      double g[UK], q[UK];
+#pragma unroll
+      for (int u = 0; u < UK; ++u) {
+        const int k = k0 + u * SP;
+        const int kc = k < na ? k : na - 1;
+        g[u] = gG[kc * ld + tc];
+        q[u] = k < na ? dq[kc] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < UK; ++u) s = fma(g[u], q[u], s);
+    }
+    s += __shfl_xor(s, 1);
+    s += __shfl_xor(s, 2);
+    s += __shfl_xor(s, 4);
+    if (part == 0 && t < na) V[t] = fld[0] * pos[t * 3] + fld[1] * pos[t * 3 + 1] + fld[2] * pos[t * 3 + 2] + s;
+  }
 }
 
 // e = q w + r (0 <= r < w) without an integer division: float reciprocal and one correction
@@ -798,11 +820,10 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
     bool use_chol = true;
     if (warm) {
       const double* wc = a.ws_C + a.ws_off[u];
-      for (int i = rgrp; i < n; i += RG)
-        for (int j = lane; j < n; j += 64) {
-          sX[i * LD + j] = wc[i * NMAX + j];
-          sA[i * LD + j] = gS[i * NMAX + j];
-        }
+      ew_global<NMAX, NT>(wc, gS, n, [&](int i, int j, double c, double sv) {
+        sX[i * LD + j] = c;
+        sA[i * LD + j] = sv;
+      });
       __syncthreads();
       gemm<NMAX, NT, false>(sA, sX, sT, n);  // T = S C0
       __syncthreads();
@@ -824,8 +845,7 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
           sX = sT;
           sT = tmp;
           if (0.75 * e * e < kNsTol * 1e-2) break;  // the next M would be I to rounding
-          for (int i = rgrp; i < n; i += RG)
-            for (int j = lane; j < n; j += 64) sA[i * LD + j] = gS[i * NMAX + j];
+          ew_global<NMAX, NT>(gS, gS, n, [&](int i, int j, double sv, double) { sA[i * LD + j] = sv; });
           __syncthreads();
           gemm<NMAX, NT, false>(sA, sX, sT, n);  // S X
           __syncthreads();
@@ -838,11 +858,10 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
         }
       }
     } else {
-      for (int i = rgrp; i < n; i += RG)
-        for (int j = lane; j < n; j += 64) {
-          sX[i * LD + j] = (i == j) ? 1.0 : 0.0;
-          sA[i * LD + j] = gS[i * NMAX + j];
-        }
+      ew_global<NMAX, NT>(gS, gS, n, [&](int i, int j, double sv, double) {
+        sX[i * LD + j] = (i == j) ? 1.0 : 0.0;
+        sA[i * LD + j] = sv;
+      });
       __syncthreads();
     }
     // right-looking Cholesky of M fused with the solve X R = C0
@@ -877,16 +896,13 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
     int it_best = 0;
     if (status == 0) {
       for (it = 1; it <= a.max_iter; ++it) {
-        // V = gamma Dq_in + field . R (gamma symmetric: column walk is coalesced)
-        for (int t = tid; t < na; t += NT) {
-          const double v = sh.fld[0] * sPos[t * 3] + sh.fld[1] * sPos[t * 3 + 1] + sh.fld[2] * sPos[t * 3 + 2];
-          sV[t] = v + dotp(gG + t, NMAX, sDqIn, 1, na);
-        }
+        // V = gamma Dq_in + field . R
+        site_potential<NT>(gG, NMAX, sDqIn, sPos, sh.fld, na, sV);
         __syncthreads();
         // H = H0 + 1/2 S o (V_a + V_b) into sA
-        for (int i = rgrp; i < n; i += RG)
-          for (int j = lane; j < n; j += 64)
-            sA[i * LD + j] = gH0[i * NMAX + j] + 0.5 * gS[i * NMAX + j] * (sV[sOrbAtom[i]] + sV[sOrbAtom[j]]);
+        ew_global<NMAX, NT>(gH0, gS, n, [&](int i, int j, double h, double sv) {
+          sA[i * LD + j] = h + 0.5 * sv * (sV[sOrbAtom[i]] + sV[sOrbAtom[j]]);
+        });
         __syncthreads();
 
         gemm<NMAX, NT, false>(sA, sX, sT, n);  // T = H X
@@ -1322,22 +1338,18 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
       // W = 2 C_occ diag(eps_occ) C_occ^T = 1/2 P H P with H of the last iteration
       // (sV still holds its V; X_occ spans the occupied eigenspace, so no
       // eigenvalues are needed).  X is free after the basis store above.
-      for (int i = rgrp; i < n; i += RG)
-        for (int j = lane; j < n; j += 64)
-          sA[i * LD + j] = 0.5 * (gH0[i * NMAX + j] + 0.5 * gS[i * NMAX + j] * (sV[sOrbAtom[i]] + sV[sOrbAtom[j]]));
+      ew_global<NMAX, NT>(gH0, gS, n, [&](int i, int j, double h, double sv) {
+        sA[i * LD + j] = 0.5 * (h + 0.5 * sv * (sV[sOrbAtom[i]] + sV[sOrbAtom[j]]));
+      });
       __syncthreads();
       gemm<NMAX, NT, false>(sA, sT, sX, n);  // (H / 2) P
       __syncthreads();
       gemm<NMAX, NT, false>(sT, sX, sA, n);  // W = P (H / 2) P
       // V from the output charges (with the field potential)
-      for (int t = tid; t < na; t += NT) {
-        const double v = sh.fld[0] * sPos[t * 3] + sh.fld[1] * sPos[t * 3 + 1] + sh.fld[2] * sPos[t * 3 + 2];
-        sV[t] = v + dotp(gG + t, NMAX, sDqOut, 1, na);
-      }
+      site_potential<NT>(gG, NMAX, sDqOut, sPos, sh.fld, na, sV);
       __syncthreads();
       double ebp = 0.0;
-      for (int i = rgrp; i < n; i += RG)
-        for (int j = lane; j < n; j += 64) ebp += sT[i * LD + j] * gH0[i * NMAX + j];
+      ew_global<NMAX, NT>(gH0, gH0, n, [&](int i, int j, double h, double) { ebp += sT[i * LD + j] * h; });
       // 1/2 Dq gamma Dq + Dq (field . R): V already holds the field potential once
       double ecp = 0.0;
       for (int t = tid; t < na; t += NT) {
