@@ -909,14 +909,39 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
         __syncthreads();
         gemm<NMAX, NT, true>(sX, sT, sA, n);  // A = X^T H X
         __syncthreads();
+        // Symmetrise A.  With the occupied columns first the same pass takes the
+        // block statistics of the occupied-virtual step below and its start
+        // K0 = A_ov / (d_v - d_o), into a slot of sT (slots: columns [0, nv) and
+        // [nv, 2 nv) of sT; the last Sylvester sweep writes the first).  Each
+        // unordered pair is read and written by one thread; the diagonal is only read.
+        const int nv = n - nocc;
+        const bool ov_try = ordered && nocc > 0 && nv > 0 && 2 * nv <= n;  // K ping-pong needs 2 n_v <= n
+        const int s0 = (kSylvester & 1) ? nv : 0;
+        double st[4] = {0.0, 0.0, -INFINITY, -INFINITY};  // off-block, ov, max d_o, -min d_v
         for (int i = rgrp; i < n; i += RG)
-          for (int j = lane; j < n; j += 64)
+          for (int j = lane; j < n; j += 64) {
             if (j > i) {
               const double v = 0.5 * (sA[i * LD + j] + sA[j * LD + i]);
               sA[i * LD + j] = v;
               sA[j * LD + i] = v;
+              if (i < nocc && j >= nocc) {
+                st[1] = fmax(st[1], fabs(v));
+                if (ov_try) sT[i * LD + s0 + j - nocc] = v / (sA[j * LD + j] - sA[i * LD + i]);
+              } else {
+                st[0] = fmax(st[0], fabs(v));
+              }
+            } else if (j == i) {
+              const double d = sA[i * LD + i];
+              if (i < nocc)
+                st[2] = fmax(st[2], d);
+              else
+                st[3] = fmax(st[3], -d);
             }
-        __syncthreads();
+          }
+        if (ov_try)
+          block_max_n<NT, 4>(st, sRed);  // also orders the writes of A and K0
+        else
+          __syncthreads();
 
         // ---- occupied-virtual step.  With the occupied columns first, rotate X by
         // the exactly orthogonal Cayley transform U = (I + B)(I - B)^{-1},
@@ -925,28 +950,9 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
         // on the Sylvester equation from K = A_ov / (d_v - d_o)).  Then
         //   X_occ <- X_occ - Z K^T - 2 X_v Y^T,  X_v <- X_v + 2 Z + 2 X_v (G - I),
         // G = (I + L^T L)^{-1} (Neumann series), Y = L G, Z = X_occ Y.
-        const int nv = n - nocc;
         bool use_ov = false;
         double kmax = 0.0;
-        if (ordered && nocc > 0 && nv > 0 && 2 * nv <= n) {  // K ping-pong needs 2 n_v <= n
-          // one pass over A: block statistics, and K0 = A_ov / (d_v - d_o) into its slot of sT
-          // (slots: columns [0, nv) and [nv, 2 nv) of sT; the last Sylvester sweep writes the first)
-          const int s0 = (kSylvester & 1) ? nv : 0;
-          double st[4] = {0.0, 0.0, -INFINITY, -INFINITY};  // off-block, ov, max d_o, -min d_v
-          for (int i = rgrp; i < n; i += RG)
-            for (int j = lane; j < n; j += 64) {
-              const double v = sA[i * LD + j];
-              if (i == j) {
-                if (i < nocc) st[2] = fmax(st[2], v);
-                else st[3] = fmax(st[3], -v);
-              } else if ((i < nocc) == (j < nocc)) {
-                st[0] = fmax(st[0], fabs(v));
-              } else {
-                st[1] = fmax(st[1], fabs(v));
-                if (i < nocc) sT[i * LD + s0 + j - nocc] = v / (sA[j * LD + j] - sA[i * LD + i]);
-              }
-            }
-          block_max_n<NT, 4>(st, sRed);  // also orders the K0 writes
+        if (ov_try) {
           const double gap = -st[3] - st[2];
           use_ov = gap > kOvGap && st[1] < kOvAngle * gap && st[0] < kOvOff * gap;
           double lf2 = 0.0;  // ||L||_F^2
