@@ -250,6 +250,20 @@ int cavdftb_init_photons(cavdftb_ctx* ctx, const double* r, double* qm, double* 
 #define CAVDFTB_N_OBS 8
 int cavdftb_step(cavdftb_ctx* ctx, double* r, double* p, double* qm, double* pm, int32_t n_steps, double dt,
                  int32_t born_mode, double h_fd, double* obs);
+
+/* MD steps as replays of one captured hipGraph (the launch sequence of one step
+ * of cavdftb_step, on the context stream).  With enable != 0, cavdftb_step
+ * replays the graph for every step whose launch sequence is steady: the context
+ * has stepped before (primed), timing (cavdftb_enable_timing) is off, and warm
+ * starts are off or their charge extrapolation has its full depth (from the
+ * fourth MD step after creation, cavdftb_eval_units or cavdftb_reset_warm_start).
+ * Other steps are issued eagerly.  The graph is captured again when an argument
+ * of cavdftb_step or any setting changes; results equal the eager ones bit for
+ * bit (the same launches with the same arguments).  The obs rows are selected by
+ * a device counter reset at the start of each cavdftb_step call.  Returns
+ * CAVDFTB_EINVAL when enabling on a context created on the null stream, which
+ * cannot be captured.  Counters: graph_replays and graph_captures. */
+int cavdftb_set_graph(cavdftb_ctx* ctx, int32_t enable);
 int cavdftb_invalidate(cavdftb_ctx* ctx);
 
 /* Wait for the context stream; n_bad_units (host, may be NULL) receives the
@@ -271,6 +285,8 @@ typedef struct cavdftb_counters {
   int64_t surrogate_fallback_units;  /* units recomputed by the exact route in surrogate mode */
   int64_t jacobi_iterations;         /* SCC iterations that diagonalised by full Jacobi (the others took
                                         one occupied-virtual rotation of the previous basis) */
+  int64_t graph_replays;             /* MD steps run as graph replays (cavdftb_set_graph) */
+  int64_t graph_captures;            /* graph captures of the MD step */
 } cavdftb_counters;
 int cavdftb_enable_timing(cavdftb_ctx* ctx, int32_t enable);
 int cavdftb_read_counters(cavdftb_ctx* ctx, cavdftb_counters* out);

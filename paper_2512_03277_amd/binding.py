@@ -40,7 +40,8 @@ class Layout(ctypes.Structure):
 class Counters(ctypes.Structure):
     _fields_ = [("scc_jobs", ctypes.c_int64), ("scc_iterations", ctypes.c_int64), ("scc_flops", _c_d),
                 ("scc_kernel_ms", _c_d), ("scc_launches", ctypes.c_int64), ("jacobi_sweeps", ctypes.c_int64),
-                ("surrogate_fallback_units", ctypes.c_int64), ("jacobi_iterations", ctypes.c_int64)]
+                ("surrogate_fallback_units", ctypes.c_int64), ("jacobi_iterations", ctypes.c_int64),
+                ("graph_replays", ctypes.c_int64), ("graph_captures", ctypes.c_int64)]
 
 
 SYMBOLS = {
@@ -57,6 +58,7 @@ SYMBOLS = {
     "cavdftb_set_surrogate": (ctypes.c_int, [_vp, _vp, _vp, _c_d]),
     "cavdftb_set_fallback": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "cavdftb_set_schedule": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32]),
+    "cavdftb_set_graph": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "cavdftb_sg_features": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "cavdftb_sg_prep": (ctypes.c_int, [_vp, _vp, _c_i32, _c_i32, _vp, _vp, _vp]),
     "cavdftb_sg_forward": (ctypes.c_int, [_vp, _vp, _c_i32, _vp, _vp, _vp]),
@@ -191,6 +193,9 @@ class Context:
 
     def set_schedule(self, job_queue=True, max_wg_per_cu=0):
         self._check(self.lib.cavdftb_set_schedule(self.ctx, int(bool(job_queue)), int(max_wg_per_cu)), "set_schedule")
+
+    def set_graph(self, enable=True):
+        self._check(self.lib.cavdftb_set_graph(self.ctx, int(bool(enable))), "set_graph")
 
     def set_warm_start(self, enable):
         self._check(self.lib.cavdftb_set_warm_start(self.ctx, int(bool(enable))), "set_warm_start")

@@ -127,6 +127,18 @@ struct cavdftb_ctx {
   int warm_enabled = 1;
   bool warm_valid = false;
   bool primed = false;
+  // MD steps as replays of one captured hipGraph
+  bool use_graph = false;
+  uint64_t gen = 1;                // bumped by every call that changes what a step launches
+  uint64_t graph_gen = 0;          // gen the graph was captured at
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  const void* graph_key[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // r, p, qm, pm, obs
+  double graph_dt = 0.0, graph_h = 0.0;
+  int32_t graph_born = -1;
+  int64_t graph_scc_launches = 0;  // SCC launches inside the graph
+  int64_t graph_replays = 0, graph_captures = 0;
+  unsigned int* d_obs_row = nullptr;  // row of obs the next observables launch writes
   // timing
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending, ev_free;
@@ -155,8 +167,16 @@ hipError_t dalloc(cavdftb_ctx* c, T** p, size_t count) {
   return e;
 }
 
+void drop_graph(cavdftb_ctx* c) {
+  if (c->graph_exec) hipGraphExecDestroy(c->graph_exec);
+  if (c->graph) hipGraphDestroy(c->graph);
+  c->graph_exec = nullptr;
+  c->graph = nullptr;
+}
+
 void release(cavdftb_ctx* c) {
   if (c->stream) hipStreamSynchronize(c->stream);
+  drop_graph(c);
   for (void* p : c->allocs) hipFree(p);
   c->allocs.clear();
   for (auto& pr : c->ev_pending) {
@@ -415,6 +435,84 @@ int matter_stage(cavdftb_ctx* c, const double* r, int born_mode, double h) {
   return CAVDFTB_OK;
 }
 
+// the launches of one MD step (velocity Verlet with the cavity field; the
+// matter stage and the cavity force at the new positions in between)
+int issue_step(cavdftb_ctx* c, double* r, double* p, double* qm, double* pm, double dt, int32_t born_mode,
+               double h_fd, double* obs) {
+  hipStream_t s = c->stream;
+  CavArgs ca = cav_args(c);
+  hipError_t e = launch_photon_kick(c->M, c->d_omega, c->d_lam, c->d_F, dt, pm, 0, qm, s);
+  if (e == hipSuccess)
+    e = launch_kick_drift(c->NA, c->d_atom_unit, c->d_inv_mass, c->d_forces, c->d_zpol, c->d_field, dt, r, p, 1, s);
+  if (e != hipSuccess) return hip_fail(c, e, "step kick/drift");
+  int rc = matter_stage(c, r, born_mode, h_fd);
+  if (rc) return rc;
+  e = launch_cav_scatter(ca, c->d_mu_pol, c->d_F, nullptr, s);
+  if (e == hipSuccess) e = launch_cav_gather(ca, qm, c->d_F, c->d_field, s);  // old q
+  if (e == hipSuccess)
+    e = launch_kick_drift(c->NA, c->d_atom_unit, c->d_inv_mass, c->d_forces, c->d_zpol, c->d_field, dt, r, p, 0, s);
+  if (e == hipSuccess) e = launch_photon_kick(c->M, c->d_omega, c->d_lam, c->d_F, dt, pm, 1, qm, s);
+  if (e == hipSuccess) e = launch_cav_gather(ca, qm, c->d_F, c->d_field, s);  // rotated q
+  if (e == hipSuccess && obs)
+    e = launch_observables(c->U, c->NA, c->M, c->d_unit_off, c->d_mass, p, c->d_energy, qm, pm, c->d_omega, c->d_lam,
+                           c->d_F, c->d_mu_pol, c->d_status, c->d_cjob_iters, c->U, obs, c->d_obs_row, s);
+  if (e != hipSuccess) return hip_fail(c, e, "step cavity/kick");
+  return CAVDFTB_OK;
+}
+
+// true when the launches of the next MD step are those of the step after it:
+// primed, no per-launch timing events, a capturable stream, and the warm-start
+// extrapolation at its full depth (or warm starts off)
+bool graph_steady(const cavdftb_ctx* c) {
+  return c->use_graph && c->primed && !c->timing && c->stream != nullptr &&
+         (!c->warm_enabled || (c->warm_valid && c->md_hist >= 3));
+}
+
+// one MD step as a replay of the captured graph; captured (again) when the
+// arguments or a setting changed since the last capture
+int replay_step(cavdftb_ctx* c, double* r, double* p, double* qm, double* pm, double dt, int32_t born_mode,
+                double h_fd, double* obs) {
+  const void* key[5] = {r, p, qm, pm, obs};
+  bool same = c->graph_exec && c->graph_gen == c->gen && c->graph_dt == dt && c->graph_h == h_fd &&
+              c->graph_born == born_mode;
+  for (int k = 0; k < 5 && same; ++k) same = c->graph_key[k] == key[k];
+  if (!same) {
+    drop_graph(c);
+    hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(c, e, "graph capture begin");
+    const int64_t l0 = c->launches;
+    const int rc = issue_step(c, r, p, qm, pm, dt, born_mode, h_fd, obs);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(c->stream, &g);
+    if (rc) {
+      if (g) hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "graph capture end");
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      hipGraphDestroy(g);
+      return hip_fail(c, e, "graph instantiate");
+    }
+    c->graph = g;
+    c->graph_exec = x;
+    c->graph_gen = c->gen;
+    c->graph_dt = dt;
+    c->graph_h = h_fd;
+    c->graph_born = born_mode;
+    for (int k = 0; k < 5; ++k) c->graph_key[k] = key[k];
+    c->graph_scc_launches = c->launches - l0;
+    c->launches = l0;
+    c->graph_captures += 1;
+  }
+  const hipError_t e = hipGraphLaunch(c->graph_exec, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "graph launch");
+  c->launches += c->graph_scc_launches;
+  c->graph_replays += 1;
+  return CAVDFTB_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -573,6 +671,7 @@ int cavdftb_create(const cavdftb_params* params, const cavdftb_layout* L, void* 
   }
   CK(dalloc(c, &c->d_counters, 8));
   CK(dalloc(c, &c->d_job_counter, 1));
+  CK(dalloc(c, &c->d_obs_row, 1));
   CK(hipMemcpy(c->d_unit_off, c->h_unit_off.data(), (U + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
   CK(hipMemcpy(c->d_species, L->species, NA, hipMemcpyHostToDevice));
   CK(hipMemcpy(c->d_unit_x, L->unit_x, U * sizeof(double), hipMemcpyHostToDevice));
@@ -676,6 +775,7 @@ int cavdftb_destroy(cavdftb_ctx* ctx) {
 
 int cavdftb_set_scc(cavdftb_ctx* ctx, double tol, int32_t max_iter, double mix_alpha) {
   if (!ctx) return CAVDFTB_EINVAL;
+  ctx->gen += 1;
   if (!(tol > 0.0) || max_iter < 1 || !(mix_alpha > 0.0) || mix_alpha > 1.0)
     return fail(ctx, CAVDFTB_EINVAL, "set_scc: need tol > 0, max_iter >= 1, 0 < alpha <= 1");
   ctx->tol = tol;
@@ -686,6 +786,7 @@ int cavdftb_set_scc(cavdftb_ctx* ctx, double tol, int32_t max_iter, double mix_a
 
 int cavdftb_set_tuning(cavdftb_ctx* ctx, double jacobi_res_factor, int32_t keep_mixer_history) {
   if (!ctx) return CAVDFTB_EINVAL;
+  ctx->gen += 1;
   if (!(jacobi_res_factor >= 0.0) || jacobi_res_factor > 1.0)
     return fail(ctx, CAVDFTB_EINVAL, "set_tuning: need 0 <= jacobi_res_factor <= 1");
   ctx->jac_factor = jacobi_res_factor;
@@ -695,6 +796,7 @@ int cavdftb_set_tuning(cavdftb_ctx* ctx, double jacobi_res_factor, int32_t keep_
 
 int cavdftb_set_schedule(cavdftb_ctx* ctx, int32_t job_queue, int32_t max_wg_per_cu) {
   if (!ctx) return CAVDFTB_EINVAL;
+  ctx->gen += 1;
   if (max_wg_per_cu < 0) return fail(ctx, CAVDFTB_EINVAL, "set_schedule: need max_wg_per_cu >= 0");
   ctx->dynamic_jobs = job_queue ? 1 : 0;
   for (Bucket& b : ctx->buckets) {
@@ -706,6 +808,7 @@ int cavdftb_set_schedule(cavdftb_ctx* ctx, int32_t job_queue, int32_t max_wg_per
 
 int cavdftb_set_warm_start(cavdftb_ctx* ctx, int32_t enable) {
   if (!ctx) return CAVDFTB_EINVAL;
+  ctx->gen += 1;
   ctx->warm_enabled = enable ? 1 : 0;
   if (!enable) ctx->warm_valid = false;
   return CAVDFTB_OK;
@@ -713,6 +816,7 @@ int cavdftb_set_warm_start(cavdftb_ctx* ctx, int32_t enable) {
 
 int cavdftb_reset_warm_start(cavdftb_ctx* ctx) {
   if (!ctx) return CAVDFTB_EINVAL;
+  ctx->gen += 1;
   ctx->warm_valid = false;
   ctx->md_hist = 0;
   return CAVDFTB_OK;
@@ -722,6 +826,7 @@ int cavdftb_eval_units(cavdftb_ctx* ctx, const double* pos, double* energy, doub
                        double* dipole, int32_t* unit_status) {
   if (!ctx || !pos || !unit_status) return ctx ? fail(ctx, CAVDFTB_EINVAL, "eval_units: null pointer")
                                                : CAVDFTB_EINVAL;
+  ctx->gen += 1;
   const bool want_f = energy || forces;
   const int32_t flags = center_flags(ctx, want_f);
   for (const Bucket& b : ctx->buckets) {
@@ -754,6 +859,7 @@ int cavdftb_born_charges(cavdftb_ctx* ctx, const double* pos, int32_t mode, doub
   if (mode != CAVDFTB_BORN_MULLIKEN && !(h > 0.0)) return fail(ctx, CAVDFTB_EINVAL, "born_charges: need h > 0");
   if (mode == CAVDFTB_BORN_SURROGATE && !ctx->sg_ready)
     return fail(ctx, CAVDFTB_EINVAL, "born_charges: no surrogate set (cavdftb_set_surrogate)");
+  ctx->gen += 1;
   int rc = eval_center(ctx, pos, false);
   if (rc) return rc;
   ctx->primed = false;
@@ -798,6 +904,7 @@ int cavdftb_cavity_forces(cavdftb_ctx* ctx, const double* mu_pol, const double* 
 
 int cavdftb_set_surrogate(cavdftb_ctx* ctx, const float* params, const float* norm, double std_threshold) {
   if (!ctx) return CAVDFTB_EINVAL;
+  ctx->gen += 1;
   if (!params || !norm || !(std_threshold >= 0.0))
     return fail(ctx, CAVDFTB_EINVAL, "set_surrogate: need params, norm and a threshold >= 0");
   hipError_t e = hipMemcpyAsync(ctx->d_sg_params, params,
@@ -814,6 +921,7 @@ int cavdftb_set_surrogate(cavdftb_ctx* ctx, const float* params, const float* no
 
 int cavdftb_set_fallback(cavdftb_ctx* ctx, int32_t mode) {
   if (!ctx) return CAVDFTB_EINVAL;
+  ctx->gen += 1;
   if (mode != CAVDFTB_BORN_FD && mode != CAVDFTB_BORN_FIELD)
     return fail(ctx, CAVDFTB_EINVAL, "set_fallback: mode must be CAVDFTB_BORN_FD or CAVDFTB_BORN_FIELD");
   ctx->fallback_mode = mode;
@@ -885,6 +993,7 @@ int cavdftb_sg_to_local(const double* frames, const double* born, const double* 
 
 int cavdftb_init_photons(cavdftb_ctx* ctx, const double* r, double* qm, double* pm) {
   if (!ctx) return CAVDFTB_EINVAL;
+  ctx->gen += 1;
   if (!r || !qm || !pm) return fail(ctx, CAVDFTB_EINVAL, "init_photons: null pointer");
   int rc = eval_center(ctx, r, false);
   if (rc) return rc;
@@ -899,6 +1008,7 @@ int cavdftb_init_photons(cavdftb_ctx* ctx, const double* r, double* qm, double* 
 
 int cavdftb_invalidate(cavdftb_ctx* ctx) {
   if (!ctx) return CAVDFTB_EINVAL;
+  ctx->gen += 1;
   ctx->primed = false;
   return CAVDFTB_OK;
 }
@@ -924,26 +1034,14 @@ int cavdftb_step(cavdftb_ctx* ctx, double* r, double* p, double* qm, double* pm,
     if (e != hipSuccess) return hip_fail(ctx, e, "step prime");
     ctx->primed = true;
   }
+  if (obs) {
+    e = launch_set_u32(ctx->d_obs_row, 0u, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "step obs row");
+  }
   for (int st = 0; st < n_steps; ++st) {
-    e = launch_photon_kick(ctx->M, ctx->d_omega, ctx->d_lam, ctx->d_F, dt, pm, 0, qm, s);
-    if (e == hipSuccess)
-      e = launch_kick_drift(ctx->NA, ctx->d_atom_unit, ctx->d_inv_mass, ctx->d_forces, ctx->d_zpol, ctx->d_field,
-                            dt, r, p, 1, s);
-    if (e != hipSuccess) return hip_fail(ctx, e, "step kick/drift");
-    rc = matter_stage(ctx, r, born_mode, h_fd);
+    rc = graph_steady(ctx) ? replay_step(ctx, r, p, qm, pm, dt, born_mode, h_fd, obs)
+                           : issue_step(ctx, r, p, qm, pm, dt, born_mode, h_fd, obs);
     if (rc) return rc;
-    e = launch_cav_scatter(ca, ctx->d_mu_pol, ctx->d_F, nullptr, s);
-    if (e == hipSuccess) e = launch_cav_gather(ca, qm, ctx->d_F, ctx->d_field, s);  // old q
-    if (e == hipSuccess)
-      e = launch_kick_drift(ctx->NA, ctx->d_atom_unit, ctx->d_inv_mass, ctx->d_forces, ctx->d_zpol, ctx->d_field,
-                            dt, r, p, 0, s);
-    if (e == hipSuccess) e = launch_photon_kick(ctx->M, ctx->d_omega, ctx->d_lam, ctx->d_F, dt, pm, 1, qm, s);
-    if (e == hipSuccess) e = launch_cav_gather(ca, qm, ctx->d_F, ctx->d_field, s);  // rotated q
-    if (e == hipSuccess && obs)
-      e = launch_observables(ctx->U, ctx->NA, ctx->M, ctx->d_unit_off, ctx->d_mass, p, ctx->d_energy, qm, pm,
-                             ctx->d_omega, ctx->d_lam, ctx->d_F, ctx->d_mu_pol, ctx->d_status, ctx->d_cjob_iters,
-                             ctx->U, obs + (int64_t)st * CAVDFTB_N_OBS, s);
-    if (e != hipSuccess) return hip_fail(ctx, e, "step cavity/kick");
   }
   return CAVDFTB_OK;
 }
@@ -963,8 +1061,21 @@ int cavdftb_sync(cavdftb_ctx* ctx, int32_t* n_bad_units) {
   return CAVDFTB_OK;
 }
 
+int cavdftb_set_graph(cavdftb_ctx* ctx, int32_t enable) {
+  if (!ctx) return CAVDFTB_EINVAL;
+  if (enable && !ctx->stream) return fail(ctx, CAVDFTB_EINVAL, "set_graph: the null stream cannot be captured");
+  ctx->gen += 1;
+  ctx->use_graph = enable != 0;
+  if (!ctx->use_graph) {
+    if (ctx->stream) hipStreamSynchronize(ctx->stream);
+    drop_graph(ctx);
+  }
+  return CAVDFTB_OK;
+}
+
 int cavdftb_enable_timing(cavdftb_ctx* ctx, int32_t enable) {
   if (!ctx) return CAVDFTB_EINVAL;
+  ctx->gen += 1;
   ctx->timing = enable != 0;
   return CAVDFTB_OK;
 }
@@ -988,6 +1099,8 @@ int cavdftb_read_counters(cavdftb_ctx* ctx, cavdftb_counters* out) {
   if (e != hipSuccess) return hip_fail(ctx, e, "counters copy");
   out->surrogate_fallback_units = (int64_t)h45[0];
   out->jacobi_iterations = (int64_t)h45[1];
+  out->graph_replays = ctx->graph_replays;
+  out->graph_captures = ctx->graph_captures;
   return CAVDFTB_OK;
 }
 
@@ -1000,6 +1113,8 @@ int cavdftb_reset_counters(cavdftb_ctx* ctx) {
   harvest_events(ctx);
   ctx->t_ms = 0.0;
   ctx->launches = 0;
+  ctx->graph_replays = 0;
+  ctx->graph_captures = 0;
   return CAVDFTB_OK;
 }
 

@@ -115,7 +115,10 @@ hipError_t launch_observables(int n_units, int n_atoms, int n_modes, const int32
                               const double* mass, const double* p, const double* energy,
                               const double* qm, const double* pm, const double* omega, const double* lam,
                               const double* F, const double* mu_pol, const int32_t* status,
-                              const int32_t* job_iters, int n_jobs, double* obs, hipStream_t s);
+                              const int32_t* job_iters, int n_jobs, double* obs, unsigned int* obs_row,
+                              hipStream_t s);
+// *c = v by a one-thread kernel (a kernel node, not a memset, inside captured graphs)
+hipError_t launch_set_u32(unsigned int* c, unsigned int v, hipStream_t s);
 
 // ---- surrogate kernels (sg_kernels.hip) ----
 hipError_t launch_sg_features(int n_atoms, const int32_t* atom_unit, const int32_t* unit_off, const int8_t* species,

@@ -216,7 +216,9 @@ __global__ __launch_bounds__(kNT) void photon_kernel(int nm, const double* __res
   pm[m] = p;
 }
 
-// one workgroup: fixed-order totals for the observables of one step
+// one workgroup: fixed-order totals for the observables of one step, written to
+// row *obs_row of obs; the row counter then advances (one launch per MD step, so
+// the same launch can be replayed from a captured graph)
 __global__ __launch_bounds__(kNT) void observables_kernel(int nu, int na, int nm, const int32_t* __restrict__ uoff,
                                                           const double* __restrict__ mass,
                                                           const double* __restrict__ p,
@@ -229,7 +231,8 @@ __global__ __launch_bounds__(kNT) void observables_kernel(int nu, int na, int nm
                                                           const double* __restrict__ mu_pol,
                                                           const int32_t* __restrict__ status,
                                                           const int32_t* __restrict__ iters, int n_jobs,
-                                                          double* __restrict__ obs) {
+                                                          double* __restrict__ obs,
+                                                          unsigned int* __restrict__ obs_row) {
   __shared__ double red[kNT];
   double ke = 0.0, v = 0.0, eph = 0.0, tsum = 0.0, nbad = 0.0, its = 0.0, mus = 0.0;
   for (int u = threadIdx.x; u < nu; u += kNT) {
@@ -263,16 +266,23 @@ __global__ __launch_bounds__(kNT) void observables_kernel(int nu, int na, int nm
   its = wg_sum(its, red);
   mus = wg_sum(mus, red);
   if (threadIdx.x == 0) {
-    obs[0] = ke;
-    obs[1] = v;
-    obs[2] = eph;
-    obs[3] = ke + v + eph;
-    obs[4] = tsum / nu;
-    obs[5] = nbad;
-    obs[6] = its;
-    obs[7] = mus;
+    const unsigned int row = *obs_row;
+    double* o = obs + (size_t)row * 8;
+    o[0] = ke;
+    o[1] = v;
+    o[2] = eph;
+    o[3] = ke + v + eph;
+    o[4] = tsum / nu;
+    o[5] = nbad;
+    o[6] = its;
+    o[7] = mus;
+    *obs_row = row + 1u;
   }
   (void)na;
+}
+
+__global__ void set_u32_kernel(unsigned int* c, unsigned int v) {
+  if (threadIdx.x == 0) c[0] = v;
 }
 
 inline int nblk(int n) { return (n + kNT - 1) / kNT; }
@@ -362,9 +372,14 @@ hipError_t launch_observables(int n_units, int n_atoms, int n_modes, const int32
                               const double* p, const double* energy, const double* qm, const double* pm,
                               const double* omega, const double* lam, const double* F, const double* mu_pol,
                               const int32_t* status, const int32_t* job_iters, int n_jobs, double* obs,
-                              hipStream_t s) {
+                              unsigned int* obs_row, hipStream_t s) {
   hipLaunchKernelGGL(observables_kernel, dim3(1), dim3(kNT), 0, s, n_units, n_atoms, n_modes, unit_off, mass, p,
-                     energy, qm, pm, omega, lam, F, mu_pol, status, job_iters, n_jobs, obs);
+                     energy, qm, pm, omega, lam, F, mu_pol, status, job_iters, n_jobs, obs, obs_row);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_u32(unsigned int* c, unsigned int v, hipStream_t s) {
+  hipLaunchKernelGGL(set_u32_kernel, dim3(1), dim3(64), 0, s, c, v);
   return hipGetLastError();
 }
 
