@@ -49,6 +49,13 @@ extern "C" {
 #define CAVDFTB_ST_NOT_PD 2        /* overlap matrix not positive definite */
 #define CAVDFTB_ST_DEGENERATE 4    /* HOMO-LUMO gap below 1e-6 hartree */
 #define CAVDFTB_ST_NAN 8           /* non-finite position or charge */
+/* A unit with CAVDFTB_ST_NOT_PD or CAVDFTB_ST_NAN has no valid density: it reports
+ * zero charges, dipole, energy and forces, so it drops out of the cavity sums
+ * and the energy totals instead of turning them non-finite for every unit.
+ * In MD steps (cavdftb_step, cavdftb_init_photons) a unit with any status bit
+ * is left out of the cavity coupling for that evaluation: its e . mu enters the
+ * mode sums F_m as zero and its atoms feel no cavity force, so one failing
+ * unit cannot drive the field that every other unit feels. */
 
 /* Born-charge modes */
 #define CAVDFTB_BORN_MULLIKEN 0  /* Z_A = Q_A I (the paper's cheap replacement, Results) */
@@ -175,6 +182,26 @@ int cavdftb_eval_units(cavdftb_ctx* ctx, const double* pos, double* energy, doub
  * the surrogate mode before cavdftb_set_surrogate. */
 int cavdftb_born_charges(cavdftb_ctx* ctx, const double* pos, int32_t mode, double h, double* born,
                          double* ens_std, int32_t* unit_status);
+
+/* Copy of a context work array, as left by the last evaluation or MD step on the
+ * context stream (device to device, asynchronous on that stream):
+ *   CAVDFTB_WORK_MU_POL   [n_units]      e . mu_n, the projected unit dipoles
+ *   CAVDFTB_WORK_DIPOLE   [n_units][3]   mu_n = sum_A Q_A R_A
+ *   CAVDFTB_WORK_ENERGY   [n_units]      matter energies V_n
+ *   CAVDFTB_WORK_CHARGES  [n_atoms]      Mulliken charges Q_A = -dq_A
+ *   CAVDFTB_WORK_FORCES   [n_atoms][3]   matter forces -dV/dR
+ *   CAVDFTB_WORK_FIELD    [n_units]      cavity field E_n felt by each unit
+ * (Theory: mu_n and E_n of Eq. dpj.)  Recording MU_POL and the photon
+ * coordinates after every step gives the dipole and photon autocorrelations
+ * behind the IR and polariton spectra (Results).  dst must hold the listed
+ * number of doubles.  Returns CAVDFTB_EINVAL for an unknown array. */
+#define CAVDFTB_WORK_MU_POL 0
+#define CAVDFTB_WORK_DIPOLE 1
+#define CAVDFTB_WORK_ENERGY 2
+#define CAVDFTB_WORK_CHARGES 3
+#define CAVDFTB_WORK_FORCES 4
+#define CAVDFTB_WORK_FIELD 5
+int cavdftb_read_work(cavdftb_ctx* ctx, int32_t which, double* dst);
 
 /* Cavity coupling for given projected dipoles mu_pol[n_units] = e . mu_n and
  * photon coordinates q[n_modes] (all device):

@@ -18,6 +18,7 @@ ST_NOT_CONVERGED, ST_NOT_PD, ST_DEGENERATE, ST_NAN = 1, 2, 4, 8
 BORN_MULLIKEN, BORN_FD, BORN_SURROGATE, BORN_FIELD = 0, 1, 2, 3
 SG_N_IN, SG_N_HID, SG_N_OUT, SG_MEMBERS, SG_N_PARAM, SG_N_NORM = 32, 128, 9, 4, 21897, 82
 N_OBS = 8
+WORK_MU_POL, WORK_DIPOLE, WORK_ENERGY, WORK_CHARGES, WORK_FORCES, WORK_FIELD = range(6)
 OBS_NAMES = ("kinetic", "potential", "photon", "total", "temperature", "n_bad_units", "scc_iterations",
              "sum_mu_pol")
 
@@ -59,6 +60,7 @@ SYMBOLS = {
     "cavdftb_set_fallback": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "cavdftb_set_schedule": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32]),
     "cavdftb_set_graph": (ctypes.c_int, [_vp, ctypes.c_int32]),
+    "cavdftb_read_work": (ctypes.c_int, [_vp, ctypes.c_int32, _vp]),
     "cavdftb_sg_features": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "cavdftb_sg_prep": (ctypes.c_int, [_vp, _vp, _c_i32, _c_i32, _vp, _vp, _vp]),
     "cavdftb_sg_forward": (ctypes.c_int, [_vp, _vp, _c_i32, _vp, _vp, _vp]),
@@ -193,6 +195,15 @@ class Context:
 
     def set_schedule(self, job_queue=True, max_wg_per_cu=0):
         self._check(self.lib.cavdftb_set_schedule(self.ctx, int(bool(job_queue)), int(max_wg_per_cu)), "set_schedule")
+
+    def read_work(self, which, dst):
+        """Device copy of a work array (WORK_MU_POL ... WORK_FIELD) into dst."""
+        sizes = {WORK_MU_POL: self.n_units, WORK_DIPOLE: 3 * self.n_units, WORK_ENERGY: self.n_units,
+                 WORK_CHARGES: self.n_atoms, WORK_FORCES: 3 * self.n_atoms, WORK_FIELD: self.n_units}
+        if which not in sizes:
+            raise CavdftbError(f"read_work: unknown array {which}")
+        self._check(self.lib.cavdftb_read_work(self.ctx, int(which), _ptr(dst, self.torch.float64, sizes[which], "dst")),
+                    "read_work")
 
     def set_graph(self, enable=True):
         self._check(self.lib.cavdftb_set_graph(self.ctx, int(bool(enable))), "set_graph")

@@ -430,7 +430,7 @@ int matter_stage(cavdftb_ctx* c, const double* r, int born_mode, double h) {
     e = launch_zpol_mulliken(c->d_charges, c->pol, c->NA, c->d_zpol, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "zpol");
   }
-  e = launch_mu_pol(c->d_dipole, c->pol, c->U, c->d_mu_pol, c->stream);
+  e = launch_mu_pol(c->d_dipole, c->pol, c->U, c->d_status, c->d_mu_pol, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "mu_pol");
   return CAVDFTB_OK;
 }
@@ -443,14 +443,16 @@ int issue_step(cavdftb_ctx* c, double* r, double* p, double* qm, double* pm, dou
   CavArgs ca = cav_args(c);
   hipError_t e = launch_photon_kick(c->M, c->d_omega, c->d_lam, c->d_F, dt, pm, 0, qm, s);
   if (e == hipSuccess)
-    e = launch_kick_drift(c->NA, c->d_atom_unit, c->d_inv_mass, c->d_forces, c->d_zpol, c->d_field, dt, r, p, 1, s);
+    e = launch_kick_drift(c->NA, c->d_atom_unit, c->d_inv_mass, c->d_forces, c->d_zpol, c->d_field, dt, r, p, 1,
+                          c->d_status, s);
   if (e != hipSuccess) return hip_fail(c, e, "step kick/drift");
   int rc = matter_stage(c, r, born_mode, h_fd);
   if (rc) return rc;
   e = launch_cav_scatter(ca, c->d_mu_pol, c->d_F, nullptr, s);
   if (e == hipSuccess) e = launch_cav_gather(ca, qm, c->d_F, c->d_field, s);  // old q
   if (e == hipSuccess)
-    e = launch_kick_drift(c->NA, c->d_atom_unit, c->d_inv_mass, c->d_forces, c->d_zpol, c->d_field, dt, r, p, 0, s);
+    e = launch_kick_drift(c->NA, c->d_atom_unit, c->d_inv_mass, c->d_forces, c->d_zpol, c->d_field, dt, r, p, 0,
+                          c->d_status, s);
   if (e == hipSuccess) e = launch_photon_kick(c->M, c->d_omega, c->d_lam, c->d_F, dt, pm, 1, qm, s);
   if (e == hipSuccess) e = launch_cav_gather(ca, qm, c->d_F, c->d_field, s);  // rotated q
   if (e == hipSuccess && obs)
@@ -887,6 +889,24 @@ int cavdftb_born_charges(cavdftb_ctx* ctx, const double* pos, int32_t mode, doub
   return CAVDFTB_OK;
 }
 
+int cavdftb_read_work(cavdftb_ctx* ctx, int32_t which, double* dst) {
+  if (!ctx) return CAVDFTB_EINVAL;
+  if (!dst) return fail(ctx, CAVDFTB_EINVAL, "read_work: null destination");
+  const double* src = nullptr;
+  size_t count = 0;
+  switch (which) {
+    case CAVDFTB_WORK_MU_POL: src = ctx->d_mu_pol; count = ctx->U; break;
+    case CAVDFTB_WORK_DIPOLE: src = ctx->d_dipole; count = 3 * (size_t)ctx->U; break;
+    case CAVDFTB_WORK_ENERGY: src = ctx->d_energy; count = ctx->U; break;
+    case CAVDFTB_WORK_CHARGES: src = ctx->d_charges; count = ctx->NA; break;
+    case CAVDFTB_WORK_FORCES: src = ctx->d_forces; count = 3 * (size_t)ctx->NA; break;
+    case CAVDFTB_WORK_FIELD: src = ctx->d_field; count = ctx->U; break;
+    default: return fail(ctx, CAVDFTB_EINVAL, "read_work: unknown array");
+  }
+  const hipError_t e = hipMemcpyAsync(dst, src, count * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream);
+  return e == hipSuccess ? CAVDFTB_OK : hip_fail(ctx, e, "read_work copy");
+}
+
 int cavdftb_cavity_forces(cavdftb_ctx* ctx, const double* mu_pol, const double* q, double* F, double* field,
                           double* fq) {
   if (!ctx) return CAVDFTB_EINVAL;
@@ -999,7 +1019,7 @@ int cavdftb_init_photons(cavdftb_ctx* ctx, const double* r, double* qm, double* 
   if (rc) return rc;
   ctx->primed = false;
   CavArgs ca = cav_args(ctx);
-  hipError_t e = launch_mu_pol(ctx->d_dipole, ctx->pol, ctx->U, ctx->d_mu_pol, ctx->stream);
+  hipError_t e = launch_mu_pol(ctx->d_dipole, ctx->pol, ctx->U, ctx->d_status, ctx->d_mu_pol, ctx->stream);
   if (e == hipSuccess) e = launch_cav_scatter(ca, ctx->d_mu_pol, ctx->d_F, nullptr, ctx->stream);
   if (e == hipSuccess) e = launch_init_photons(ca, ctx->d_F, qm, pm, ctx->stream);
   if (e != hipSuccess) return hip_fail(ctx, e, "init_photons");

@@ -91,7 +91,9 @@ struct CavArgs {
   double pol[3];
 };
 
-hipError_t launch_mu_pol(const double* dipole, const double pol[3], int n_units, double* mu_pol, hipStream_t s);
+// e . mu_n, zero for units with a status bit (status may be null: no masking)
+hipError_t launch_mu_pol(const double* dipole, const double pol[3], int n_units, const int32_t* status,
+                         double* mu_pol, hipStream_t s);
 hipError_t launch_cav_scatter(const CavArgs& c, const double* mu_pol, double* F, double* fq, hipStream_t s);
 hipError_t launch_cav_gather(const CavArgs& c, const double* q, const double* F, double* field, hipStream_t s);
 hipError_t launch_init_photons(const CavArgs& c, const double* F, double* qm, double* pm, hipStream_t s);
@@ -108,7 +110,7 @@ hipError_t launch_born_fd_assemble(const int32_t* unit_off, const int32_t* fd_un
                                    int32_t* status, hipStream_t s);
 hipError_t launch_kick_drift(int n_atoms, const int32_t* atom_unit, const double* inv_mass, const double* forces,
                              const double* zpol, const double* field, double dt, double* r, double* p,
-                             int do_drift, hipStream_t s);
+                             int do_drift, const int32_t* status, hipStream_t s);  // no cavity force on flagged units
 hipError_t launch_photon_kick(int n_modes, const double* omega, const double* lam, const double* F, double dt,
                               double* pm, int rotate, double* qm, hipStream_t s);
 hipError_t launch_observables(int n_units, int n_atoms, int n_modes, const int32_t* unit_off,

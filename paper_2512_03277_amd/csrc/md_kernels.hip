@@ -31,10 +31,17 @@ __device__ double wg_sum(double v, double* red) {
   return r;
 }
 
+// e . mu_n; a unit whose evaluation set a status bit enters the mode sums as zero
+// (its dipole is not that of a converged density, and one runaway unit must not
+// drive every F_m)
 __global__ __launch_bounds__(kNT) void mu_pol_kernel(const double* __restrict__ dip, double e0, double e1, double e2,
-                                                     int n, double* __restrict__ out) {
+                                                     int n, const int32_t* __restrict__ status,
+                                                     double* __restrict__ out) {
   const int i = blockIdx.x * kNT + threadIdx.x;
-  if (i < n) out[i] = e0 * dip[i * 3] + e1 * dip[i * 3 + 1] + e2 * dip[i * 3 + 2];
+  if (i < n) {
+    const double v = e0 * dip[i * 3] + e1 * dip[i * 3 + 1] + e2 * dip[i * 3 + 2];
+    out[i] = (!status || status[i] == 0) && isfinite(v) ? v : 0.0;
+  }
 }
 
 // one workgroup per mode: F_m = sum_n phi_m(X_n) mu_n ; fq_m = -lambda omega F_m
@@ -187,10 +194,11 @@ __global__ __launch_bounds__(kNT) void kick_drift_kernel(int n, const int32_t* _
                                                          const double* __restrict__ zp,
                                                          const double* __restrict__ field, double dt,
                                                          double* __restrict__ r, double* __restrict__ p,
-                                                         int drift) {
+                                                         int drift, const int32_t* __restrict__ status) {
   const int i = blockIdx.x * kNT + threadIdx.x;
   if (i >= n) return;
-  const double e = field[atom_unit[i]];
+  const int u = atom_unit[i];
+  const double e = status && status[u] != 0 ? 0.0 : field[u];  // flagged units feel no cavity force
   for (int g = 0; g < 3; ++g) {
     const double pn = p[i * 3 + g] + 0.5 * dt * (f[i * 3 + g] - e * zp[i * 3 + g]);
     p[i * 3 + g] = pn;
@@ -289,10 +297,11 @@ inline int nblk(int n) { return (n + kNT - 1) / kNT; }
 
 }  // namespace
 
-hipError_t launch_mu_pol(const double* dipole, const double pol[3], int n_units, double* mu_pol, hipStream_t s) {
+hipError_t launch_mu_pol(const double* dipole, const double pol[3], int n_units, const int32_t* status,
+                         double* mu_pol, hipStream_t s) {
   if (n_units <= 0) return hipSuccess;
   hipLaunchKernelGGL(mu_pol_kernel, dim3(nblk(n_units)), dim3(kNT), 0, s, dipole, pol[0], pol[1], pol[2], n_units,
-                     mu_pol);
+                     status, mu_pol);
   return hipGetLastError();
 }
 
@@ -354,9 +363,9 @@ hipError_t launch_born_field_assemble(int n_atoms, const int32_t* atom_unit, con
 
 hipError_t launch_kick_drift(int n_atoms, const int32_t* atom_unit, const double* inv_mass, const double* forces,
                              const double* zpol, const double* field, double dt, double* r, double* p,
-                             int do_drift, hipStream_t s) {
+                             int do_drift, const int32_t* status, hipStream_t s) {
   hipLaunchKernelGGL(kick_drift_kernel, dim3(nblk(n_atoms)), dim3(kNT), 0, s, n_atoms, atom_unit, inv_mass, forces,
-                     zpol, field, dt, r, p, do_drift);
+                     zpol, field, dt, r, p, do_drift, status);
   return hipGetLastError();
 }
 

@@ -1326,10 +1326,12 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
       for (int t = tid; t < na; t += NT) sDqOut[t] = 0.0;
     }
     __syncthreads();
-    // dipole mu = sum_A Q_A R_A with Q = -Dq
+    // dipole mu = sum_A Q_A R_A with Q = -Dq; zero for a unit without a valid
+    // density (its positions may be non-finite), so it drops out of the cavity sums
+    const bool dead = (status & (CAVDFTB_ST_NOT_PD | CAVDFTB_ST_NAN)) != 0;
     if (tid < 3) {
       double m = 0.0;
-      for (int t = 0; t < na; ++t) m -= sDqOut[t] * sPos[t * 3 + tid];
+      for (int t = 0; !dead && t < na; ++t) m -= sDqOut[t] * sPos[t * 3 + tid];
       if (disp != -1) {
         if (a.mu_job) a.mu_job[(int64_t)job * 3 + tid] = m;
       } else if (a.dipole) {
@@ -1400,7 +1402,7 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
           if (fo) fo[(int64_t)(a0 + t) * 3 + g] = f;
         }
       }
-      if (tid == 0 && a.energy && disp == -1) a.energy[u] = etot;
+      if (tid == 0 && a.energy && disp == -1) a.energy[u] = dead ? 0.0 : etot;
     }
     if (tid == 0) {
       if (disp == -1 && a.status) a.status[u] = status;

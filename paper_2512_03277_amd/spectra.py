@@ -1,0 +1,89 @@
+"""Vibrational and polariton spectra from recorded MD trajectories.
+
+Host-side post-processing of series sampled once per MD step (the device path
+records them; nothing here runs on the GPU).  The spectrum is the dipole
+(or photon-coordinate) autocorrelation transformed with an omega^2 prefactor
+(Results: I(omega) proportional to omega^2 times the windowed cosine transform
+of C(t), C the time-origin averaged autocorrelation).  The paper's smoothing is
+a weighted moving average; the reading taken here is a Hann window over lags up
+to half the run, zero padding by 8 and the peak located by a parabola through
+the largest sample and its two neighbours.  The same processing is applied to
+every path that is compared, so its small bias cancels in peak shifts.
+"""
+import numpy as np
+
+HARTREE_CM = 219474.6313632  # 1 hartree in cm^-1 (angular frequency in a.u. -> wavenumber)
+
+
+def autocorrelation(x, max_lag=None):
+    """C(t) = < dx(t0 + t) dx(t0) >, averaged over time origins t0 and over the
+    series, for x of shape [T] or [T, K] (T samples of K series) with each series'
+    time mean removed (dx = x - <x>).  Lags 0..max_lag (default T // 2); the
+    average over origins divides by the T - t pairs of each lag."""
+    x = np.asarray(x, dtype=np.float64)
+    if x.ndim == 1:
+        x = x[:, None]
+    T = x.shape[0]
+    L = T // 2 if max_lag is None else int(max_lag)
+    if not 0 < L < T:
+        raise ValueError("need 0 < max_lag < number of samples")
+    dx = x - x.mean(axis=0)
+    nfft = 1 << int(np.ceil(np.log2(2 * T)))  # zero padding: linear, not circular, correlation
+    f = np.fft.rfft(dx, n=nfft, axis=0)
+    s = np.fft.irfft(f * np.conj(f), n=nfft, axis=0)[: L + 1]
+    s /= (T - np.arange(L + 1))[:, None]
+    return s.mean(axis=1)
+
+
+def spectrum(C, dt, pad=8, omega_squared=True):
+    """I(omega) = omega^2 [w_0 C_0 + 2 sum_{t=1..L} w_t C_t cos(omega t dt)] with the
+    half Hann window w_t = (1 + cos(pi t / L)) / 2 over the L + 1 lags of C, on a
+    grid refined by zero padding the even extension to pad * 2L points.
+    Returns (wavenumbers in cm^-1, I); dt is the sampling interval in atomic
+    units of time (omega in hartree)."""
+    C = np.asarray(C, dtype=np.float64)
+    L = len(C) - 1
+    if L < 2:
+        raise ValueError("need at least three lags")
+    w = 0.5 * (1.0 + np.cos(np.pi * np.arange(L + 1) / L))
+    n = pad * 2 * L
+    y = np.zeros(n)
+    y[: L + 1] = w * C
+    y[n - L:] = (w * C)[1:][::-1]
+    S = np.fft.rfft(y).real  # w_0 C_0 + 2 sum_t w_t C_t cos(2 pi k t / n)
+    omega = 2.0 * np.pi * np.arange(len(S)) / (n * dt)
+    I = omega ** 2 * S if omega_squared else S
+    return omega * HARTREE_CM, I
+
+
+def peak(freq, I, lo, hi):
+    """Position of the largest value of I with lo <= freq <= hi, refined by the
+    parabola through that sample and its neighbours (the sample itself when it
+    sits on the edge of the grid)."""
+    freq = np.asarray(freq)
+    I = np.asarray(I)
+    idx = np.nonzero((freq >= lo) & (freq <= hi))[0]
+    if len(idx) == 0:
+        raise ValueError("no frequencies in the band")
+    k = idx[np.argmax(I[idx])]
+    if k == 0 or k == len(I) - 1:
+        return float(freq[k])
+    a, b, c = I[k - 1], I[k], I[k + 1]
+    den = a - 2.0 * b + c
+    d = 0.5 * (a - c) / den if den != 0.0 else 0.0
+    return float(freq[k] + d * (freq[k + 1] - freq[k]))
+
+
+def resolution_cm(n_samples, dt):
+    """Frequency resolution 2 pi / (T dt) of a run of n_samples steps, in cm^-1."""
+    return 2.0 * np.pi / (n_samples * dt) * HARTREE_CM
+
+
+def peak_report(series_a, series_b, dt, lo, hi):
+    """Spectra of two runs recorded from the same start (series [T, K]) and the
+    shift of their largest peak in [lo, hi] cm^-1."""
+    fa, Ia = spectrum(autocorrelation(series_a), dt)
+    fb, Ib = spectrum(autocorrelation(series_b), dt)
+    pa, pb = peak(fa, Ia, lo, hi), peak(fb, Ib, lo, hi)
+    return {"peak_a_cm": pa, "peak_b_cm": pb, "shift_cm": pa - pb,
+            "resolution_cm": resolution_cm(len(series_a), dt)}

@@ -377,6 +377,41 @@ def test_status_flags(params):
     pos[4, 1] = np.nan
     g = gpu_eval(ctx, pos)
     assert g["status"][1] & 8 and np.all(g["status"][[0, 2, 3, 4, 5, 6, 7]] == 0)
+    # no valid density: zero charges, dipole, energy and forces for that unit only
+    assert np.all(g["dipole"][1] == 0.0) and g["energy"][1] == 0.0
+    assert np.all(g["charges"][3:6] == 0.0) and np.all(g["forces"][3:6] == 0.0)
+    ok = np.r_[0:3, 6:len(pos)]
+    assert np.all(np.isfinite(g["forces"][ok])) and np.all(np.isfinite(g["dipole"][[0, 2, 3, 4, 5, 6, 7]]))
+
+
+def test_failed_unit_does_not_poison_the_cavity(params):
+    # a unit with a non-finite position drops out of the mode sums: every other
+    # unit keeps finite, unchanged-in-kind dynamics and the totals stay finite
+    s = make_system(5, n_units=8)
+    masses = params["mass"][s["species"]]
+    out = {}
+    for tag in ("clean", "nan"):
+        ctx = make_ctx(params, s, tol=1e-10)
+        pos = s["pos"].copy()
+        if tag == "nan":
+            pos[s["unit_off"][2], 0] = np.nan
+        r = _t(pos)
+        p = _t(s["vel"] * masses[:, None])
+        qm = torch.zeros(ctx.n_modes, dtype=torch.float64, device=DEV)
+        pm = torch.zeros_like(qm)
+        obs = torch.zeros(3, cd.N_OBS, dtype=torch.float64, device=DEV)
+        ctx.init_photons(r, qm, pm)
+        ctx.step(r, p, qm, pm, 3, s["dt"], cd.BORN_MULLIKEN, 0.0, obs)
+        ctx.sync()
+        out[tag] = (r.cpu().numpy(), qm.cpu().numpy(), obs.cpu().numpy())
+        ctx.close()
+    a0, a1 = s["unit_off"][2], s["unit_off"][3]
+    keep = np.r_[0:a0, a1:len(s["pos"])]
+    r_nan, q_nan, o_nan = out["nan"]
+    assert np.all(np.isfinite(r_nan[keep])) and np.all(np.isfinite(q_nan)) and np.all(np.isfinite(o_nan))
+    assert np.all(o_nan[:, 5] == 1)  # exactly the one unit is flagged
+    # the other units feel only the missing unit's (tiny) cavity contribution
+    assert np.max(np.abs(r_nan[keep] - out["clean"][0][keep])) < 1e-6
 
 
 def test_autotune_picks_a_candidate_and_keeps_results(params):
@@ -392,3 +427,40 @@ def test_autotune_picks_a_candidate_and_keeps_results(params):
     r = eval_units(params, s["species"], s["pos"], s["unit_off"], tol=1e-12)
     assert_parity(g, r, pos=s["pos"], unit_off=s["unit_off"])
     assert np.max(np.abs(g["charges"] - ref["charges"])) <= 1e-10
+
+
+def test_read_work_arrays_match_the_evaluation(params):
+    # the context's work arrays after init_photons / a step are those of an
+    # evaluation at the same positions; the field is the cavity gather's
+    s = make_system(5, n_units=8)
+    ctx = make_ctx(params, s, tol=1e-12)
+    masses = params["mass"][s["species"]]
+    r = _t(s["pos"])
+    p = _t(s["vel"] * masses[:, None])
+    qm = torch.zeros(ctx.n_modes, dtype=torch.float64, device=DEV)
+    pm = torch.zeros_like(qm)
+    ctx.init_photons(r, qm, pm)
+    ctx.step(r, p, qm, pm, 2, s["dt"], cd.BORN_MULLIKEN, 0.0, None)
+    U, NA = ctx.n_units, ctx.n_atoms
+    w = {k: torch.zeros(n, dtype=torch.float64, device=DEV) for k, n in
+         (("mu_pol", U), ("dipole", 3 * U), ("energy", U), ("charges", NA), ("forces", 3 * NA), ("field", U))}
+    for k, which in (("mu_pol", cd.WORK_MU_POL), ("dipole", cd.WORK_DIPOLE), ("energy", cd.WORK_ENERGY),
+                     ("charges", cd.WORK_CHARGES), ("forces", cd.WORK_FORCES), ("field", cd.WORK_FIELD)):
+        ctx.read_work(which, w[k])
+    ctx.sync()
+    ref = make_ctx(params, s, tol=1e-12)
+    g = gpu_eval(ref, r.cpu().numpy())
+    wk = {k: v.cpu().numpy() for k, v in w.items()}
+    assert np.max(np.abs(wk["energy"] - g["energy"])) <= 1e-10 * np.max(np.abs(g["energy"]))
+    assert np.max(np.abs(wk["forces"].reshape(-1, 3) - g["forces"])) <= 1e-8 * np.max(np.abs(g["forces"]))
+    assert np.max(np.abs(wk["charges"] - g["charges"])) <= 1e-10
+    assert np.max(np.abs(wk["dipole"].reshape(-1, 3) - g["dipole"])) <= 1e-8
+    assert np.allclose(wk["mu_pol"], wk["dipole"].reshape(-1, 3) @ np.asarray(s["pol"]), rtol=0, atol=1e-14)
+    field = torch.zeros(U, dtype=torch.float64, device=DEV)
+    ctx.cavity_forces(w["mu_pol"], qm, field=field)
+    ctx.sync()
+    assert torch.equal(field, w["field"])
+    with pytest.raises(RuntimeError):
+        ctx.read_work(17, w["energy"])
+    ref.close()
+    ctx.close()

@@ -1,0 +1,96 @@
+"""Pins of the spectrum post-processing (host code, no GPU): the autocorrelation
+against its definition written out, a sampled cosine against its own frequency,
+and a harmonic polariton run through the oracle integrator against the exact
+frequencies of that (linear) discrete-time map, which are where the sampled
+trajectory's spectral lines lie.
+"""
+import numpy as np
+import pytest
+
+from oracle import cavity as cav
+from oracle import md
+from oracle.harmonic import HarmonicBackend
+from paper_2512_03277_amd import spectra
+
+AMU = 1822.888486
+DT = 10.3353  # 0.25 fs
+
+
+def test_autocorrelation_is_the_origin_average():
+    rng = np.random.default_rng(1)
+    x = rng.normal(size=(37, 3))
+    L = 11
+    dx = x - x.mean(0)
+    ref = np.array([np.mean([np.mean([dx[t0 + t, k] * dx[t0, k] for t0 in range(37 - t)]) for k in range(3)])
+                    for t in range(L + 1)])
+    assert np.allclose(spectra.autocorrelation(x, L), ref, rtol=1e-13, atol=1e-15)
+
+
+def test_cosine_line_sits_at_its_frequency():
+    nu0 = 1650.0
+    w0 = nu0 / spectra.HARTREE_CM
+    t = np.arange(8000) * DT
+    x = np.cos(w0 * t + 0.3)[:, None]
+    f, I = spectra.spectrum(spectra.autocorrelation(x), DT, omega_squared=False)
+    assert spectra.peak(f, I, 1000, 3000) == pytest.approx(nu0, abs=0.05)
+    # the omega^2 prefactor moves the maximum up by about 2 sigma^2 / nu of the line
+    f, I = spectra.spectrum(spectra.autocorrelation(x), DT)
+    p = spectra.peak(f, I, 1000, 3000)
+    assert 0.0 < p - nu0 < 2.0
+
+
+def test_two_lines_are_resolved():
+    t = np.arange(8000) * DT
+    nus = (1600.0, 3700.0)
+    x = sum(np.cos(nu / spectra.HARTREE_CM * t) for nu in nus)
+    f, I = spectra.spectrum(spectra.autocorrelation(x), DT, omega_squared=False)
+    assert spectra.peak(f, I, 1000, 2500) == pytest.approx(nus[0], abs=0.1)
+    assert spectra.peak(f, I, 2500, 4500) == pytest.approx(nus[1], abs=0.1)
+    assert spectra.resolution_cm(2000, DT) == pytest.approx(66.7, abs=0.1)
+
+
+def _map_frequencies(be, cavity, dt):
+    """Angles of the eigenvalues of the one-step map over (z, p_z, q, p_q) / dt."""
+    T = np.zeros((4, 4))
+    for j in range(4):
+        v = np.zeros(4)
+        v[j] = 1.0
+        r = np.zeros((1, 3))
+        p = np.zeros((1, 3))
+        r[0, 2], p[0, 2] = v[0], v[1]
+        ev = be.evaluate(r)
+        F = cav.dipole_sums(cavity.phi, ev["mu"] @ cavity.pol)
+        st = {"r": r, "p": p, "q": v[2:3].copy(), "pm": v[3:4].copy(), "ev": ev, "F": F,
+              "E": cav.fields(cavity.phi, cavity.omega, cavity.lam, v[2:3], F),
+              "masses": be.m.copy(), "atom_unit": np.arange(1)}
+        md.step(st, be, cavity, dt)
+        T[:, j] = [st["r"][0, 2], st["p"][0, 2], st["q"][0], st["pm"][0]]
+    ang = np.sort(np.abs(np.angle(np.linalg.eigvals(T))))[::2]
+    return ang / dt * spectra.HARTREE_CM
+
+
+def test_harmonic_polariton_lines_from_an_oracle_trajectory():
+    # one oscillator at 1650 cm^-1 coupled to one resonant mode: the upper and
+    # lower polariton lines appear in both the dipole and the photon spectra
+    w = 1650.0 / spectra.HARTREE_CM
+    m = np.array([16.0 * AMU])
+    be = HarmonicBackend(m, np.array([w]), np.array([0.5]), np.zeros((1, 3)))
+    cavity = md.Cavity(np.array([w]), np.array([w / 137.036]), np.array([np.pi / 2]), np.array([0.4]),
+                       np.array([0.0]), np.array([0.0, 0.0, 1.0]))
+    lines = _map_frequencies(be, cavity, DT)
+    assert lines[1] - lines[0] > 200.0  # well above the resolution of the run below
+    r = np.zeros((1, 3))
+    r[0, 2] = 0.05
+    st = md.init_state(be, cavity, r, np.zeros((1, 3)), m, np.arange(1), photons="zero")
+    z, q = [], []
+    for _ in range(6000):
+        md.step(st, be, cavity, DT)
+        z.append(st["ev"]["mu"][0, 2])
+        q.append(st["q"][0])
+    for series in (np.array(z), np.array(q)):
+        f, I = spectra.spectrum(spectra.autocorrelation(series), DT)
+        mid = 0.5 * (lines[0] + lines[1])
+        assert spectra.peak(f, I, 500.0, mid) == pytest.approx(lines[0], abs=2.0)
+        assert spectra.peak(f, I, mid, 4000.0) == pytest.approx(lines[1], abs=2.0)
+    rep = spectra.peak_report(np.array(z)[:, None], np.array(z)[:, None], DT, 500.0, 4000.0)
+    assert rep["shift_cm"] == 0.0
