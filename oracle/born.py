@@ -11,6 +11,11 @@ obtained by finite differences of the SCC dipole).  Two forms:
 Layout: Z[A][a][b] = d mu_a / d R_{A b}.  Displaced SCCs are warm-started from
 the undisplaced charges.
 
+  Exact by forward finite differences (the paper's own scheme, Computational
+  details), against the undisplaced dipole mu(R):
+      Z_A[a][b] = (mu_a(R + h e_{A b}) - mu_a(R)) / h
+  3 N_a displaced SCCs per unit; first-order in h.
+
   Exact by the Maxwell relation (the force on an atom responds to a uniform
   field exactly as the dipole responds to that atom's displacement):
       Z_A[a][b] = d F_{A b} / d field_a
@@ -47,6 +52,24 @@ def born_field(params, species, pos, e=1.0e-4, tol=1e-12, max_iter=200, dq_cente
             worst |= r["status"]
             fs.append(r["forces"])
         Z[:, a, :] = (fs[0] - fs[1]) / (2.0 * e)
+    return Z, worst
+
+
+def born_fd_forward(params, species, pos, mu_center, h=1.0e-3, tol=1e-12, max_iter=200, dq_center=None):
+    """Forward differences against the undisplaced dipole mu_center (3,).
+    Returns (Z (Na,3,3), worst SCC status over the 3 Na displaced runs)."""
+    pos = np.asarray(pos, dtype=np.float64)
+    mu0 = np.asarray(mu_center, dtype=np.float64)
+    na = len(species)
+    Z = np.zeros((na, 3, 3))
+    worst = 0
+    for a in range(na):
+        for b in range(3):
+            x = pos.copy()
+            x[a, b] += h
+            r = scc_unit(params, species, x, tol=tol, max_iter=max_iter, dq_start=dq_center, want_forces=False)
+            worst |= r["status"]
+            Z[a, :, b] = (r["dipole"] - mu0) / h
     return Z, worst
 
 

@@ -28,21 +28,27 @@ exact-Born path (tests/test_oracle_cavity.py, tests/test_oracle_md.py).
 import numpy as np
 
 from . import cavity as cav
-from .born import born_fd, born_field, born_mulliken
+from .born import born_fd, born_fd_forward, born_field, born_mulliken
 from .scc import scc_unit
 from cavgen.constants import KB
 
 
 class DFTBBackend:
     """SCC-DFTB matter for every unit; Born charges by the Mulliken replacement
-    or by central finite differences (born="fd": of the dipole in the atom
-    displacements; born="field": of the forces in a uniform field, step h in
-    atomic units of field)."""
+    or by finite differences (born="fd": central, of the dipole in the atom
+    displacements; born="fd_forward": forward, against the undisplaced dipole;
+    born="field": central, of the forces in a uniform field, step h in atomic
+    units of field).  With born_every = k > 1 the exact Born charges are
+    recomputed on every k-th evaluation only (the first included) and reused in
+    between (the paper refreshes them every 3 steps, Computational details)."""
 
-    def __init__(self, params, species, unit_off, born="mulliken", tol=1e-12, h=1e-3, max_iter=200):
+    def __init__(self, params, species, unit_off, born="mulliken", tol=1e-12, h=1e-3, max_iter=200, born_every=1):
         self.params, self.species, self.unit_off = params, np.asarray(species), np.asarray(unit_off)
         self.born, self.tol, self.h, self.max_iter = born, tol, h, max_iter
         self.n_units = len(unit_off) - 1
+        self.born_every = int(born_every)
+        self.calls = 0
+        self.Z_last = None
 
     def evaluate(self, r):
         U = self.n_units
@@ -58,9 +64,16 @@ class DFTBBackend:
             out["forces"][a0:a1] = res["forces"]
             out["mu"][u] = res["dipole"]
             out["charges"][a0:a1] = res["charges"]
-            if self.born == "fd":
+            refresh = self.calls % self.born_every == 0
+            if self.born in ("fd", "fd_forward", "field") and not refresh:
+                Z = self.Z_last[a0:a1]
+            elif self.born == "fd":
                 Z, st = born_fd(self.params, sp, r[a0:a1], h=self.h, tol=self.tol, max_iter=self.max_iter,
                                 dq_center=res["dq"])
+                out["status"][u] |= st
+            elif self.born == "fd_forward":
+                Z, st = born_fd_forward(self.params, sp, r[a0:a1], res["dipole"], h=self.h, tol=self.tol,
+                                        max_iter=self.max_iter, dq_center=res["dq"])
                 out["status"][u] |= st
             elif self.born == "field":
                 Z, st = born_field(self.params, sp, r[a0:a1], e=self.h, tol=self.tol, max_iter=self.max_iter,
@@ -69,6 +82,9 @@ class DFTBBackend:
             else:
                 Z = born_mulliken(res["charges"])
             out["Z"][a0:a1] = Z
+        if self.born in ("fd", "fd_forward", "field") and self.calls % self.born_every == 0:
+            self.Z_last = out["Z"].copy()
+        self.calls += 1
         return out
 
 

@@ -201,3 +201,34 @@ def test_exact_born_nve_energy_bounded_and_shrinks_with_dt(params):
         ke = md.observables(st, cavity)["kinetic"]
         assert np.max(np.abs(devs)) < 1e-2 * max(ke, 1e-3)
     assert maxdev[0] / maxdev[1] > 1.6      # first-order splitting: error at least halves
+
+
+def test_forward_fd_born_is_first_order(params, monomer_born):
+    # against the independent field route, the forward-difference error halves with h
+    from oracle.born import born_fd_forward
+    pos, c, Z, st = monomer_born
+    sp = np.array([0, 1, 1])
+    Zf, _ = born_field(params, sp, pos, e=1e-4, tol=1e-13, dq_center=c["dq"])
+    errs = []
+    for h in (4e-3, 2e-3, 1e-3):
+        Zw, stw = born_fd_forward(params, sp, pos, c["dipole"], h=h, tol=1e-13, dq_center=c["dq"])
+        assert stw == 0
+        errs.append(np.max(np.abs(Zw - Zf)))
+    assert 1.7 < errs[0] / errs[1] < 2.3 and 1.7 < errs[1] / errs[2] < 2.3
+    # forward and backward (h -> -h) differences average to the central one
+    Zp, _ = born_fd_forward(params, sp, pos, c["dipole"], h=1e-3, tol=1e-13, dq_center=c["dq"])
+    Zm, _ = born_fd_forward(params, sp, pos, c["dipole"], h=-1e-3, tol=1e-13, dq_center=c["dq"])
+    assert np.max(np.abs(0.5 * (Zp + Zm) - Z)) < 1e-8
+
+
+def test_born_refresh_interval_reuses_the_tensors(params):
+    s = make_system(1, n_units=2)
+    be = md.DFTBBackend(params, s["species"], s["unit_off"], born="fd_forward", born_every=3)
+    r = s["pos"].copy()
+    Zs = []
+    for k in range(4):
+        Zs.append(be.evaluate(r + 0.01 * k)["Z"])
+    assert np.array_equal(Zs[1], Zs[0]) and np.array_equal(Zs[2], Zs[0])
+    assert not np.array_equal(Zs[3], Zs[0])
+    ref = md.DFTBBackend(params, s["species"], s["unit_off"], born="fd_forward")
+    assert np.array_equal(ref.evaluate(r + 0.03)["Z"], Zs[3])
