@@ -62,6 +62,7 @@ extern "C" {
 #define CAVDFTB_BORN_FD 1        /* central finite differences of the SCC dipole (Results) */
 #define CAVDFTB_BORN_SURROGATE 2 /* learned ensemble, exact route for units where it disagrees */
 #define CAVDFTB_BORN_FIELD 3     /* exact, from the force response to a uniform field (Maxwell relation) */
+#define CAVDFTB_BORN_FD_FORWARD 4 /* forward differences of the SCC dipole (the paper's own scheme) */
 
 /* Surrogate network: per species (O, H) and member, 32 -> 128 SiLU -> 128
  * SiLU -> 9, flat FP32 parameters [W1 (32x128, row = input) | b1 | W2 (128x128)
@@ -172,6 +173,9 @@ int cavdftb_eval_units(cavdftb_ctx* ctx, const double* pos, double* energy, doub
  * d mu_a / d R_Ab = d F_Ab / d field_a, as central differences of the SCC
  * forces in a uniform field +-h e_a (h in atomic units of field, e.g. 1e-4):
  * 6 field-perturbed SCCs per unit instead of 6 n_atoms, same warm start;
+ * CAVDFTB_BORN_FD_FORWARD: forward differences (mu_a(R + h e_Ab) - mu_a(R)) / h
+ * against the undisplaced dipole, 3 n_atoms displaced SCCs per unit, first
+ * order in h (Computational details: the paper's finite differences);
  * CAVDFTB_BORN_SURROGATE: the ensemble set by cavdftb_set_surrogate (mean of
  * the members, acoustic sum rule imposed per unit); units whose largest
  * ensemble standard deviation exceeds the threshold are recomputed by the
@@ -277,6 +281,15 @@ int cavdftb_init_photons(cavdftb_ctx* ctx, const double* r, double* qm, double* 
 #define CAVDFTB_N_OBS 8
 int cavdftb_step(cavdftb_ctx* ctx, double* r, double* p, double* qm, double* pm, int32_t n_steps, double dt,
                  int32_t born_mode, double h_fd, double* obs);
+
+/* Refresh interval of the exact Born charges in MD steps (CAVDFTB_BORN_FD,
+ * CAVDFTB_BORN_FD_FORWARD, CAVDFTB_BORN_FIELD): with every = k > 1, cavdftb_step
+ * recomputes them at the first matter evaluation after priming and then on
+ * every k-th one, and reuses the last e . Z in between (the paper refreshes its
+ * Born charges every 3 steps, Computational details).  Other modes and
+ * cavdftb_born_charges are not affected.  Steps with k > 1 and an exact mode run
+ * eagerly (no graph replay).  Returns CAVDFTB_EINVAL for every < 1. */
+int cavdftb_set_born_interval(cavdftb_ctx* ctx, int32_t every);
 
 /* MD steps as replays of one captured hipGraph (the launch sequence of one step
  * of cavdftb_step, on the context stream).  With enable != 0, cavdftb_step

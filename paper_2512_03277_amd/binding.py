@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libcavdftb.so")
 
 OK, EINVAL, ENOMEM, EHIP = 0, -1, -2, -3
 ST_NOT_CONVERGED, ST_NOT_PD, ST_DEGENERATE, ST_NAN = 1, 2, 4, 8
-BORN_MULLIKEN, BORN_FD, BORN_SURROGATE, BORN_FIELD = 0, 1, 2, 3
+BORN_MULLIKEN, BORN_FD, BORN_SURROGATE, BORN_FIELD, BORN_FD_FORWARD = 0, 1, 2, 3, 4
 SG_N_IN, SG_N_HID, SG_N_OUT, SG_MEMBERS, SG_N_PARAM, SG_N_NORM = 32, 128, 9, 4, 21897, 82
 N_OBS = 8
 WORK_MU_POL, WORK_DIPOLE, WORK_ENERGY, WORK_CHARGES, WORK_FORCES, WORK_FIELD = range(6)
@@ -60,6 +60,7 @@ SYMBOLS = {
     "cavdftb_set_fallback": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "cavdftb_set_schedule": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32]),
     "cavdftb_set_graph": (ctypes.c_int, [_vp, ctypes.c_int32]),
+    "cavdftb_set_born_interval": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "cavdftb_read_work": (ctypes.c_int, [_vp, ctypes.c_int32, _vp]),
     "cavdftb_sg_features": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "cavdftb_sg_prep": (ctypes.c_int, [_vp, _vp, _c_i32, _c_i32, _vp, _vp, _vp]),
@@ -204,6 +205,9 @@ class Context:
             raise CavdftbError(f"read_work: unknown array {which}")
         self._check(self.lib.cavdftb_read_work(self.ctx, int(which), _ptr(dst, self.torch.float64, sizes[which], "dst")),
                     "read_work")
+
+    def set_born_interval(self, every):
+        self._check(self.lib.cavdftb_set_born_interval(self.ctx, int(every)), "set_born_interval")
 
     def set_graph(self, enable=True):
         self._check(self.lib.cavdftb_set_graph(self.ctx, int(bool(enable))), "set_graph")

@@ -53,6 +53,11 @@ struct Bucket {
   int32_t* d_fd_job_disp = nullptr;
   int32_t* d_fd_unit = nullptr;  // [n_units] unit of each fd block
   int32_t* d_fd_job0 = nullptr;  // [n_units] first fd job (relative to this bucket's mu_job base)
+  // forward differences: 3 jobs per atom (+h only), in the same job slots
+  int n_fw_jobs = 0;
+  int32_t* d_fw_job_unit = nullptr;
+  int32_t* d_fw_job_disp = nullptr;
+  int32_t* d_fw_job0 = nullptr;
   // field jobs of the Maxwell-relation Born charges: six per unit, -2 - (dir*2 + sign)
   int32_t* d_ff_job_unit = nullptr;
   int32_t* d_ff_job_disp = nullptr;
@@ -127,6 +132,8 @@ struct cavdftb_ctx {
   int warm_enabled = 1;
   bool warm_valid = false;
   bool primed = false;
+  int born_every = 1;   // MD: exact Born charges on every born_every-th matter evaluation
+  int64_t born_count = 0;
   // MD steps as replays of one captured hipGraph
   bool use_graph = false;
   uint64_t gen = 1;                // bumped by every call that changes what a step launches
@@ -358,14 +365,44 @@ int eval_field(cavdftb_ctx* c, const double* pos, double e_field, double* born, 
   return CAVDFTB_OK;
 }
 
-// exact Born charges by the route of mode (displacements or field)
+// forward-difference displaced SCCs (3 per atom) against the undisplaced
+// dipoles of eval_center, which must run first
+int eval_fd_forward(cavdftb_ctx* c, const double* pos, double h, double* born) {
+  for (const Bucket& b : c->buckets) {
+    SccArgs a = base_args(c, pos);
+    a.job_unit = b.d_fw_job_unit;
+    a.job_disp = b.d_fw_job_disp;
+    a.n_jobs = b.n_fw_jobs;
+    a.fd_h = h;
+    a.mu_job = c->d_mu_job + (int64_t)b.fjob0 * 3;
+    a.job_status = c->d_fjob_status + b.fjob0;
+    a.job_iters = c->d_fjob_iters + b.fjob0;
+    a.flags = JF_WARM_C | JF_WARM_DQ | (c->keep_hist ? JF_WARM_HIST : 0);
+    int rc = run_scc(c, b, a);
+    if (rc) return rc;
+    hipError_t e = launch_born_fd_forward_assemble(c->d_unit_off, b.d_fd_unit, b.d_fw_job0, b.n_units,
+                                                   c->d_mu_job + (int64_t)b.fjob0 * 3, c->d_dipole, h, c->pol,
+                                                   c->d_fjob_status + b.fjob0, born, c->d_zpol, c->d_status,
+                                                   c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "born fd forward assemble");
+  }
+  return CAVDFTB_OK;
+}
+
+// exact Born charges by the route of mode (displacements, central or forward, or field)
 int eval_exact(cavdftb_ctx* c, int mode, const double* pos, double h, double* born, const int32_t* unit_flag = nullptr) {
-  return mode == CAVDFTB_BORN_FIELD ? eval_field(c, pos, h, born, unit_flag) : eval_fd(c, pos, h, born, unit_flag);
+  if (mode == CAVDFTB_BORN_FIELD) return eval_field(c, pos, h, born, unit_flag);
+  if (mode == CAVDFTB_BORN_FD_FORWARD) return eval_fd_forward(c, pos, h, born);
+  return eval_fd(c, pos, h, born, unit_flag);
+}
+
+bool exact_mode(int mode) {
+  return mode == CAVDFTB_BORN_FD || mode == CAVDFTB_BORN_FD_FORWARD || mode == CAVDFTB_BORN_FIELD;
 }
 
 bool born_mode_ok(int mode) {
   return mode == CAVDFTB_BORN_MULLIKEN || mode == CAVDFTB_BORN_FD || mode == CAVDFTB_BORN_SURROGATE ||
-         mode == CAVDFTB_BORN_FIELD;
+         mode == CAVDFTB_BORN_FIELD || mode == CAVDFTB_BORN_FD_FORWARD;
 }
 
 // surrogate Born charges at pos into born (ensemble mean, acoustic sum imposed),
@@ -417,9 +454,14 @@ int matter_stage(cavdftb_ctx* c, const double* r, int born_mode, double h) {
   int rc = eval_center(c, r, true, true);
   if (rc) return rc;
   hipError_t e;
-  if (born_mode == CAVDFTB_BORN_FD || born_mode == CAVDFTB_BORN_FIELD) {
-    rc = eval_exact(c, born_mode, r, h, nullptr);
-    if (rc) return rc;
+  if (exact_mode(born_mode)) {
+    // refreshed on every born_every-th evaluation since priming; e.Z kept in between
+    const bool refresh = c->born_count % c->born_every == 0;
+    c->born_count += 1;
+    if (refresh) {
+      rc = eval_exact(c, born_mode, r, h, nullptr);
+      if (rc) return rc;
+    }
   } else if (born_mode == CAVDFTB_BORN_SURROGATE) {
     rc = sg_infer(c, r, c->d_born);
     if (rc == CAVDFTB_OK) rc = eval_exact(c, c->fallback_mode, r, h, c->d_born, c->d_unit_flag);
@@ -742,6 +784,25 @@ int cavdftb_create(const cavdftb_params* params, const cavdftb_layout* L, void* 
     CK(hipMemcpy(b.d_fd_unit, fdu.data(), fdu.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     CK(hipMemcpy(b.d_fd_job0, fdj0.data(), fdj0.size() * sizeof(int32_t), hipMemcpyHostToDevice));
     {
+      std::vector<int32_t> wu, wd, w0;
+      for (int u : bunits[k]) {
+        const int na = c->h_unit_off[u + 1] - c->h_unit_off[u];
+        w0.push_back((int32_t)wu.size());
+        for (int a = 0; a < na; ++a)
+          for (int dir = 0; dir < 3; ++dir) {
+            wu.push_back(u);
+            wd.push_back((a * 3 + dir) * 2);  // + h
+          }
+      }
+      b.n_fw_jobs = (int)wu.size();
+      CK(dalloc(c, &b.d_fw_job_unit, b.n_fw_jobs));
+      CK(dalloc(c, &b.d_fw_job_disp, b.n_fw_jobs));
+      CK(dalloc(c, &b.d_fw_job0, b.n_units));
+      CK(hipMemcpy(b.d_fw_job_unit, wu.data(), wu.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+      CK(hipMemcpy(b.d_fw_job_disp, wd.data(), wd.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+      CK(hipMemcpy(b.d_fw_job0, w0.data(), w0.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    }
+    {
       std::vector<int32_t> fu, fd;
       for (int u : bunits[k])
         for (int code = 0; code < 6; ++code) {
@@ -868,7 +929,7 @@ int cavdftb_born_charges(cavdftb_ctx* ctx, const double* pos, int32_t mode, doub
   if (mode == CAVDFTB_BORN_MULLIKEN) {
     hipError_t e = launch_born_mulliken(ctx->d_charges, ctx->NA, born, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "born mulliken");
-  } else if (mode == CAVDFTB_BORN_FD || mode == CAVDFTB_BORN_FIELD) {
+  } else if (exact_mode(mode)) {
     rc = eval_exact(ctx, mode, pos, h, born);
     if (rc) return rc;
   } else {
@@ -1047,6 +1108,7 @@ int cavdftb_step(cavdftb_ctx* ctx, double* r, double* p, double* qm, double* pm,
   hipError_t e;
   int rc;
   if (!ctx->primed) {
+    ctx->born_count = 0;
     rc = matter_stage(ctx, r, born_mode, h_fd);
     if (rc) return rc;
     e = launch_cav_scatter(ca, ctx->d_mu_pol, ctx->d_F, nullptr, s);
@@ -1059,8 +1121,9 @@ int cavdftb_step(cavdftb_ctx* ctx, double* r, double* p, double* qm, double* pm,
     if (e != hipSuccess) return hip_fail(ctx, e, "step obs row");
   }
   for (int st = 0; st < n_steps; ++st) {
-    rc = graph_steady(ctx) ? replay_step(ctx, r, p, qm, pm, dt, born_mode, h_fd, obs)
-                           : issue_step(ctx, r, p, qm, pm, dt, born_mode, h_fd, obs);
+    const bool periodic = ctx->born_every > 1 && exact_mode(born_mode);  // launches differ step to step
+    rc = graph_steady(ctx) && !periodic ? replay_step(ctx, r, p, qm, pm, dt, born_mode, h_fd, obs)
+                                        : issue_step(ctx, r, p, qm, pm, dt, born_mode, h_fd, obs);
     if (rc) return rc;
   }
   return CAVDFTB_OK;
@@ -1078,6 +1141,14 @@ int cavdftb_sync(cavdftb_ctx* ctx, int32_t* n_bad_units) {
     for (int32_t v : st) nb += v != 0;
     *n_bad_units = nb;
   }
+  return CAVDFTB_OK;
+}
+
+int cavdftb_set_born_interval(cavdftb_ctx* ctx, int32_t every) {
+  if (!ctx) return CAVDFTB_EINVAL;
+  if (every < 1) return fail(ctx, CAVDFTB_EINVAL, "set_born_interval: need every >= 1");
+  ctx->gen += 1;
+  ctx->born_every = every;
   return CAVDFTB_OK;
 }
 

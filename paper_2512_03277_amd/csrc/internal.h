@@ -108,6 +108,11 @@ hipError_t launch_born_fd_assemble(const int32_t* unit_off, const int32_t* fd_un
                                    int n_fd_units, const double* mu_job, double h, const double pol[3],
                                    const int32_t* job_status, const int32_t* unit_mask, double* born, double* zpol,
                                    int32_t* status, hipStream_t s);
+// forward differences against the undisplaced dipoles (3 jobs per atom)
+hipError_t launch_born_fd_forward_assemble(const int32_t* unit_off, const int32_t* fd_unit, const int32_t* fd_job0,
+                                           int n_fd_units, const double* mu_job, const double* dipole, double h,
+                                           const double pol[3], const int32_t* job_status, double* born,
+                                           double* zpol, int32_t* status, hipStream_t s);
 hipError_t launch_kick_drift(int n_atoms, const int32_t* atom_unit, const double* inv_mass, const double* forces,
                              const double* zpol, const double* field, double dt, double* r, double* p,
                              int do_drift, const int32_t* status, hipStream_t s);  // no cavity force on flagged units

@@ -138,6 +138,36 @@ __global__ __launch_bounds__(256) void born_fd_kernel(const int32_t* __restrict_
   }
 }
 
+// one workgroup per fd unit: Z[A][al][b] = (mu_al(+h e_Ab) - mu_al(R)) / h from the
+// unit's 3 n_a forward jobs (atom-major, then b) and its undisplaced dipole
+__global__ __launch_bounds__(256) void born_fd_forward_kernel(const int32_t* __restrict__ unit_off,
+                                                              const int32_t* __restrict__ fd_unit,
+                                                              const int32_t* __restrict__ fd_job0, int n_fd_units,
+                                                              const double* __restrict__ mu_job,
+                                                              const double* __restrict__ dipole, double h, double e0,
+                                                              double e1, double e2, double* __restrict__ born,
+                                                              double* __restrict__ zpol) {
+  const int w = blockIdx.x;
+  if (w >= n_fd_units) return;
+  const int u = fd_unit[w];
+  const int a0 = unit_off[u], na = unit_off[u + 1] - a0;
+  const int64_t j0 = fd_job0[w];
+  const double m0[3] = {dipole[u * 3], dipole[u * 3 + 1], dipole[u * 3 + 2]};
+  for (int loc = threadIdx.x; loc < na; loc += blockDim.x) {
+    double Z[3][3];
+    for (int b = 0; b < 3; ++b) {
+      const int64_t jp = j0 + (int64_t)(loc * 3 + b);
+      for (int al = 0; al < 3; ++al) Z[al][b] = (mu_job[jp * 3 + al] - m0[al]) / h;
+    }
+    const int64_t A = a0 + loc;
+    if (born)
+      for (int al = 0; al < 3; ++al)
+        for (int b = 0; b < 3; ++b) born[A * 9 + al * 3 + b] = Z[al][b];
+    if (zpol)
+      for (int b = 0; b < 3; ++b) zpol[A * 3 + b] = e0 * Z[0][b] + e1 * Z[1][b] + e2 * Z[2][b];
+  }
+}
+
 // one thread per atom: Z[A][al][b] = (F_Ab(+e e_al) - F_Ab(-e e_al)) / 2e from the
 // forces of the six field jobs of the atom's unit (Maxwell relation d mu_al / d R_Ab
 // = d F_Ab / d field_al); the unit's first atom ORs the field-job status into the
@@ -175,7 +205,7 @@ __global__ __launch_bounds__(kNT) void born_fd_status_kernel(const int32_t* __re
                                                              const int32_t* __restrict__ fd_unit,
                                                              const int32_t* __restrict__ fd_job0, int n_fd_units,
                                                              const int32_t* __restrict__ job_status,
-                                                             const int32_t* __restrict__ mask,
+                                                             const int32_t* __restrict__ mask, int per_atom,
                                                              int32_t* __restrict__ status) {
   const int w = blockIdx.x * kNT + threadIdx.x;
   if (w >= n_fd_units) return;
@@ -183,7 +213,7 @@ __global__ __launch_bounds__(kNT) void born_fd_status_kernel(const int32_t* __re
   if (mask && !mask[u]) return;
   const int na = unit_off[u + 1] - unit_off[u];
   int st = status[u];
-  for (int j = 0; j < 6 * na; ++j) st |= job_status[fd_job0[w] + j];
+  for (int j = 0; j < per_atom * na; ++j) st |= job_status[fd_job0[w] + j];
   status[u] = st;
 }
 
@@ -346,7 +376,24 @@ hipError_t launch_born_fd_assemble(const int32_t* unit_off, const int32_t* fd_un
   if (e != hipSuccess) return e;
   if (status && job_status) {
     hipLaunchKernelGGL(born_fd_status_kernel, dim3(nblk(n_fd_units)), dim3(kNT), 0, s, unit_off, fd_unit, fd_job0,
-                       n_fd_units, job_status, unit_mask, status);
+                       n_fd_units, job_status, unit_mask, 6, status);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+hipError_t launch_born_fd_forward_assemble(const int32_t* unit_off, const int32_t* fd_unit, const int32_t* fd_job0,
+                                           int n_fd_units, const double* mu_job, const double* dipole, double h,
+                                           const double pol[3], const int32_t* job_status, double* born,
+                                           double* zpol, int32_t* status, hipStream_t s) {
+  if (n_fd_units <= 0) return hipSuccess;
+  hipLaunchKernelGGL(born_fd_forward_kernel, dim3(n_fd_units), dim3(256), 0, s, unit_off, fd_unit, fd_job0,
+                     n_fd_units, mu_job, dipole, h, pol[0], pol[1], pol[2], born, zpol);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (status && job_status) {
+    hipLaunchKernelGGL(born_fd_status_kernel, dim3(nblk(n_fd_units)), dim3(kNT), 0, s, unit_off, fd_unit, fd_job0,
+                       n_fd_units, job_status, nullptr, 3, status);
     e = hipGetLastError();
   }
   return e;

@@ -12,7 +12,7 @@ from cavgen import make_params, make_system, mode_comb
 from cavgen.systems import CAVITY_LENGTH
 from oracle import cavity as ocav
 from oracle import md as omd
-from oracle.born import born_fd, born_field
+from oracle.born import born_fd, born_fd_forward, born_field
 from oracle.scc import eval_units, scc_unit
 
 pytestmark = pytest.mark.gpu
@@ -344,6 +344,54 @@ def test_md_step_exact_born_parity(params):
     st, _ = _oracle_md(params, s, "fd", 2)
     assert _rel(r, st["r"]) <= 1e-9 and _rel(p, st["p"]) <= 1e-8
     assert _rel(qm, st["q"]) <= 1e-8 and _rel(pm, st["pm"]) <= 1e-8
+
+
+def test_born_fd_forward_parity(params):
+    # the paper's forward differences against the undisplaced dipole
+    s = subsystem(make_system(5, n_units=6), [0, 1, 5])
+    ctx = make_ctx(params, s)
+    born = torch.zeros(ctx.n_atoms, 3, 3, dtype=torch.float64, device=DEV)
+    st = torch.zeros(ctx.n_units, dtype=torch.int32, device=DEV)
+    ctx.born_charges(_t(s["pos"]), cd.BORN_FD_FORWARD, 1e-3, born, st)
+    ctx.sync()
+    Z = born.cpu().numpy()
+    assert np.all(st.cpu().numpy() == 0)
+    off = s["unit_off"]
+    for u in range(ctx.n_units):
+        a0, a1 = off[u], off[u + 1]
+        c = scc_unit(params, s["species"][a0:a1], s["pos"][a0:a1], tol=1e-12)
+        Zr, _ = born_fd_forward(params, s["species"][a0:a1], s["pos"][a0:a1], c["dipole"], h=1e-3, tol=1e-12,
+                                dq_center=c["dq"])
+        # SCC tolerance 1e-12 on both dipoles, divided by h
+        assert np.max(np.abs(Z[a0:a1] - Zr)) <= 5e-8
+
+
+def test_md_steps_forward_born_refresh_every_three(params):
+    s = subsystem(make_system(1), [0, 3])
+    masses = params["mass"][s["species"]]
+    out = {}
+    for every in (3, 1):
+        ctx = make_ctx(params, s)
+        ctx.set_born_interval(every)
+        r = _t(s["pos"])
+        p = _t(s["vel"] * masses[:, None])
+        qm = torch.zeros(ctx.n_modes, dtype=torch.float64, device=DEV)
+        pm = torch.zeros_like(qm)
+        ctx.init_photons(r, qm, pm)
+        ctx.step(r, p, qm, pm, 4, s["dt"], cd.BORN_FD_FORWARD, 1e-3)
+        assert ctx.sync() == 0
+        out[every] = [x.cpu().numpy() for x in (r, p, qm, pm)]
+        ctx.close()
+    be = omd.DFTBBackend(params, s["species"], s["unit_off"], born="fd_forward", tol=1e-12, h=1e-3, born_every=3)
+    cav = omd.Cavity(s["omega"], s["k"], s["theta"], s["lam"], s["unit_x"], s["pol"])
+    atom_unit = np.repeat(np.arange(len(s["unit_off"]) - 1), np.diff(s["unit_off"]))
+    st = omd.init_state(be, cav, s["pos"], s["vel"] * masses[:, None], masses, atom_unit)
+    for _ in range(4):
+        omd.step(st, be, cav, s["dt"])
+    r, p, qm, pm = out[3]
+    assert _rel(r, st["r"]) <= 1e-9 and _rel(p, st["p"]) <= 1e-8
+    assert _rel(qm, st["q"]) <= 1e-8 and _rel(pm, st["pm"]) <= 1e-8
+    assert not np.array_equal(out[1][1], out[3][1])  # the stale tensors change the momenta
 
 
 def test_md_step_field_born_parity(params):
