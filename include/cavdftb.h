@@ -187,6 +187,45 @@ int cavdftb_eval_units(cavdftb_ctx* ctx, const double* pos, double* energy, doub
 int cavdftb_born_charges(cavdftb_ctx* ctx, const double* pos, int32_t mode, double h, double* born,
                          double* ens_std, int32_t* unit_status);
 
+/* The paper's real-space / reciprocal-space photon propagation (Theory, Eq.
+ * hlm3 and Eq. dpj; Steps 1-4), an alternative to the mode-space cavity of
+ * cavdftb_step.  One photon pair (q_n, p_n) per unit (cell n at R_n = n a), the
+ * coupling taken at omega_0 for every k so that it is local in real space:
+ * each cell carries eta q_n mu_n + eta^2 mu_n^2 / (2 omega_0^2), mu_n = e . mu.
+ * The free photons are propagated exactly in k-space with the cavity
+ * dispersion omega_k = sqrt(omega_0^2 + c^2 k^2) (= c sqrt((pi/L)^2 + k^2) with
+ * omega_0 = c pi / L), k = 2 pi j / (n_units a) on the symmetric grid
+ * j = -floor((n-1)/2) .. floor(n/2), stored by DFT index j mod n.
+ * cavdftb_set_realspace_cavity sets eta, omega_0, c (speed of light in the
+ * medium, a.u.) and a (bohr).  The transforms are radix-2 FFTs for a power-of-
+ * two number of units and direct sums otherwise, up to CAVDFTB_RS_MAX_DIRECT
+ * units; other sizes return CAVDFTB_EINVAL. */
+#define CAVDFTB_RS_MAX_DIRECT 4096
+int cavdftb_set_realspace_cavity(cavdftb_ctx* ctx, double eta, double omega0, double c_medium, double cell_a);
+
+/* Photon start at frozen matter for the real-space scheme: one SCC per unit
+ * at r, then q_n = -eta mu_n / omega_0^2 (the minimum of the local photon
+ * term) and p_n = 0 (device [n_units] each). */
+int cavdftb_init_photons_realspace(cavdftb_ctx* ctx, const double* r, double* qn, double* pn);
+
+/* n_steps MD steps of the real-space scheme on device state r, p [n_atoms][3]
+ * and qn, pn [n_units] (Steps 1-4):
+ *   p_n -= dt/2 eta mu_n(t); p += dt/2 (F - (eta q_n + eta^2 mu_n / omega_0^2) e.Z);
+ *   r += dt p/m; matter at r(t+dt); the same nuclear half-kick with q_n(t) and
+ *   mu_n(t+dt); p_n -= dt/2 eta mu_n(t+dt);
+ *   a_k = sum_n sqrt(omega_0/2N) (q_n + i p_n/omega_0) e^{-ik R_n} -> (q_k, p_k);
+ *   exact rotation by omega_k dt; back with a_n = sum_k sqrt(omega_k/2N)
+ *   (q_k + i p_k/omega_k) e^{ik R_n}.
+ * born_mode and h_fd as in cavdftb_step (with cavdftb_set_born_interval).
+ * obs (device [n_steps][CAVDFTB_N_OBS] or NULL) as in cavdftb_step, the photon
+ * energy being sum_k (p_k^2 + omega_k^2 q_k^2)/2 plus the local coupling and
+ * self-energy terms.  qk_record (device [n_steps][n_units] or NULL) receives
+ * q_k after every step, by DFT index, for the angle-resolved photon spectra
+ * (Results: I_k(omega) from the q_k autocorrelation).  The first call after
+ * cavdftb_init_photons_realspace evaluates the matter at r first. */
+int cavdftb_step_realspace(cavdftb_ctx* ctx, double* r, double* p, double* qn, double* pn, int32_t n_steps,
+                           double dt, int32_t born_mode, double h_fd, double* obs, double* qk_record);
+
 /* Copy of a context work array, as left by the last evaluation or MD step on the
  * context stream (device to device, asynchronous on that stream):
  *   CAVDFTB_WORK_MU_POL   [n_units]      e . mu_n, the projected unit dipoles

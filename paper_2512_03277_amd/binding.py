@@ -61,6 +61,10 @@ SYMBOLS = {
     "cavdftb_set_schedule": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32]),
     "cavdftb_set_graph": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "cavdftb_set_born_interval": (ctypes.c_int, [_vp, ctypes.c_int32]),
+    "cavdftb_set_realspace_cavity": (ctypes.c_int, [_vp, _c_d, _c_d, _c_d, _c_d]),
+    "cavdftb_init_photons_realspace": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "cavdftb_step_realspace": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, ctypes.c_int32, _c_d, ctypes.c_int32, _c_d,
+                                              _vp, _vp]),
     "cavdftb_read_work": (ctypes.c_int, [_vp, ctypes.c_int32, _vp]),
     "cavdftb_sg_features": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "cavdftb_sg_prep": (ctypes.c_int, [_vp, _vp, _c_i32, _c_i32, _vp, _vp, _vp]),
@@ -205,6 +209,26 @@ class Context:
             raise CavdftbError(f"read_work: unknown array {which}")
         self._check(self.lib.cavdftb_read_work(self.ctx, int(which), _ptr(dst, self.torch.float64, sizes[which], "dst")),
                     "read_work")
+
+    def set_realspace_cavity(self, eta, omega0, c_medium, cell_a):
+        self._check(self.lib.cavdftb_set_realspace_cavity(self.ctx, float(eta), float(omega0), float(c_medium),
+                                                          float(cell_a)), "set_realspace_cavity")
+
+    def init_photons_realspace(self, r, qn, pn):
+        t = self.torch
+        U = self.n_units
+        self._check(self.lib.cavdftb_init_photons_realspace(
+            self.ctx, _ptr(r, t.float64, self.n_atoms * 3, "r"), _ptr(qn, t.float64, U, "qn"),
+            _ptr(pn, t.float64, U, "pn")), "init_photons_realspace")
+
+    def step_realspace(self, r, p, qn, pn, n_steps, dt, born_mode=BORN_MULLIKEN, h_fd=1e-3, obs=None, qk_record=None):
+        t = self.torch
+        NA, U = self.n_atoms, self.n_units
+        self._check(self.lib.cavdftb_step_realspace(
+            self.ctx, _ptr(r, t.float64, NA * 3, "r"), _ptr(p, t.float64, NA * 3, "p"), _ptr(qn, t.float64, U, "qn"),
+            _ptr(pn, t.float64, U, "pn"), int(n_steps), float(dt), int(born_mode), float(h_fd),
+            _ptr(obs, t.float64, int(n_steps) * N_OBS, "obs"),
+            _ptr(qk_record, t.float64, int(n_steps) * U, "qk_record")), "step_realspace")
 
     def set_born_interval(self, every):
         self._check(self.lib.cavdftb_set_born_interval(self.ctx, int(every)), "set_born_interval")

@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <new>
 #include <string>
 #include <utility>
@@ -146,6 +147,14 @@ struct cavdftb_ctx {
   int64_t graph_scc_launches = 0;  // SCC launches inside the graph
   int64_t graph_replays = 0, graph_captures = 0;
   unsigned int* d_obs_row = nullptr;  // row of obs the next observables launch writes
+  // real-space cavity: one photon pair per cell (U cells)
+  bool rs_ready = false, rs_primed = false;
+  double rs_eta = 0.0, rs_w0 = 0.0;
+  double* d_rs_wk = nullptr;      // [U] omega_k by DFT index
+  double* d_rs_qk = nullptr;      // [U] q_k after the last step
+  double* d_rs_pk = nullptr;      // [U] p_k after the last step
+  double2* d_rs_buf0 = nullptr;   // [U] transform buffers
+  double2* d_rs_buf1 = nullptr;
   // timing
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending, ev_free;
@@ -716,6 +725,11 @@ int cavdftb_create(const cavdftb_params* params, const cavdftb_layout* L, void* 
   CK(dalloc(c, &c->d_counters, 8));
   CK(dalloc(c, &c->d_job_counter, 1));
   CK(dalloc(c, &c->d_obs_row, 1));
+  CK(dalloc(c, &c->d_rs_wk, U));
+  CK(dalloc(c, &c->d_rs_qk, U));
+  CK(dalloc(c, &c->d_rs_pk, U));
+  CK(dalloc(c, &c->d_rs_buf0, U));
+  CK(dalloc(c, &c->d_rs_buf1, U));
   CK(hipMemcpy(c->d_unit_off, c->h_unit_off.data(), (U + 1) * sizeof(int32_t), hipMemcpyHostToDevice));
   CK(hipMemcpy(c->d_species, L->species, NA, hipMemcpyHostToDevice));
   CK(hipMemcpy(c->d_unit_x, L->unit_x, U * sizeof(double), hipMemcpyHostToDevice));
@@ -909,6 +923,7 @@ int cavdftb_eval_units(cavdftb_ctx* ctx, const double* pos, double* energy, doub
   }
   ctx->warm_valid = ctx->warm_enabled != 0;
   ctx->primed = false;
+  ctx->rs_primed = false;
   ctx->md_hist = 0;
   return CAVDFTB_OK;
 }
@@ -926,6 +941,7 @@ int cavdftb_born_charges(cavdftb_ctx* ctx, const double* pos, int32_t mode, doub
   int rc = eval_center(ctx, pos, false);
   if (rc) return rc;
   ctx->primed = false;
+  ctx->rs_primed = false;
   if (mode == CAVDFTB_BORN_MULLIKEN) {
     hipError_t e = launch_born_mulliken(ctx->d_charges, ctx->NA, born, ctx->stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "born mulliken");
@@ -1079,6 +1095,7 @@ int cavdftb_init_photons(cavdftb_ctx* ctx, const double* r, double* qm, double* 
   int rc = eval_center(ctx, r, false);
   if (rc) return rc;
   ctx->primed = false;
+  ctx->rs_primed = false;
   CavArgs ca = cav_args(ctx);
   hipError_t e = launch_mu_pol(ctx->d_dipole, ctx->pol, ctx->U, ctx->d_status, ctx->d_mu_pol, ctx->stream);
   if (e == hipSuccess) e = launch_cav_scatter(ca, ctx->d_mu_pol, ctx->d_F, nullptr, ctx->stream);
@@ -1091,6 +1108,7 @@ int cavdftb_invalidate(cavdftb_ctx* ctx) {
   if (!ctx) return CAVDFTB_EINVAL;
   ctx->gen += 1;
   ctx->primed = false;
+  ctx->rs_primed = false;
   return CAVDFTB_OK;
 }
 
@@ -1103,6 +1121,7 @@ int cavdftb_step(cavdftb_ctx* ctx, double* r, double* p, double* qm, double* pm,
   if (born_mode != CAVDFTB_BORN_MULLIKEN && !(h_fd > 0.0)) return fail(ctx, CAVDFTB_EINVAL, "step: need h_fd > 0");
   if (born_mode == CAVDFTB_BORN_SURROGATE && !ctx->sg_ready)
     return fail(ctx, CAVDFTB_EINVAL, "step: no surrogate set (cavdftb_set_surrogate)");
+  ctx->rs_primed = false;
   hipStream_t s = ctx->stream;
   CavArgs ca = cav_args(ctx);
   hipError_t e;
@@ -1125,6 +1144,100 @@ int cavdftb_step(cavdftb_ctx* ctx, double* r, double* p, double* qm, double* pm,
     rc = graph_steady(ctx) && !periodic ? replay_step(ctx, r, p, qm, pm, dt, born_mode, h_fd, obs)
                                         : issue_step(ctx, r, p, qm, pm, dt, born_mode, h_fd, obs);
     if (rc) return rc;
+  }
+  return CAVDFTB_OK;
+}
+
+int cavdftb_set_realspace_cavity(cavdftb_ctx* ctx, double eta, double omega0, double c_medium, double cell_a) {
+  if (!ctx) return CAVDFTB_EINVAL;
+  if (!(eta >= 0.0) || !(omega0 > 0.0) || !(c_medium > 0.0) || !(cell_a > 0.0))
+    return fail(ctx, CAVDFTB_EINVAL, "set_realspace_cavity: need eta >= 0 and omega0, c, cell_a > 0");
+  const int n = ctx->U;
+  if ((n & (n - 1)) != 0 && n > CAVDFTB_RS_MAX_DIRECT)
+    return fail(ctx, CAVDFTB_EINVAL, "set_realspace_cavity: n_units must be a power of two above 4096");
+  std::vector<double> wk(n);
+  for (int i = 0; i < n; ++i) {
+    const int j = i <= n / 2 ? i : i - n;  // symmetric grid by DFT index
+    const double k = 2.0 * M_PI * j / (n * cell_a);
+    wk[i] = std::sqrt(omega0 * omega0 + c_medium * c_medium * k * k);
+  }
+  hipError_t e = hipMemcpyAsync(ctx->d_rs_wk, wk.data(), n * sizeof(double), hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "set_realspace_cavity copy");
+  ctx->rs_eta = eta;
+  ctx->rs_w0 = omega0;
+  ctx->rs_ready = true;
+  ctx->rs_primed = false;
+  ctx->gen += 1;
+  return CAVDFTB_OK;
+}
+
+int cavdftb_init_photons_realspace(cavdftb_ctx* ctx, const double* r, double* qn, double* pn) {
+  if (!ctx) return CAVDFTB_EINVAL;
+  if (!r || !qn || !pn) return fail(ctx, CAVDFTB_EINVAL, "init_photons_realspace: null pointer");
+  if (!ctx->rs_ready) return fail(ctx, CAVDFTB_EINVAL, "init_photons_realspace: no real-space cavity set");
+  ctx->gen += 1;
+  int rc = eval_center(ctx, r, false);
+  if (rc) return rc;
+  ctx->primed = false;
+  ctx->rs_primed = false;
+  hipError_t e = launch_mu_pol(ctx->d_dipole, ctx->pol, ctx->U, ctx->d_status, ctx->d_mu_pol, ctx->stream);
+  if (e == hipSuccess) e = launch_rs_init(ctx->U, ctx->d_mu_pol, ctx->rs_eta, ctx->rs_w0, qn, pn, ctx->stream);
+  return e == hipSuccess ? CAVDFTB_OK : hip_fail(ctx, e, "init_photons_realspace");
+}
+
+int cavdftb_step_realspace(cavdftb_ctx* ctx, double* r, double* p, double* qn, double* pn, int32_t n_steps,
+                           double dt, int32_t born_mode, double h_fd, double* obs, double* qk_record) {
+  if (!ctx) return CAVDFTB_EINVAL;
+  if (!r || !p || !qn || !pn || n_steps < 0 || !(dt > 0.0))
+    return fail(ctx, CAVDFTB_EINVAL, "step_realspace: bad arguments");
+  if (!ctx->rs_ready) return fail(ctx, CAVDFTB_EINVAL, "step_realspace: no real-space cavity set");
+  if (!born_mode_ok(born_mode)) return fail(ctx, CAVDFTB_EINVAL, "step_realspace: unknown born mode");
+  if (born_mode != CAVDFTB_BORN_MULLIKEN && !(h_fd > 0.0))
+    return fail(ctx, CAVDFTB_EINVAL, "step_realspace: need h_fd > 0");
+  if (born_mode == CAVDFTB_BORN_SURROGATE && !ctx->sg_ready)
+    return fail(ctx, CAVDFTB_EINVAL, "step_realspace: no surrogate set (cavdftb_set_surrogate)");
+  hipStream_t s = ctx->stream;
+  const int n = ctx->U;
+  const double eta = ctx->rs_eta, w0 = ctx->rs_w0;
+  hipError_t e;
+  int rc;
+  ctx->gen += 1;  // the mode-space graph (if any) does not describe these launches
+  ctx->primed = false;
+  if (!ctx->rs_primed) {
+    ctx->born_count = 0;
+    rc = matter_stage(ctx, r, born_mode, h_fd);
+    if (rc) return rc;
+    ctx->rs_primed = true;
+  }
+  if (obs) {
+    e = launch_set_u32(ctx->d_obs_row, 0u, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "step_realspace obs row");
+  }
+  for (int st = 0; st < n_steps; ++st) {
+    // Step 1: local photon half-kick and nuclear velocity Verlet with q(t) held
+    e = launch_rs_photon_kick(n, ctx->d_mu_pol, eta, dt, pn, s);
+    if (e == hipSuccess) e = launch_rs_field(n, qn, ctx->d_mu_pol, eta, w0, ctx->d_field, s);
+    if (e == hipSuccess)
+      e = launch_kick_drift(ctx->NA, ctx->d_atom_unit, ctx->d_inv_mass, ctx->d_forces, ctx->d_zpol, ctx->d_field,
+                            dt, r, p, 1, ctx->d_status, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "step_realspace kick/drift");
+    rc = matter_stage(ctx, r, born_mode, h_fd);
+    if (rc) return rc;
+    e = launch_rs_field(n, qn, ctx->d_mu_pol, eta, w0, ctx->d_field, s);
+    if (e == hipSuccess)
+      e = launch_kick_drift(ctx->NA, ctx->d_atom_unit, ctx->d_inv_mass, ctx->d_forces, ctx->d_zpol, ctx->d_field,
+                            dt, r, p, 0, ctx->d_status, s);
+    if (e == hipSuccess) e = launch_rs_photon_kick(n, ctx->d_mu_pol, eta, dt, pn, s);
+    // Steps 2-4: to k-space, exact rotation, back to real space
+    if (e == hipSuccess)
+      e = launch_rs_photon_step(n, ctx->d_rs_wk, w0, dt, qn, pn, ctx->d_rs_buf0, ctx->d_rs_buf1, ctx->d_rs_qk,
+                                ctx->d_rs_pk, qk_record ? qk_record + (int64_t)st * n : nullptr, s);
+    if (e == hipSuccess && obs)
+      e = launch_rs_observables(ctx->U, ctx->d_unit_off, ctx->d_mass, p, ctx->d_energy, qn, ctx->d_mu_pol,
+                                ctx->d_rs_qk, ctx->d_rs_pk, ctx->d_rs_wk, eta, w0, ctx->d_status, ctx->d_cjob_iters,
+                                obs, ctx->d_obs_row, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "step_realspace photons");
   }
   return CAVDFTB_OK;
 }

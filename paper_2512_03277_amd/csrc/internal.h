@@ -124,6 +124,20 @@ hipError_t launch_observables(int n_units, int n_atoms, int n_modes, const int32
                               const double* F, const double* mu_pol, const int32_t* status,
                               const int32_t* job_iters, int n_jobs, double* obs, unsigned int* obs_row,
                               hipStream_t s);
+// ---- real-space cavity (one photon pair per cell) ----
+hipError_t launch_rs_photon_kick(int n, const double* mu_pol, double eta, double dt, double* pn, hipStream_t s);
+hipError_t launch_rs_field(int n, const double* q, const double* mu_pol, double eta, double w0, double* field,
+                           hipStream_t s);
+hipError_t launch_rs_init(int n, const double* mu_pol, double eta, double w0, double* q, double* pn, hipStream_t s);
+// Steps 2-4: transform to k-space, rotate by omega_k dt (recording q_k when qk_rec
+// is not null), transform back; buf0 / buf1 hold n complex values each
+hipError_t launch_rs_photon_step(int n, const double* wk, double w0, double dt, double* q, double* pn,
+                                 double2* buf0, double2* buf1, double* qk, double* pk, double* qk_rec,
+                                 hipStream_t s);
+hipError_t launch_rs_observables(int n_units, const int32_t* unit_off, const double* mass, const double* p,
+                                 const double* energy, const double* q, const double* mu_pol, const double* qk,
+                                 const double* pk, const double* wk, double eta, double w0, const int32_t* status,
+                                 const int32_t* job_iters, double* obs, unsigned int* obs_row, hipStream_t s);
 // *c = v by a one-thread kernel (a kernel node, not a memset, inside captured graphs)
 hipError_t launch_set_u32(unsigned int* c, unsigned int v, hipStream_t s);
 

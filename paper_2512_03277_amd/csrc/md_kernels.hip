@@ -319,6 +319,168 @@ __global__ __launch_bounds__(kNT) void observables_kernel(int nu, int na, int nm
   (void)na;
 }
 
+// ---- real-space cavity (one photon pair per cell, coupling local in real space)
+// p_n -= dt/2 eta mu_n
+__global__ __launch_bounds__(kNT) void rs_photon_kick_kernel(int n, const double* __restrict__ mu_pol, double eta,
+                                                             double dt, double* __restrict__ pn) {
+  const int i = blockIdx.x * kNT + threadIdx.x;
+  if (i < n) pn[i] -= 0.5 * dt * eta * mu_pol[i];
+}
+
+// field felt by the nuclei of cell n: eta q_n + eta^2 mu_n / omega_0^2
+__global__ __launch_bounds__(kNT) void rs_field_kernel(int n, const double* __restrict__ q,
+                                                       const double* __restrict__ mu_pol, double eta, double w0,
+                                                       double* __restrict__ field) {
+  const int i = blockIdx.x * kNT + threadIdx.x;
+  if (i < n) field[i] = eta * q[i] + eta * eta * mu_pol[i] / (w0 * w0);
+}
+
+// z_n = sqrt(omega_0 / 2N) (q_n + i p_n / omega_0)
+__global__ __launch_bounds__(kNT) void rs_pack_kernel(int n, const double* __restrict__ q,
+                                                      const double* __restrict__ pn, double w0,
+                                                      double2* __restrict__ z) {
+  const int i = blockIdx.x * kNT + threadIdx.x;
+  if (i >= n) return;
+  const double s = sqrt(w0 / (2.0 * n));
+  z[i] = make_double2(s * q[i], s * pn[i] / w0);
+}
+
+// a_k -> (q_k, p_k), exact rotation by omega_k dt, optional record of q_k, and
+// c_k = sqrt(omega_k / 2N) (q_k + i p_k / omega_k) for the inverse transform
+__global__ __launch_bounds__(kNT) void rs_kspace_kernel(int n, const double* __restrict__ wk, double dt,
+                                                        double2* __restrict__ a, double* __restrict__ qk_out,
+                                                        double* __restrict__ pk_out, double* __restrict__ qk_rec) {
+  const int k = blockIdx.x * kNT + threadIdx.x;
+  if (k >= n) return;
+  const double w = wk[k];
+  const double2 v = a[k];
+  const double q0 = 2.0 * v.x / sqrt(2.0 * w), p0 = sqrt(2.0 * w) * v.y;
+  const double c = cos(w * dt), s = sin(w * dt);
+  const double q = q0 * c + p0 * s / w, p = p0 * c - w * q0 * s;
+  if (qk_out) qk_out[k] = q;
+  if (pk_out) pk_out[k] = p;
+  if (qk_rec) qk_rec[k] = q;
+  const double sc = sqrt(w / (2.0 * n));
+  a[k] = make_double2(sc * q, sc * p / w);
+}
+
+// a_n -> q_n = 2 Re a_n / sqrt(2 omega_0), p_n = sqrt(2 omega_0) Im a_n
+__global__ __launch_bounds__(kNT) void rs_unpack_kernel(int n, const double2* __restrict__ a, double w0,
+                                                        double* __restrict__ q, double* __restrict__ pn) {
+  const int i = blockIdx.x * kNT + threadIdx.x;
+  if (i >= n) return;
+  q[i] = 2.0 * a[i].x / sqrt(2.0 * w0);
+  pn[i] = sqrt(2.0 * w0) * a[i].y;
+}
+
+// q_n = -eta mu_n / omega_0^2, p_n = 0
+__global__ __launch_bounds__(kNT) void rs_init_kernel(int n, const double* __restrict__ mu_pol, double eta, double w0,
+                                                      double* __restrict__ q, double* __restrict__ pn) {
+  const int i = blockIdx.x * kNT + threadIdx.x;
+  if (i >= n) return;
+  q[i] = -eta * mu_pol[i] / (w0 * w0);
+  pn[i] = 0.0;
+}
+
+// one radix-2 Stockham stage of X_k = sum_n x_n e^{sign 2 pi i k n / N} (N a power
+// of two, natural order in and out): butterflies j < N/2 with span ns
+__global__ __launch_bounds__(kNT) void fft_stage_kernel(int n, int ns, double sign, const double2* __restrict__ x,
+                                                        double2* __restrict__ y) {
+  const int j = blockIdx.x * kNT + threadIdx.x;
+  const int half = n >> 1;
+  if (j >= half) return;
+  const int k = j & (ns - 1);
+  double sn, cs;
+  sincospi(sign * (double)k / (double)ns, &sn, &cs);
+  const double2 v0 = x[j], u = x[j + half];
+  const double2 v1 = make_double2(u.x * cs - u.y * sn, u.x * sn + u.y * cs);
+  const int d = ((j - k) << 1) + k;
+  y[d] = make_double2(v0.x + v1.x, v0.y + v1.y);
+  y[d + ns] = make_double2(v0.x - v1.x, v0.y - v1.y);
+}
+
+// the same transform term by term for any N: one thread per output, angle from
+// the exact residue (k n) mod N
+__global__ __launch_bounds__(kNT) void dft_direct_kernel(int n, double sign, const double2* __restrict__ x,
+                                                         double2* __restrict__ y) {
+  const int k = blockIdx.x * kNT + threadIdx.x;
+  if (k >= n) return;
+  double re = 0.0, im = 0.0;
+  long long r = 0;  // (k m) mod n
+  for (int m = 0; m < n; ++m) {
+    double sn, cs;
+    sincospi(sign * 2.0 * (double)r / (double)n, &sn, &cs);
+    const double2 v = x[m];
+    re += v.x * cs - v.y * sn;
+    im += v.x * sn + v.y * cs;
+    r += k;
+    if (r >= n) r -= n;
+  }
+  y[k] = make_double2(re, im);
+}
+
+// observables of the real-space scheme: kinetic, matter, photon (free part in
+// k-space plus the local coupling and dipole self-energy), total, temperature,
+// flagged units, SCC iterations, sum of e.mu (same layout as the mode-space
+// observables); row *obs_row of obs, then the row counter advances
+__global__ __launch_bounds__(kNT) void rs_observables_kernel(int nu, const int32_t* __restrict__ uoff,
+                                                             const double* __restrict__ mass,
+                                                             const double* __restrict__ p,
+                                                             const double* __restrict__ energy,
+                                                             const double* __restrict__ q,
+                                                             const double* __restrict__ mu_pol,
+                                                             const double* __restrict__ qk,
+                                                             const double* __restrict__ pk,
+                                                             const double* __restrict__ wk, double eta, double w0,
+                                                             const int32_t* __restrict__ status,
+                                                             const int32_t* __restrict__ iters,
+                                                             double* __restrict__ obs,
+                                                             unsigned int* __restrict__ obs_row) {
+  __shared__ double red[kNT];
+  double ke = 0.0, v = 0.0, eph = 0.0, tsum = 0.0, nbad = 0.0, its = 0.0, mus = 0.0;
+  for (int u = threadIdx.x; u < nu; u += kNT) {
+    const int a0 = uoff[u], a1 = uoff[u + 1];
+    double pc[3] = {0.0, 0.0, 0.0}, mt = 0.0, k2 = 0.0;
+    for (int a = a0; a < a1; ++a) {
+      mt += mass[a];
+      for (int g = 0; g < 3; ++g) {
+        pc[g] += p[a * 3 + g];
+        k2 += p[a * 3 + g] * p[a * 3 + g] / (2.0 * mass[a]);
+      }
+    }
+    ke += k2;
+    const double kcm = (pc[0] * pc[0] + pc[1] * pc[1] + pc[2] * pc[2]) / (2.0 * mt);
+    const int dof = 3 * (a1 - a0) - 3;
+    if (dof > 0) tsum += 2.0 * (k2 - kcm) / (dof * 3.166811563e-6);
+    v += energy[u];
+    nbad += status[u] != 0 ? 1.0 : 0.0;
+    its += iters[u];
+    mus += mu_pol[u];
+    eph += 0.5 * (pk[u] * pk[u] + wk[u] * wk[u] * qk[u] * qk[u]) + eta * q[u] * mu_pol[u] +
+           eta * eta * mu_pol[u] * mu_pol[u] / (2.0 * w0 * w0);
+  }
+  ke = wg_sum(ke, red);
+  v = wg_sum(v, red);
+  eph = wg_sum(eph, red);
+  tsum = wg_sum(tsum, red);
+  nbad = wg_sum(nbad, red);
+  its = wg_sum(its, red);
+  mus = wg_sum(mus, red);
+  if (threadIdx.x == 0) {
+    const unsigned int row = *obs_row;
+    double* o = obs + (size_t)row * 8;
+    o[0] = ke;
+    o[1] = v;
+    o[2] = eph;
+    o[3] = ke + v + eph;
+    o[4] = tsum / nu;
+    o[5] = nbad;
+    o[6] = its;
+    o[7] = mus;
+    *obs_row = row + 1u;
+  }
+}
+
 __global__ void set_u32_kernel(unsigned int* c, unsigned int v) {
   if (threadIdx.x == 0) c[0] = v;
 }
@@ -436,6 +598,76 @@ hipError_t launch_observables(int n_units, int n_atoms, int n_modes, const int32
 
 hipError_t launch_set_u32(unsigned int* c, unsigned int v, hipStream_t s) {
   hipLaunchKernelGGL(set_u32_kernel, dim3(1), dim3(64), 0, s, c, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_rs_photon_kick(int n, const double* mu_pol, double eta, double dt, double* pn, hipStream_t s) {
+  hipLaunchKernelGGL(rs_photon_kick_kernel, dim3(nblk(n)), dim3(kNT), 0, s, n, mu_pol, eta, dt, pn);
+  return hipGetLastError();
+}
+
+hipError_t launch_rs_field(int n, const double* q, const double* mu_pol, double eta, double w0, double* field,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(rs_field_kernel, dim3(nblk(n)), dim3(kNT), 0, s, n, q, mu_pol, eta, w0, field);
+  return hipGetLastError();
+}
+
+hipError_t launch_rs_init(int n, const double* mu_pol, double eta, double w0, double* q, double* pn, hipStream_t s) {
+  hipLaunchKernelGGL(rs_init_kernel, dim3(nblk(n)), dim3(kNT), 0, s, n, mu_pol, eta, w0, q, pn);
+  return hipGetLastError();
+}
+
+// X = sum_m x_m e^{sign 2 pi i k m / n} into one of buf0 / buf1 (returned); x may
+// alias buf0.  Powers of two by Stockham stages, any other n term by term.
+hipError_t launch_dft(int n, double sign, const double2* x, double2* buf0, double2* buf1, double2** result,
+                      hipStream_t s) {
+  if ((n & (n - 1)) != 0) {
+    hipLaunchKernelGGL(dft_direct_kernel, dim3(nblk(n)), dim3(kNT), 0, s, n, sign, x, buf1);
+    *result = buf1;
+    return hipGetLastError();
+  }
+  const double2* src = x;
+  double2* dst = (x == buf1) ? buf0 : buf1;
+  if (n == 1) {
+    *result = const_cast<double2*>(x);
+    return hipSuccess;
+  }
+  for (int ns = 1; ns < n; ns <<= 1) {
+    hipLaunchKernelGGL(fft_stage_kernel, dim3(nblk(n / 2)), dim3(kNT), 0, s, n, ns, sign, src, dst);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    src = dst;
+    dst = (dst == buf1) ? buf0 : buf1;
+  }
+  *result = const_cast<double2*>(src);
+  return hipSuccess;
+}
+
+hipError_t launch_rs_photon_step(int n, const double* wk, double w0, double dt, double* q, double* pn,
+                                 double2* buf0, double2* buf1, double* qk, double* pk, double* qk_rec,
+                                 hipStream_t s) {
+  hipLaunchKernelGGL(rs_pack_kernel, dim3(nblk(n)), dim3(kNT), 0, s, n, q, pn, w0, buf0);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  double2* a = nullptr;
+  e = launch_dft(n, -1.0, buf0, buf0, buf1, &a, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(rs_kspace_kernel, dim3(nblk(n)), dim3(kNT), 0, s, n, wk, dt, a, qk, pk, qk_rec);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  double2* b = nullptr;
+  e = launch_dft(n, 1.0, a, a == buf0 ? buf0 : buf1, a == buf0 ? buf1 : buf0, &b, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(rs_unpack_kernel, dim3(nblk(n)), dim3(kNT), 0, s, n, b, w0, q, pn);
+  return hipGetLastError();
+}
+
+hipError_t launch_rs_observables(int n_units, const int32_t* unit_off, const double* mass, const double* p,
+                                 const double* energy, const double* q, const double* mu_pol, const double* qk,
+                                 const double* pk, const double* wk, double eta, double w0, const int32_t* status,
+                                 const int32_t* job_iters, double* obs, unsigned int* obs_row, hipStream_t s) {
+  hipLaunchKernelGGL(rs_observables_kernel, dim3(1), dim3(kNT), 0, s, n_units, unit_off, mass, p, energy, q, mu_pol,
+                     qk, pk, wk, eta, w0, status, job_iters, obs, obs_row);
   return hipGetLastError();
 }
 

@@ -1,0 +1,114 @@
+"""GPU parity of the real-space / reciprocal-space photon propagation against
+the oracle (oracle/realspace.py): full MD steps with SCC-DFTB matter for a
+power-of-two cell count (FFT stages) and for another count (direct sums), and
+free photons at 1024 cells rotating exactly with their dispersion.
+"""
+import numpy as np
+import pytest
+
+from cavgen import make_params, make_system
+from oracle import md as omd
+from oracle import realspace as ors
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2512_03277_amd as cd  # noqa: E402
+
+DEV = torch.device("cuda:0")
+ETA, W0, C, A = 0.01, 0.0075, 137.036, 1.0e4
+
+
+@pytest.fixture(scope="module")
+def params():
+    return make_params()
+
+
+def _t(a, dtype=torch.float64):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device=DEV)
+
+
+def _rel(a, b):
+    return np.max(np.abs(a - b)) / np.max(np.abs(b))
+
+
+def _subsystem(s, units):
+    off = s["unit_off"]
+    idx = np.concatenate([np.arange(off[u], off[u + 1]) for u in units])
+    out = dict(s)
+    out.update({"species": s["species"][idx], "pos": s["pos"][idx], "vel": s["vel"][idx],
+                "unit_off": np.concatenate([[0], np.cumsum([off[u + 1] - off[u] for u in units])]).astype(np.int32),
+                "unit_x": s["unit_x"][list(units)]})
+    return out
+
+
+@pytest.mark.parametrize("units", [list(range(8)), [0, 2, 3, 5, 7]])
+def test_realspace_md_steps_match_the_oracle(params, units):
+    s = _subsystem(make_system(1), units)
+    n, steps = len(units), 3
+    masses = params["mass"][s["species"]]
+    ctx = cd.context_from_system(params, s)
+    ctx.set_scc(1e-12, 300, 0.2)
+    ctx.set_realspace_cavity(ETA, W0, C, A)
+    r = _t(s["pos"])
+    p = _t(s["vel"] * masses[:, None])
+    qn = torch.zeros(n, dtype=torch.float64, device=DEV)
+    pn = torch.zeros_like(qn)
+    rec = torch.zeros(steps, n, dtype=torch.float64, device=DEV)
+    obs = torch.zeros(steps, cd.N_OBS, dtype=torch.float64, device=DEV)
+    ctx.init_photons_realspace(r, qn, pn)
+    ctx.step_realspace(r, p, qn, pn, steps, s["dt"], cd.BORN_MULLIKEN, 0.0, obs, rec)
+    assert ctx.sync() == 0
+    be = omd.DFTBBackend(params, s["species"], s["unit_off"], born="mulliken", tol=1e-12)
+    cav = ors.RealSpaceCavity(ETA, W0, ors.dispersion(n, W0, C, A), s["pol"])
+    atom_unit = np.repeat(np.arange(n), np.diff(s["unit_off"]))
+    st = ors.init_state(be, cav, s["pos"], s["vel"] * masses[:, None], masses, atom_unit)
+    qk_ref = []
+    for _ in range(steps):
+        ors.step(st, be, cav, s["dt"])
+        qk_ref.append(st["qk"].copy())
+    assert _rel(r.cpu().numpy(), st["r"]) <= 1e-9 and _rel(p.cpu().numpy(), st["p"]) <= 1e-8
+    assert _rel(qn.cpu().numpy(), st["q"]) <= 1e-8 and _rel(pn.cpu().numpy(), st["pn"]) <= 1e-8
+    assert _rel(rec.cpu().numpy(), np.array(qk_ref)) <= 1e-8
+    o = obs.cpu().numpy()[-1]
+    mu = st["ev"]["mu"] @ np.asarray(s["pol"])
+    assert o[2] == pytest.approx(ors.photon_energy(st["q"], st["pn"], mu, cav), rel=1e-8, abs=1e-12)
+    ctx.close()
+
+
+def test_free_photons_rotate_with_their_dispersion_at_1024_cells(params):
+    s = make_system(5, n_units=1024)
+    n, steps = 1024, 40
+    masses = params["mass"][s["species"]]
+    ctx = cd.context_from_system(params, s)
+    ctx.set_scc(1e-10, 200, 0.2)
+    ctx.set_realspace_cavity(0.0, W0, C, A)  # eta = 0: matter and photons decouple
+    r = _t(s["pos"])
+    p = _t(s["vel"] * masses[:, None])
+    qn = torch.zeros(n, dtype=torch.float64, device=DEV)
+    pn = torch.zeros_like(qn)
+    ctx.init_photons_realspace(r, qn, pn)
+    rng = np.random.default_rng(4)
+    q0, p0 = rng.normal(size=n), rng.normal(size=n) * W0
+    qn.copy_(_t(q0))
+    pn.copy_(_t(p0))
+    rec = torch.zeros(steps, n, dtype=torch.float64, device=DEV)
+    ctx.step_realspace(r, p, qn, pn, steps, s["dt"], cd.BORN_MULLIKEN, 0.0, None, rec)
+    ctx.sync()
+    wk = ors.dispersion(n, W0, C, A)
+    qk0, pk0 = ors.to_kspace(q0, p0, W0, wk)
+    t = steps * s["dt"]
+    ref = qk0 * np.cos(wk * t) + pk0 / wk * np.sin(wk * t)
+    assert np.max(np.abs(rec.cpu().numpy()[-1] - ref)) <= 1e-11 * np.max(np.abs(ref))
+    ctx.close()
+
+
+def test_realspace_cavity_rejects_large_non_power_of_two(params):
+    s = make_system(5, n_units=4100)
+    ctx = cd.context_from_system(params, s)
+    with pytest.raises(RuntimeError):
+        ctx.set_realspace_cavity(ETA, W0, C, A)
+    ctx.close()
