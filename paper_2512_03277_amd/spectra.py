@@ -87,3 +87,38 @@ def peak_report(series_a, series_b, dt, lo, hi):
     pa, pb = peak(fa, Ia, lo, hi), peak(fb, Ib, lo, hi)
     return {"peak_a_cm": pa, "peak_b_cm": pb, "shift_cm": pa - pb,
             "resolution_cm": resolution_cm(len(series_a), dt)}
+
+
+def spectrum_per_series(x, dt, pad=8, omega_squared=True):
+    """Spectrum of each column of x [T, K] separately (e.g. the angle-resolved
+    photon spectra I_k(omega), one column per k).  Returns (wavenumbers, I [K, F])."""
+    x = np.asarray(x, dtype=np.float64)
+    out = []
+    freq = None
+    for k in range(x.shape[1]):
+        freq, I = spectrum(autocorrelation(x[:, k]), dt, pad=pad, omega_squared=omega_squared)
+        out.append(I)
+    return freq, np.array(out)
+
+
+def top_peaks(freq, I, lo, hi, count=2, rel=0.1):
+    """The `count` highest local maxima of I with lo <= freq <= hi and at least
+    rel times the largest value there (the Hann window's side lobes stay below
+    3 % of their line), each refined by a parabola through its neighbours, in
+    increasing frequency."""
+    freq = np.asarray(freq)
+    I = np.asarray(I)
+    idx = np.nonzero((freq >= lo) & (freq <= hi))[0]
+    idx = idx[(idx > 0) & (idx < len(I) - 1)]
+    if len(idx) == 0:
+        return []
+    floor = rel * np.max(I[idx])
+    loc = [k for k in idx if I[k] >= I[k - 1] and I[k] > I[k + 1] and I[k] >= floor]
+    loc = sorted(loc, key=lambda k: -I[k])[:count]
+    out = []
+    for k in loc:
+        a, b, c = I[k - 1], I[k], I[k + 1]
+        den = a - 2.0 * b + c
+        d = 0.5 * (a - c) / den if den != 0.0 else 0.0
+        out.append(float(freq[k] + d * (freq[k + 1] - freq[k])))
+    return sorted(out)

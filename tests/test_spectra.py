@@ -94,3 +94,18 @@ def test_harmonic_polariton_lines_from_an_oracle_trajectory():
         assert spectra.peak(f, I, mid, 4000.0) == pytest.approx(lines[1], abs=2.0)
     rep = spectra.peak_report(np.array(z)[:, None], np.array(z)[:, None], DT, 500.0, 4000.0)
     assert rep["shift_cm"] == 0.0
+
+
+def test_per_series_spectra_and_top_peaks():
+    t = np.arange(6000) * DT
+    nus = (1500.0, 2200.0)
+    x = np.stack([np.cos(nus[0] / spectra.HARTREE_CM * t) + 0.5 * np.cos(nus[1] / spectra.HARTREE_CM * t),
+                  np.cos(nus[1] / spectra.HARTREE_CM * t)], axis=1)
+    f, I = spectra.spectrum_per_series(x, DT, omega_squared=False)
+    assert I.shape == (2, len(f))
+    p0 = spectra.top_peaks(f, I[0], 1000.0, 3000.0, count=2)
+    assert p0 == pytest.approx(list(nus), abs=0.2)
+    assert spectra.top_peaks(f, I[1], 1000.0, 3000.0, count=1) == pytest.approx([nus[1]], abs=0.2)
+
+    # a single line: its window side lobes are not reported as lines
+    assert len(spectra.top_peaks(f, I[1], 1000.0, 3000.0, count=3)) == 1
