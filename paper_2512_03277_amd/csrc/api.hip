@@ -126,7 +126,7 @@ struct cavdftb_ctx {
   // controls
   double tol = 1e-8;
   int32_t max_iter = 200;
-  double alpha = 0.2;
+  double alpha = 0.5;
   double w0 = 0.01;
   double jac_factor = 1.0e-3;
   int keep_hist = 1;
@@ -330,7 +330,7 @@ int eval_fd(cavdftb_ctx* c, const double* pos, double h, double* born, const int
     a.mu_job = c->d_mu_job + (int64_t)b.fjob0 * 3;
     a.job_status = c->d_fjob_status + b.fjob0;
     a.job_iters = c->d_fjob_iters + b.fjob0;
-    a.flags = JF_WARM_C | JF_WARM_DQ | (c->keep_hist ? JF_WARM_HIST : 0);
+    a.flags = JF_WARM_C | JF_WARM_DQ;  // fresh mixer: the stored history belongs to undisplaced SCCs
     int rc = run_scc(c, b, a);
     if (rc) return rc;
     hipError_t e = launch_born_fd_assemble(c->d_unit_off, b.d_fd_unit, job0, b.n_units,
@@ -364,7 +364,7 @@ int eval_field(cavdftb_ctx* c, const double* pos, double e_field, double* born, 
     a.f_status = c->d_f_status;
     a.job_status = c->d_fjob_status + b.fjob0;  // 6 n_units <= the bucket's displaced-job slots
     a.job_iters = c->d_fjob_iters + b.fjob0;
-    a.flags = JF_FORCES | JF_WARM_C | JF_WARM_DQ | (c->keep_hist ? JF_WARM_HIST : 0);
+    a.flags = JF_FORCES | JF_WARM_C | JF_WARM_DQ;  // fresh mixer, as for displaced jobs
     int rc = run_scc(c, b, a);
     if (rc) return rc;
   }
@@ -386,7 +386,7 @@ int eval_fd_forward(cavdftb_ctx* c, const double* pos, double h, double* born) {
     a.mu_job = c->d_mu_job + (int64_t)b.fjob0 * 3;
     a.job_status = c->d_fjob_status + b.fjob0;
     a.job_iters = c->d_fjob_iters + b.fjob0;
-    a.flags = JF_WARM_C | JF_WARM_DQ | (c->keep_hist ? JF_WARM_HIST : 0);
+    a.flags = JF_WARM_C | JF_WARM_DQ;  // fresh mixer, as for central differences
     int rc = run_scc(c, b, a);
     if (rc) return rc;
     hipError_t e = launch_born_fd_forward_assemble(c->d_unit_off, b.d_fd_unit, b.d_fw_job0, b.n_units,

@@ -38,7 +38,7 @@ def md_snapshots(params, system, n_snap, stride, warm=10, dt=None, tol=1e-8, log
     torch = _torch()
     dev = torch.device("cuda:0")
     ctx = B.context_from_system(params, system)
-    ctx.set_scc(tol, 200, 0.2)
+    ctx.set_scc(tol, 200, 0.5)
     masses = params["mass"][system["species"]]
     r = torch.tensor(system["pos"], device=dev)
     p = torch.tensor(system["vel"] * masses[:, None], device=dev)
@@ -86,7 +86,7 @@ def exact_born(params, system, pos_list, route="field", tol=1e-10, log=None):
     torch = _torch()
     dev = torch.device("cuda:0")
     ctx = B.context_from_system(params, system)
-    ctx.set_scc(tol, 300, 0.2)
+    ctx.set_scc(tol, 300, 0.5)
     out = torch.empty(len(pos_list), ctx.n_atoms, 9, dtype=torch.float64, device=dev)
     q = torch.empty(len(pos_list), ctx.n_atoms, dtype=torch.float64, device=dev)
     st = torch.zeros(ctx.n_units, dtype=torch.int32, device=dev)
@@ -232,7 +232,7 @@ def evaluate(params_sg, norm_sg, params, system, pos_list, born_exact, h=1e-3, t
     torch = _torch()
     dev = torch.device("cuda:0")
     ctx = B.context_from_system(params, system)
-    ctx.set_scc(1e-10, 300, 0.2)
+    ctx.set_scc(1e-10, 300, 0.5)
     ctx.set_surrogate(params_sg.contiguous().view(-1), norm_sg.contiguous().view(-1), thr)
     NA = ctx.n_atoms
     zs = torch.empty(NA, 9, dtype=torch.float64, device=dev)
