@@ -918,26 +918,47 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
         const bool ov_try = ordered && nocc > 0 && nv > 0 && 2 * nv <= n;  // K ping-pong needs 2 n_v <= n
         const int s0 = (kSylvester & 1) ? nv : 0;
         double st[4] = {0.0, 0.0, -INFINITY, -INFINITY};  // off-block, ov, max d_o, -min d_v
-        for (int i = rgrp; i < n; i += RG)
-          for (int j = lane; j < n; j += 64) {
-            if (j > i) {
-              const double v = 0.5 * (sA[i * LD + j] + sA[j * LD + i]);
-              sA[i * LD + j] = v;
-              sA[j * LD + i] = v;
-              if (i < nocc && j >= nocc) {
-                st[1] = fmax(st[1], fabs(v));
-                if (ov_try) sT[i * LD + s0 + j - nocc] = v / (sA[j * LD + j] - sA[i * LD + i]);
-              } else {
-                st[0] = fmax(st[0], fabs(v));
+        {
+          // rows in groups of SR per thread: all loads of a group (both triangles and
+          // the diagonals) are issued before its stores, so a group pays one LDS
+          // round trip; every index is clamped into the block, clamped work is skipped
+          constexpr int SR = 4;
+          for (int j0 = 0; j0 < n; j0 += 64) {
+            const int j = j0 + lane, jc = j < n ? j : n - 1;
+            const double djj = sA[jc * LD + jc];
+            for (int i0 = rgrp; i0 < n; i0 += SR * RG) {
+              double aij[SR], aji[SR], dii[SR];
+#pragma unroll
+              for (int g = 0; g < SR; ++g) {
+                const int i = min(i0 + g * RG, n - 1);
+                aij[g] = sA[i * LD + jc];
+                aji[g] = sA[jc * LD + i];
+                dii[g] = sA[i * LD + i];
               }
-            } else if (j == i) {
-              const double d = sA[i * LD + i];
-              if (i < nocc)
-                st[2] = fmax(st[2], d);
-              else
-                st[3] = fmax(st[3], -d);
+#pragma unroll
+              for (int g = 0; g < SR; ++g) {
+                const int i = i0 + g * RG;
+                if (i >= n || j >= n) continue;
+                if (j > i) {
+                  const double v = 0.5 * (aij[g] + aji[g]);
+                  sA[i * LD + j] = v;
+                  sA[j * LD + i] = v;
+                  if (i < nocc && j >= nocc) {
+                    st[1] = fmax(st[1], fabs(v));
+                    if (ov_try) sT[i * LD + s0 + j - nocc] = v / (djj - dii[g]);
+                  } else {
+                    st[0] = fmax(st[0], fabs(v));
+                  }
+                } else if (j == i) {
+                  if (i < nocc)
+                    st[2] = fmax(st[2], dii[g]);
+                  else
+                    st[3] = fmax(st[3], -dii[g]);
+                }
+              }
             }
           }
+        }
         if (ov_try)
           block_max_n<NT, 4>(st, sRed);  // also orders the writes of A and K0
         else
