@@ -45,7 +45,7 @@ extern "C" {
 #define CAVDFTB_EHIP (-3)
 
 /* unit_status bits */
-#define CAVDFTB_ST_NOT_CONVERGED 1 /* SCC hit max_iter, or set no new smallest residual for 40 iterations, before reaching tol */
+#define CAVDFTB_ST_NOT_CONVERGED 1 /* SCC hit max_iter, or set no new smallest residual for 20 iterations, before reaching tol */
 #define CAVDFTB_ST_NOT_PD 2        /* overlap matrix not positive definite */
 #define CAVDFTB_ST_DEGENERATE 4    /* HOMO-LUMO gap below 1e-6 hartree */
 #define CAVDFTB_ST_NAN 8           /* non-finite position or charge */

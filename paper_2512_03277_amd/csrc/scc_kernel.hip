@@ -32,7 +32,7 @@ namespace {
 constexpr int kMaxSweeps = 30;
 constexpr double kJacobiThr = 1.0e-14;  // off-diagonal threshold (hartree)
 constexpr double kGapMin = 1.0e-6;
-constexpr int kStagnation = 40;  // iterations without a new smallest residual before giving up
+constexpr int kStagnation = 20;  // iterations without a new smallest residual before giving up
 // warm orthonormalisation: Newton-Schulz from max|C0^T S C0 - I| <= kNsStart
 constexpr double kNsStart = 0.1;
 constexpr double kNsTol = 1.0e-15;
