@@ -4,8 +4,8 @@ The exact Born charges are the method's bottleneck (Results: the dipole
 derivatives are evaluated numerically and dominate the cost; Conclusion).  The
 surrogate replaces them by a small ensemble of per-species neural networks on
 rotation-invariant radial descriptors, with exact finite differences as the
-fallback where the ensemble disagrees.  Concrete form (the paper does not give
-one; readings listed in the design doc):
+fallback where the ensemble disagrees.  Concrete form (the paper gives none;
+each choice below is a reading, not the paper's):
 
   descriptors  G[A, s*16 + k] = sum_{B != A, species B = s, R_AB < Rc}
                    exp(-(R_AB - r_k)^2 / (2 sigma^2)) * (cos(pi R_AB / Rc) + 1) / 2
