@@ -19,7 +19,10 @@ needed when the photon state is kept per mode) one step of length dt is
   9. E_n(t+dt) with the rotated q for the next step.
 
 Photon start (Step 0 reading): q_m = -lambda_m F_m / omega_m, p_m = 0, the
-minimum of the photon energy at frozen matter.
+minimum of the photon energy at frozen matter.  A thermal start draws (q_m, p_m)
+from the classical Boltzmann distribution of that photon energy at temperature
+T instead: p_m = sqrt(kT) xi_m, q_m = -lambda_m F_m / omega_m + sqrt(kT) xi'_m / omega_m,
+with the standard normal draws xi passed in (no random numbers are drawn here).
 
 Pinned by: the free-mode closed form (lambda = 0), the normal-mode frequencies
 of a harmonic polariton, bounded energy error that shrinks with dt on the
@@ -101,14 +104,22 @@ def _zpol(Z, pol):
     return np.einsum("a,jab->jb", pol, Z)
 
 
-def init_state(backend, cavity, r, p, masses, atom_unit, photons="relaxed"):
+def init_state(backend, cavity, r, p, masses, atom_unit, photons="relaxed", kT=0.0, xi=None):
+    """photons: "relaxed" (minimum of the photon energy at frozen matter),
+    "zero" (q = p = 0) or "thermal" (Boltzmann at kT about the relaxed start;
+    xi holds 2M standard normal draws: xi[:M] for q, xi[M:] for p)."""
     ev = backend.evaluate(r)
     F = cav.dipole_sums(cavity.phi, ev["mu"] @ cavity.pol)
-    if photons == "relaxed":
+    pm = np.zeros_like(cavity.omega)
+    if photons in ("relaxed", "thermal"):
         q = -cavity.lam * F / cavity.omega
     else:
         q = np.zeros_like(cavity.omega)
-    pm = np.zeros_like(cavity.omega)
+    if photons == "thermal":
+        M = len(cavity.omega)
+        xi = np.asarray(xi, dtype=np.float64)
+        q = q + np.sqrt(kT) * xi[:M] / cavity.omega
+        pm = np.sqrt(kT) * xi[M:2 * M]
     E = cav.fields(cavity.phi, cavity.omega, cavity.lam, q, F)
     return {"r": np.array(r, dtype=np.float64), "p": np.array(p, dtype=np.float64), "q": q, "pm": pm,
             "ev": ev, "F": F, "E": E, "masses": np.asarray(masses, dtype=np.float64),

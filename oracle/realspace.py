@@ -23,10 +23,16 @@ DFT index j mod N), dispersion omega_k = c sqrt((pi / L)^2 + k^2) with
 omega_0 = c pi / L the k = 0 frequency (Theory).  The sums of Steps 2 and 4 are
 discrete Fourier transforms (numpy's FFT serves as that step).
 
+Photon start: q_n = -eta mu_n / omega_0^2, p_n = 0 (the minimum of the local
+term at frozen matter).  A thermal start adds the Boltzmann fluctuation of the
+free field at temperature T: q_k = sqrt(kT) xi_k / omega_k, p_k = sqrt(kT) xi'_k
+(standard normal draws passed in), carried to real space by Step 4's transform.
+
 Pinned by (tests/test_oracle_realspace.py): Steps 2 -> 4 with no rotation is the
 identity in both directions; Parseval for a flat dispersion; one cell with
 harmonic matter has the normal modes of its 2 x 2 mass-weighted Hessian; free
-photons (eta = 0) rotate exactly with omega_k.
+photons (eta = 0) rotate exactly with omega_k; the k = 0 polariton splitting of
+harmonic cells is linear in eta; a thermal start has kT/2 per quadratic term.
 """
 import numpy as np
 
@@ -69,13 +75,27 @@ def _zpol(Z, pol):
     return np.einsum("a,jab->jb", pol, Z)
 
 
-def init_state(backend, cav, r, p, masses, atom_unit):
+def thermal_offset(kT, xi, omega0, omega_k):
+    """Real-space (q_n, p_n) of the free-field fluctuation q_k = sqrt(kT) xi_k / omega_k,
+    p_k = sqrt(kT) xi'_k, with xi of length 2N (xi[:N] for q_k, xi[N:] for p_k)."""
+    N = len(omega_k)
+    xi = np.asarray(xi, dtype=np.float64)
+    return to_realspace(np.sqrt(kT) * xi[:N] / omega_k, np.sqrt(kT) * xi[N:2 * N], omega0, omega_k)
+
+
+def init_state(backend, cav, r, p, masses, atom_unit, kT=0.0, xi=None):
     """Photons at the minimum of the local photon term at frozen matter:
-    q_n = -eta mu_n / omega_0^2, p_n = 0."""
+    q_n = -eta mu_n / omega_0^2, p_n = 0; with xi given, plus the thermal
+    free-field fluctuation at kT (thermal_offset)."""
     ev = backend.evaluate(r)
     mu = ev["mu"] @ cav.pol
+    q = -cav.eta * mu / cav.omega0 ** 2
+    pn = np.zeros_like(mu)
+    if xi is not None:
+        dq, dp = thermal_offset(kT, xi, cav.omega0, cav.omega_k)
+        q, pn = q + dq, pn + dp
     return {"r": np.array(r, dtype=np.float64), "p": np.array(p, dtype=np.float64),
-            "q": -cav.eta * mu / cav.omega0 ** 2, "pn": np.zeros_like(mu), "ev": ev,
+            "q": q, "pn": pn, "ev": ev,
             "masses": np.asarray(masses, dtype=np.float64), "atom_unit": np.asarray(atom_unit)}
 
 

@@ -232,3 +232,30 @@ def test_born_refresh_interval_reuses_the_tensors(params):
     assert not np.array_equal(Zs[3], Zs[0])
     ref = md.DFTBBackend(params, s["species"], s["unit_off"], born="fd_forward")
     assert np.array_equal(ref.evaluate(r + 0.03)["Z"], Zs[3])
+
+
+def test_thermal_photon_start_is_boltzmann_about_the_relaxed_start():
+    # p_m ~ N(0, kT), q_m ~ N(-lambda F / omega, kT / omega^2): the photon energy at
+    # frozen matter (whose minimum is the relaxed start) has kT/2 per quadratic term
+    rng = np.random.default_rng(11)
+    n_units, M = 6, 4096
+    kT = 300.0 * 3.166811563e-6
+    m = np.full(n_units, 16.0 * AMU)
+    be = HarmonicBackend(m, np.full(n_units, 0.0075), rng.uniform(0.3, 0.8, n_units), np.zeros((n_units, 3)))
+    omega, k, theta, lam = mode_comb(M)
+    cavity = md.Cavity(omega, k, theta, lam, rng.uniform(0, 5e5, n_units), np.array([0.0, 0.0, 1.0]))
+    r = rng.normal(size=(n_units, 3)) * 0.05
+    xi = rng.normal(size=2 * M)
+    st0 = md.init_state(be, cavity, r, np.zeros((n_units, 3)), m, np.arange(n_units))
+    st = md.init_state(be, cavity, r, np.zeros((n_units, 3)), m, np.arange(n_units), photons="thermal", kT=kT, xi=xi)
+    assert cav.photon_energy(st0["q"], st0["pm"], omega, cavity.lam, st0["F"]) == pytest.approx(0.0, abs=1e-20)
+    kin = 0.5 * st["pm"] ** 2
+    pot = 0.5 * (omega * (st["q"] + cavity.lam * st["F"] / omega)) ** 2
+    tol = 5.0 * kT / 2 * np.sqrt(2.0 / M)
+    assert abs(kin.mean() - kT / 2) < tol and abs(pot.mean() - kT / 2) < tol
+    total = cav.photon_energy(st["q"], st["pm"], omega, cavity.lam, st["F"])
+    assert total == pytest.approx(kin.sum() + pot.sum(), rel=1e-12)
+    # kT = 0 is the relaxed start
+    st_cold = md.init_state(be, cavity, r, np.zeros((n_units, 3)), m, np.arange(n_units), photons="thermal", kT=0.0,
+                            xi=xi)
+    assert np.array_equal(st_cold["q"], st0["q"]) and not np.any(st_cold["pm"])
