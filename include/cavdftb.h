@@ -208,6 +208,18 @@ int cavdftb_set_realspace_cavity(cavdftb_ctx* ctx, double eta, double omega0, do
  * term) and p_n = 0 (device [n_units] each). */
 int cavdftb_init_photons_realspace(cavdftb_ctx* ctx, const double* r, double* qn, double* pn);
 
+/* Thermal photon start for the real-space scheme: the start above plus the
+ * classical Boltzmann fluctuation of the free field at temperature kT
+ * (hartree, finite, >= 0), drawn in k-space as q_k = sqrt(kT) xi[k] / omega_k,
+ * p_k = sqrt(kT) xi[n_units + k] (k by DFT index) and carried to (q_n, p_n)
+ * by the inverse transform of the step below.  xi: device [2 n_units]
+ * standard normal draws owned by the caller (the library draws no random
+ * numbers).  Null xi or a bad kT: CAVDFTB_EINVAL.  (Reading of Step 0: the
+ * paper equilibrates the photons by constrained dynamics at frozen matter;
+ * this gives that equilibrium directly for the free field.) */
+int cavdftb_init_photons_realspace_thermal(cavdftb_ctx* ctx, const double* r, double* qn, double* pn, double kT,
+                                           const double* xi);
+
 /* n_steps MD steps of the real-space scheme on device state r, p [n_atoms][3]
  * and qn, pn [n_units] (Steps 1-4):
  *   p_n -= dt/2 eta mu_n(t); p += dt/2 (F - (eta q_n + eta^2 mu_n / omega_0^2) e.Z);
@@ -303,6 +315,15 @@ int cavdftb_sg_to_local(const double* frames, const double* born, const double* 
 /* Photon start at frozen matter (Step 0 reading): q_m = -lambda_m F_m/omega_m,
  * p_m = 0, with F from one SCC evaluation at r (device). */
 int cavdftb_init_photons(cavdftb_ctx* ctx, const double* r, double* qm, double* pm);
+
+/* Thermal photon start (Step 0 reading): the classical Boltzmann distribution
+ * at temperature kT (hartree, finite, >= 0) of the photon energy at frozen
+ * matter, q_m = -lambda_m F_m/omega_m + sqrt(kT) xi[m]/omega_m and
+ * p_m = sqrt(kT) xi[M + m].  xi: device [2M] standard normal draws owned by
+ * the caller (the library draws no random numbers).  Null xi (M > 0) or a bad
+ * kT: CAVDFTB_EINVAL. */
+int cavdftb_init_photons_thermal(cavdftb_ctx* ctx, const double* r, double* qm, double* pm, double kT,
+                                 const double* xi);
 
 /* Advance n_steps MD steps of length dt in place on device state r, p
  * [n_atoms][3] (positions, momenta) and qm, pm [n_modes]:

@@ -56,6 +56,7 @@ SYMBOLS = {
     "cavdftb_born_charges": (ctypes.c_int, [_vp, _vp, _c_i32, _c_d, _vp, _vp, _vp]),
     "cavdftb_cavity_forces": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "cavdftb_init_photons": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "cavdftb_init_photons_thermal": (ctypes.c_int, [_vp, _vp, _vp, _vp, _c_d, _vp]),
     "cavdftb_set_surrogate": (ctypes.c_int, [_vp, _vp, _vp, _c_d]),
     "cavdftb_set_fallback": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "cavdftb_set_schedule": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32]),
@@ -63,6 +64,7 @@ SYMBOLS = {
     "cavdftb_set_born_interval": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "cavdftb_set_realspace_cavity": (ctypes.c_int, [_vp, _c_d, _c_d, _c_d, _c_d]),
     "cavdftb_init_photons_realspace": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "cavdftb_init_photons_realspace_thermal": (ctypes.c_int, [_vp, _vp, _vp, _vp, _c_d, _vp]),
     "cavdftb_step_realspace": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, ctypes.c_int32, _c_d, ctypes.c_int32, _c_d,
                                               _vp, _vp]),
     "cavdftb_read_work": (ctypes.c_int, [_vp, ctypes.c_int32, _vp]),
@@ -221,6 +223,15 @@ class Context:
             self.ctx, _ptr(r, t.float64, self.n_atoms * 3, "r"), _ptr(qn, t.float64, U, "qn"),
             _ptr(pn, t.float64, U, "pn")), "init_photons_realspace")
 
+    def init_photons_realspace_thermal(self, r, qn, pn, kT, xi):
+        """xi: device [2 n_units] standard normal draws (q_k first, then p_k)."""
+        t = self.torch
+        U = self.n_units
+        self._check(self.lib.cavdftb_init_photons_realspace_thermal(
+            self.ctx, _ptr(r, t.float64, self.n_atoms * 3, "r"), _ptr(qn, t.float64, U, "qn"),
+            _ptr(pn, t.float64, U, "pn"), float(kT), _ptr(xi, t.float64, 2 * U, "xi")),
+            "init_photons_realspace_thermal")
+
     def step_realspace(self, r, p, qn, pn, n_steps, dt, born_mode=BORN_MULLIKEN, h_fd=1e-3, obs=None, qk_record=None):
         t = self.torch
         NA, U = self.n_atoms, self.n_units
@@ -285,6 +296,14 @@ class Context:
         self._check(self.lib.cavdftb_init_photons(
             self.ctx, _ptr(r, t.float64, self.n_atoms * 3, "r"), _ptr(qm, t.float64, self.n_modes, "qm"),
             _ptr(pm, t.float64, self.n_modes, "pm")), "init_photons")
+
+    def init_photons_thermal(self, r, qm, pm, kT, xi):
+        """xi: device [2 n_modes] standard normal draws (q first, then p)."""
+        t = self.torch
+        self._check(self.lib.cavdftb_init_photons_thermal(
+            self.ctx, _ptr(r, t.float64, self.n_atoms * 3, "r"), _ptr(qm, t.float64, self.n_modes, "qm"),
+            _ptr(pm, t.float64, self.n_modes, "pm"), float(kT), _ptr(xi, t.float64, 2 * self.n_modes, "xi")),
+            "init_photons_thermal")
 
     def step(self, r, p, qm, pm, n_steps, dt, born_mode=BORN_MULLIKEN, h_fd=1e-3, obs=None):
         t = self.torch

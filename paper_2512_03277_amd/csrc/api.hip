@@ -1104,6 +1104,17 @@ int cavdftb_init_photons(cavdftb_ctx* ctx, const double* r, double* qm, double* 
   return CAVDFTB_OK;
 }
 
+int cavdftb_init_photons_thermal(cavdftb_ctx* ctx, const double* r, double* qm, double* pm, double kT,
+                                 const double* xi) {
+  if (!ctx) return CAVDFTB_EINVAL;
+  if (!(kT >= 0.0) || !std::isfinite(kT) || (ctx->M > 0 && !xi))
+    return fail(ctx, CAVDFTB_EINVAL, "init_photons_thermal: need finite kT >= 0 and xi");
+  const int rc = cavdftb_init_photons(ctx, r, qm, pm);
+  if (rc) return rc;
+  const hipError_t e = launch_photon_thermal(cav_args(ctx), kT, xi, qm, pm, ctx->stream);
+  return e == hipSuccess ? CAVDFTB_OK : hip_fail(ctx, e, "init_photons_thermal");
+}
+
 int cavdftb_invalidate(cavdftb_ctx* ctx) {
   if (!ctx) return CAVDFTB_EINVAL;
   ctx->gen += 1;
@@ -1184,6 +1195,18 @@ int cavdftb_init_photons_realspace(cavdftb_ctx* ctx, const double* r, double* qn
   hipError_t e = launch_mu_pol(ctx->d_dipole, ctx->pol, ctx->U, ctx->d_status, ctx->d_mu_pol, ctx->stream);
   if (e == hipSuccess) e = launch_rs_init(ctx->U, ctx->d_mu_pol, ctx->rs_eta, ctx->rs_w0, qn, pn, ctx->stream);
   return e == hipSuccess ? CAVDFTB_OK : hip_fail(ctx, e, "init_photons_realspace");
+}
+
+int cavdftb_init_photons_realspace_thermal(cavdftb_ctx* ctx, const double* r, double* qn, double* pn, double kT,
+                                           const double* xi) {
+  if (!ctx) return CAVDFTB_EINVAL;
+  if (!(kT >= 0.0) || !std::isfinite(kT) || !xi)
+    return fail(ctx, CAVDFTB_EINVAL, "init_photons_realspace_thermal: need finite kT >= 0 and xi");
+  const int rc = cavdftb_init_photons_realspace(ctx, r, qn, pn);
+  if (rc) return rc;
+  const hipError_t e = launch_rs_thermal(ctx->U, ctx->d_rs_wk, ctx->rs_w0, kT, xi, qn, pn, ctx->d_rs_buf0,
+                                         ctx->d_rs_buf1, ctx->stream);
+  return e == hipSuccess ? CAVDFTB_OK : hip_fail(ctx, e, "init_photons_realspace_thermal");
 }
 
 int cavdftb_step_realspace(cavdftb_ctx* ctx, double* r, double* p, double* qn, double* pn, int32_t n_steps,

@@ -97,6 +97,9 @@ hipError_t launch_mu_pol(const double* dipole, const double pol[3], int n_units,
 hipError_t launch_cav_scatter(const CavArgs& c, const double* mu_pol, double* F, double* fq, hipStream_t s);
 hipError_t launch_cav_gather(const CavArgs& c, const double* q, const double* F, double* field, hipStream_t s);
 hipError_t launch_init_photons(const CavArgs& c, const double* F, double* qm, double* pm, hipStream_t s);
+// q_m += sqrt(kT) xi_m / omega_m, p_m = sqrt(kT) xi_{M+m} (xi: 2M standard normals)
+hipError_t launch_photon_thermal(const CavArgs& c, double kT, const double* xi, double* qm, double* pm,
+                                 hipStream_t s);
 hipError_t launch_born_mulliken(const double* charges, int n_atoms, double* born, hipStream_t s);
 hipError_t launch_zpol_mulliken(const double* charges, const double pol[3], int n_atoms, double* zpol,
                                 hipStream_t s);
@@ -129,6 +132,10 @@ hipError_t launch_rs_photon_kick(int n, const double* mu_pol, double eta, double
 hipError_t launch_rs_field(int n, const double* q, const double* mu_pol, double eta, double w0, double* field,
                            hipStream_t s);
 hipError_t launch_rs_init(int n, const double* mu_pol, double eta, double w0, double* q, double* pn, hipStream_t s);
+// adds to (q_n, p_n) the real-space image of the k-space fluctuation q_k = sqrt(kT) xi_k / omega_k,
+// p_k = sqrt(kT) xi_{N+k} (xi: 2N standard normals); buf0, buf1: [n] transform buffers
+hipError_t launch_rs_thermal(int n, const double* wk, double w0, double kT, const double* xi, double* q, double* pn,
+                             double2* buf0, double2* buf1, hipStream_t s);
 // Steps 2-4: transform to k-space, rotate by omega_k dt (recording q_k when qk_rec
 // is not null), transform back; buf0 / buf1 hold n complex values each
 hipError_t launch_rs_photon_step(int n, const double* wk, double w0, double dt, double* q, double* pn,

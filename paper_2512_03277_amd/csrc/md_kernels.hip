@@ -92,6 +92,18 @@ __global__ __launch_bounds__(kNT) void init_photons_kernel(const CavArgs c, cons
   }
 }
 
+// thermal start: the classical Boltzmann fluctuation of each mode about the
+// relaxed start, q_m += sqrt(kT) xi_m / omega_m, p_m = sqrt(kT) xi_{M+m}
+__global__ __launch_bounds__(kNT) void photon_thermal_kernel(int n_modes, const double* __restrict__ omega,
+                                                             double kT, const double* __restrict__ xi,
+                                                             double* __restrict__ qm, double* __restrict__ pm) {
+  const int m = blockIdx.x * kNT + threadIdx.x;
+  if (m >= n_modes) return;
+  const double s = sqrt(kT);
+  qm[m] += s * xi[m] / omega[m];
+  pm[m] = s * xi[n_modes + m];
+}
+
 __global__ __launch_bounds__(kNT) void born_mulliken_kernel(const double* __restrict__ q, int n,
                                                             double* __restrict__ born) {
   const int i = blockIdx.x * kNT + threadIdx.x;
@@ -373,6 +385,27 @@ __global__ __launch_bounds__(kNT) void rs_unpack_kernel(int n, const double2* __
   pn[i] = sqrt(2.0 * w0) * a[i].y;
 }
 
+// free-field thermal fluctuation in k-space, q_k = sqrt(kT) xi_k / omega_k and
+// p_k = sqrt(kT) xi_{N+k}, as c_k = sqrt(omega_k / 2N) (q_k + i p_k / omega_k)
+__global__ __launch_bounds__(kNT) void rs_thermal_kernel(int n, const double* __restrict__ wk, double kT,
+                                                         const double* __restrict__ xi, double2* __restrict__ c) {
+  const int k = blockIdx.x * kNT + threadIdx.x;
+  if (k >= n) return;
+  const double w = wk[k], s = sqrt(kT);
+  const double q = s * xi[k] / w, p = s * xi[n + k];
+  const double sc = sqrt(w / (2.0 * n));
+  c[k] = make_double2(sc * q, sc * p / w);
+}
+
+// a_n -> (q_n, p_n) as in rs_unpack_kernel, added to the current values
+__global__ __launch_bounds__(kNT) void rs_unpack_add_kernel(int n, const double2* __restrict__ a, double w0,
+                                                            double* __restrict__ q, double* __restrict__ pn) {
+  const int i = blockIdx.x * kNT + threadIdx.x;
+  if (i >= n) return;
+  q[i] += 2.0 * a[i].x / sqrt(2.0 * w0);
+  pn[i] += sqrt(2.0 * w0) * a[i].y;
+}
+
 // q_n = -eta mu_n / omega_0^2, p_n = 0
 __global__ __launch_bounds__(kNT) void rs_init_kernel(int n, const double* __restrict__ mu_pol, double eta, double w0,
                                                       double* __restrict__ q, double* __restrict__ pn) {
@@ -515,6 +548,14 @@ hipError_t launch_init_photons(const CavArgs& c, const double* F, double* qm, do
   return hipGetLastError();
 }
 
+hipError_t launch_photon_thermal(const CavArgs& c, double kT, const double* xi, double* qm, double* pm,
+                                 hipStream_t s) {
+  if (c.n_modes <= 0) return hipSuccess;
+  hipLaunchKernelGGL(photon_thermal_kernel, dim3(nblk(c.n_modes)), dim3(kNT), 0, s, c.n_modes, c.omega, kT, xi, qm,
+                     pm);
+  return hipGetLastError();
+}
+
 hipError_t launch_born_mulliken(const double* charges, int n_atoms, double* born, hipStream_t s) {
   hipLaunchKernelGGL(born_mulliken_kernel, dim3(nblk(n_atoms)), dim3(kNT), 0, s, charges, n_atoms, born);
   return hipGetLastError();
@@ -641,6 +682,18 @@ hipError_t launch_dft(int n, double sign, const double2* x, double2* buf0, doubl
   }
   *result = const_cast<double2*>(src);
   return hipSuccess;
+}
+
+hipError_t launch_rs_thermal(int n, const double* wk, double w0, double kT, const double* xi, double* q, double* pn,
+                             double2* buf0, double2* buf1, hipStream_t s) {
+  hipLaunchKernelGGL(rs_thermal_kernel, dim3(nblk(n)), dim3(kNT), 0, s, n, wk, kT, xi, buf0);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  double2* b = nullptr;
+  e = launch_dft(n, 1.0, buf0, buf0, buf1, &b, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(rs_unpack_add_kernel, dim3(nblk(n)), dim3(kNT), 0, s, n, b, w0, q, pn);
+  return hipGetLastError();
 }
 
 hipError_t launch_rs_photon_step(int n, const double* wk, double w0, double dt, double* q, double* pn,

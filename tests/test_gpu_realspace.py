@@ -112,3 +112,59 @@ def test_realspace_cavity_rejects_large_non_power_of_two(params):
     with pytest.raises(RuntimeError):
         ctx.set_realspace_cavity(ETA, W0, C, A)
     ctx.close()
+
+
+@pytest.mark.parametrize("units", [list(range(8)), [0, 2, 3, 5, 7]])
+def test_thermal_realspace_start_and_steps_match_the_oracle(params, units):
+    s = _subsystem(make_system(1), units)
+    n, steps = len(units), 2
+    kT = 300.0 * 3.166811563e-6
+    masses = params["mass"][s["species"]]
+    xi = np.random.default_rng(5).normal(size=2 * n)
+    ctx = cd.context_from_system(params, s)
+    ctx.set_scc(1e-12, 300, 0.2)
+    ctx.set_realspace_cavity(ETA, W0, C, A)
+    r = _t(s["pos"])
+    p = _t(s["vel"] * masses[:, None])
+    qn = torch.zeros(n, dtype=torch.float64, device=DEV)
+    pn = torch.zeros_like(qn)
+    ctx.init_photons_realspace_thermal(r, qn, pn, kT, _t(xi))
+    assert ctx.sync() == 0
+    be = omd.DFTBBackend(params, s["species"], s["unit_off"], born="mulliken", tol=1e-12)
+    cav = ors.RealSpaceCavity(ETA, W0, ors.dispersion(n, W0, C, A), s["pol"])
+    atom_unit = np.repeat(np.arange(n), np.diff(s["unit_off"]))
+    st = ors.init_state(be, cav, s["pos"], s["vel"] * masses[:, None], masses, atom_unit, kT=kT, xi=xi)
+    assert _rel(qn.cpu().numpy(), st["q"]) <= 1e-10 and _rel(pn.cpu().numpy(), st["pn"]) <= 1e-10
+    ctx.step_realspace(r, p, qn, pn, steps, s["dt"], cd.BORN_MULLIKEN, 0.0, None, None)
+    assert ctx.sync() == 0
+    for _ in range(steps):
+        ors.step(st, be, cav, s["dt"])
+    assert _rel(r.cpu().numpy(), st["r"]) <= 1e-9 and _rel(p.cpu().numpy(), st["p"]) <= 1e-8
+    assert _rel(qn.cpu().numpy(), st["q"]) <= 1e-8 and _rel(pn.cpu().numpy(), st["pn"]) <= 1e-8
+    with pytest.raises(RuntimeError):
+        ctx.init_photons_realspace_thermal(r, qn, pn, -1.0, _t(xi))
+    ctx.close()
+
+
+def test_thermal_mode_start_matches_the_oracle(params):
+    s = make_system(1)
+    masses = params["mass"][s["species"]]
+    ctx = cd.context_from_system(params, s)
+    ctx.set_scc(1e-12, 300, 0.2)
+    M = ctx.n_modes
+    kT = 300.0 * 3.166811563e-6
+    xi = np.random.default_rng(6).normal(size=2 * M)
+    r = _t(s["pos"])
+    qm = torch.zeros(M, dtype=torch.float64, device=DEV)
+    pm = torch.zeros_like(qm)
+    ctx.init_photons_thermal(r, qm, pm, kT, _t(xi))
+    assert ctx.sync() == 0
+    be = omd.DFTBBackend(params, s["species"], s["unit_off"], born="mulliken", tol=1e-12)
+    cavity = omd.Cavity(s["omega"], s["k"], s["theta"], s["lam"], s["unit_x"], s["pol"])
+    atom_unit = np.repeat(np.arange(len(s["unit_off"]) - 1), np.diff(s["unit_off"]))
+    st = omd.init_state(be, cavity, s["pos"], s["vel"] * masses[:, None], masses, atom_unit, photons="thermal",
+                        kT=kT, xi=xi)
+    assert _rel(qm.cpu().numpy(), st["q"]) <= 1e-10 and _rel(pm.cpu().numpy(), st["pm"]) <= 1e-12
+    with pytest.raises(RuntimeError):
+        ctx.init_photons_thermal(r, qm, pm, float("nan"), _t(xi))
+    ctx.close()
