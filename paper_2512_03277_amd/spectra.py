@@ -101,6 +101,18 @@ def spectrum_per_series(x, dt, pad=8, omega_squared=True):
     return freq, np.array(out)
 
 
+def averaged_spectrum(x, dt, columns, pad=8, omega_squared=False):
+    """One spectrum from the time-origin autocorrelations of the selected
+    columns of x [T, K], averaged over those columns (e.g. the photon
+    coordinates q_k of all modes near normal incidence, whose frequencies
+    differ by less than the resolution).  Returns (wavenumbers, I)."""
+    x = np.asarray(x, dtype=np.float64)
+    cols = np.asarray(columns)
+    if cols.size == 0:
+        raise ValueError("no columns selected")
+    return spectrum(autocorrelation(x[:, cols]), dt, pad=pad, omega_squared=omega_squared)
+
+
 def top_peaks(freq, I, lo, hi, count=2, rel=0.1):
     """The `count` highest local maxima of I with lo <= freq <= hi and at least
     rel times the largest value there (the Hann window's side lobes stay below

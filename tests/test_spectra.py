@@ -109,3 +109,36 @@ def test_per_series_spectra_and_top_peaks():
 
     # a single line: its window side lobes are not reported as lines
     assert len(spectra.top_peaks(f, I[1], 1000.0, 3000.0, count=3)) == 1
+
+
+def test_near_normal_average_resolves_the_polariton_pair_of_an_oracle_run():
+    # harmonic cells in the oracle's real-space scheme, all displaced at random so
+    # that every k is excited: the photon spectrum averaged over the modes near
+    # normal incidence has its two lines at the k = 0 polariton frequencies
+    from oracle import realspace as rs
+    N, W, d, eta, dt = 32, 0.0075, 0.6, 0.002, DT
+    m = np.full(N, 16.0 * AMU)
+    be = HarmonicBackend(m, np.full(N, W), np.full(N, d), np.zeros((N, 3)))
+    wk = rs.dispersion(N, W, 137.036, 1.0e6)
+    cav = rs.RealSpaceCavity(eta, W, wk, np.array([0.0, 0.0, 1.0]))
+    rng = np.random.default_rng(9)
+    r = np.zeros((N, 3))
+    r[:, 2] = rng.normal(size=N) * 0.05
+    st = rs.init_state(be, cav, r, np.zeros((N, 3)), m, np.arange(N))
+    qk = []
+    for _ in range(6000):
+        rs.step(st, be, cav, dt)
+        qk.append(st["qk"].copy())
+    qk = np.array(qk)
+    near = np.nonzero((wk - W) * spectra.HARTREE_CM <= 10.0)[0]
+    assert len(near) >= 5
+    f, I = spectra.averaged_spectrum(qk, dt, near)
+    g = eta * d / np.sqrt(m[0])
+    H = np.array([[W ** 2 + eta ** 2 * d ** 2 / (m[0] * W ** 2), g], [g, W ** 2]])
+    exact = np.sqrt(np.linalg.eigvalsh(H)) * spectra.HARTREE_CM
+    lines = spectra.top_peaks(f, I, W * spectra.HARTREE_CM - 700.0, W * spectra.HARTREE_CM + 700.0, count=2)
+    assert len(lines) == 2
+    res = spectra.resolution_cm(6000, dt)
+    assert np.allclose(lines, exact, atol=0.15 * res)
+    with pytest.raises(ValueError):
+        spectra.averaged_spectrum(qk, dt, [])
