@@ -268,12 +268,12 @@ def test_born_mulliken_is_charge_identity(params):
     assert np.max(np.abs(Z - r["charges"][:, None, None] * np.eye(3))) <= 1e-10
 
 
-def test_cavity_forces_parity(params):
-    # cavity sums at the benchmarked shape: 4096 cells, 256 modes
-    s = {"unit_x": (np.arange(4096) + 0.5) * CAVITY_LENGTH / 4096, "pol": np.array([0.0, 0.0, 1.0])}
-    s["omega"], s["k"], s["theta"], s["lam"] = mode_comb(256)
+@pytest.mark.parametrize("U,M", [(4096, 256), (4093, 2047), (3, 5)])
+def test_cavity_forces_parity(params, U, M):
+    # cavity sums at the benchmarked shape (4096 cells, 256 modes) and ragged ones
+    s = {"unit_x": (np.arange(U) + 0.5) * CAVITY_LENGTH / U, "pol": np.array([0.0, 0.0, 1.0])}
+    s["omega"], s["k"], s["theta"], s["lam"] = mode_comb(M)
     rng = np.random.default_rng(4)
-    U, M = 4096, len(s["omega"])
     off = np.arange(U + 1, dtype=np.int32) * 3
     sp = np.tile(np.array([0, 1, 1], dtype=np.int8), U)
     ctx = cd.Context(params, sp, off, s["unit_x"], s["omega"], s["k"], s["theta"], s["lam"], s["pol"])
@@ -511,4 +511,43 @@ def test_read_work_arrays_match_the_evaluation(params):
     with pytest.raises(RuntimeError):
         ctx.read_work(17, w["energy"])
     ref.close()
+    ctx.close()
+
+
+def test_observables_over_many_workgroups_match_their_definition(params):
+    # 1024 units and 2048 modes: the step observables are reduced over several
+    # workgroups of partial sums, then totalled in one; compared with the oracle's
+    # definition evaluated on the state and work arrays the device returns
+    s = make_system(5, n_units=1024)
+    masses = params["mass"][s["species"]]
+    ctx = cd.context_from_system(params, s)
+    ctx.set_scc(1e-8, 200)
+    U, M = ctx.n_units, ctx.n_modes
+    assert U == 1024 and M == 2048
+    r = _t(s["pos"])
+    p = _t(s["vel"] * masses[:, None])
+    qm = torch.zeros(M, dtype=torch.float64, device=DEV)
+    pm = torch.zeros_like(qm)
+    ctx.init_photons(r, qm, pm)
+    obs = torch.zeros(2, cd.N_OBS, dtype=torch.float64, device=DEV)
+    ctx.step(r, p, qm, pm, 2, s["dt"], cd.BORN_MULLIKEN, 0.0, obs)
+    n_bad = ctx.sync()
+    energy = torch.empty(U, dtype=torch.float64, device=DEV)
+    mu = torch.empty(U, dtype=torch.float64, device=DEV)
+    ctx.read_work(cd.WORK_ENERGY, energy)
+    ctx.read_work(cd.WORK_MU_POL, mu)
+    ctx.sync()
+    cav = omd.Cavity(s["omega"], s["k"], s["theta"], s["lam"], s["unit_x"], s["pol"])
+    mu_h = mu.cpu().numpy()
+    st = {"p": p.cpu().numpy(), "masses": masses, "ev": {"energy": energy.cpu().numpy()},
+          "q": qm.cpu().numpy(), "pm": pm.cpu().numpy(), "F": ocav.dipole_sums(cav.phi, mu_h)}
+    o = omd.observables(st, cav, s["unit_off"])
+    row = obs.cpu().numpy()[-1]
+    assert row[0] == pytest.approx(o["kinetic"], rel=1e-12)
+    assert row[1] == pytest.approx(o["potential"], rel=1e-12)
+    assert row[2] == pytest.approx(o["photon"], rel=1e-10)
+    assert row[3] == pytest.approx(o["total"], rel=1e-12)
+    assert row[4] == pytest.approx(o["temperature"], rel=1e-12)
+    assert row[5] == n_bad
+    assert abs(row[7] - mu_h.sum()) <= 1e-12 * np.abs(mu_h).sum()
     ctx.close()
