@@ -147,6 +147,8 @@ struct cavdftb_ctx {
   int64_t graph_scc_launches = 0;  // SCC launches inside the graph
   int64_t graph_replays = 0, graph_captures = 0;
   unsigned int* d_obs_row = nullptr;  // row of obs the next observables launch writes
+  double* d_obs_part = nullptr;       // [obs_part_rows][8] partial sums of the observables
+  int obs_part_rows = 0;
   // real-space cavity: one photon pair per cell (U cells)
   bool rs_ready = false, rs_primed = false;
   double rs_eta = 0.0, rs_w0 = 0.0;
@@ -508,7 +510,8 @@ int issue_step(cavdftb_ctx* c, double* r, double* p, double* qm, double* pm, dou
   if (e == hipSuccess) e = launch_cav_gather(ca, qm, c->d_F, c->d_field, s);  // rotated q
   if (e == hipSuccess && obs)
     e = launch_observables(c->U, c->NA, c->M, c->d_unit_off, c->d_mass, p, c->d_energy, qm, pm, c->d_omega, c->d_lam,
-                           c->d_F, c->d_mu_pol, c->d_status, c->d_cjob_iters, c->U, obs, c->d_obs_row, s);
+                           c->d_F, c->d_mu_pol, c->d_status, c->d_cjob_iters, c->U, c->d_obs_part, c->obs_part_rows,
+                           obs, c->d_obs_row, s);
   if (e != hipSuccess) return hip_fail(c, e, "step cavity/kick");
   return CAVDFTB_OK;
 }
@@ -725,6 +728,8 @@ int cavdftb_create(const cavdftb_params* params, const cavdftb_layout* L, void* 
   CK(dalloc(c, &c->d_counters, 8));
   CK(dalloc(c, &c->d_job_counter, 1));
   CK(dalloc(c, &c->d_obs_row, 1));
+  c->obs_part_rows = observables_part_rows(std::max(U, c->M));
+  CK(dalloc(c, &c->d_obs_part, (size_t)c->obs_part_rows * 8));
   CK(dalloc(c, &c->d_rs_wk, U));
   CK(dalloc(c, &c->d_rs_qk, U));
   CK(dalloc(c, &c->d_rs_pk, U));
@@ -1259,7 +1264,7 @@ int cavdftb_step_realspace(cavdftb_ctx* ctx, double* r, double* p, double* qn, d
     if (e == hipSuccess && obs)
       e = launch_rs_observables(ctx->U, ctx->d_unit_off, ctx->d_mass, p, ctx->d_energy, qn, ctx->d_mu_pol,
                                 ctx->d_rs_qk, ctx->d_rs_pk, ctx->d_rs_wk, eta, w0, ctx->d_status, ctx->d_cjob_iters,
-                                obs, ctx->d_obs_row, s);
+                                ctx->d_obs_part, ctx->obs_part_rows, obs, ctx->d_obs_row, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "step_realspace photons");
   }
   return CAVDFTB_OK;

@@ -121,12 +121,18 @@ hipError_t launch_kick_drift(int n_atoms, const int32_t* atom_unit, const double
                              int do_drift, const int32_t* status, hipStream_t s);  // no cavity force on flagged units
 hipError_t launch_photon_kick(int n_modes, const double* omega, const double* lam, const double* F, double dt,
                               double* pm, int rotate, double* qm, hipStream_t s);
+// rows of 8 doubles of partial sums the observables need for n units, modes or jobs
+int observables_part_rows(int n);
+// step observables into row *obs_row of obs (then the counter advances): a first
+// pass writes fixed-order partial sums into part (part_rows rows of 8 doubles,
+// at least observables_part_rows(max(n_units, n_modes, n_jobs)), else
+// hipErrorInvalidValue), a one-workgroup second pass totals them in fixed order
 hipError_t launch_observables(int n_units, int n_atoms, int n_modes, const int32_t* unit_off,
                               const double* mass, const double* p, const double* energy,
                               const double* qm, const double* pm, const double* omega, const double* lam,
                               const double* F, const double* mu_pol, const int32_t* status,
-                              const int32_t* job_iters, int n_jobs, double* obs, unsigned int* obs_row,
-                              hipStream_t s);
+                              const int32_t* job_iters, int n_jobs, double* part, int part_rows, double* obs,
+                              unsigned int* obs_row, hipStream_t s);
 // ---- real-space cavity (one photon pair per cell) ----
 hipError_t launch_rs_photon_kick(int n, const double* mu_pol, double eta, double dt, double* pn, hipStream_t s);
 hipError_t launch_rs_field(int n, const double* q, const double* mu_pol, double eta, double w0, double* field,
@@ -144,7 +150,8 @@ hipError_t launch_rs_photon_step(int n, const double* wk, double w0, double dt, 
 hipError_t launch_rs_observables(int n_units, const int32_t* unit_off, const double* mass, const double* p,
                                  const double* energy, const double* q, const double* mu_pol, const double* qk,
                                  const double* pk, const double* wk, double eta, double w0, const int32_t* status,
-                                 const int32_t* job_iters, double* obs, unsigned int* obs_row, hipStream_t s);
+                                 const int32_t* job_iters, double* part, int part_rows, double* obs,
+                                 unsigned int* obs_row, hipStream_t s);
 // *c = v by a one-thread kernel (a kernel node, not a memset, inside captured graphs)
 hipError_t launch_set_u32(unsigned int* c, unsigned int v, hipStream_t s);
 

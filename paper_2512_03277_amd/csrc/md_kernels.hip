@@ -11,6 +11,8 @@
 // runs in a fixed order (no floating-point atomics).
 #include <math.h>
 
+#include <algorithm>
+
 #include "internal.h"
 
 namespace cavdftb {
@@ -59,28 +61,22 @@ __global__ __launch_bounds__(kNT) void scatter_kernel(const CavArgs c, const dou
   }
 }
 
-// E_n = sum_m phi_m(X_n) g_m with g_m = lambda omega (q + lambda F / omega);
-// one thread per cell, modes staged through LDS in chunks.
+// E_n = sum_m phi_m(X_n) g_m with g_m = lambda omega (q + lambda F / omega): one
+// wave per cell, lane l taking the modes m = l (mod 64), then a fixed butterfly
+// over the wave (enough waves to fill the chip for a few thousand cells)
 __global__ __launch_bounds__(kNT) void gather_kernel(const CavArgs c, const double* __restrict__ q,
                                                      const double* __restrict__ F, double* __restrict__ field) {
-  __shared__ double sg[kNT], sk[kNT], sth[kNT];
-  const int n = blockIdx.x * kNT + threadIdx.x;
-  const double x = n < c.n_units ? c.unit_x[n] : 0.0;
+  const int lane = threadIdx.x & 63;
+  const int n = blockIdx.x * (kNT / 64) + (threadIdx.x >> 6);
+  if (n >= c.n_units) return;  // whole waves
+  const double x = c.unit_x[n];
   double acc = 0.0;
-  for (int m0 = 0; m0 < c.n_modes; m0 += kNT) {
-    const int m = m0 + threadIdx.x;
-    if (m < c.n_modes) {
-      const double lw = c.lam[m] * c.omega[m];
-      sg[threadIdx.x] = lw * (q[m] + c.lam[m] * F[m] / c.omega[m]);
-      sk[threadIdx.x] = c.k[m];
-      sth[threadIdx.x] = c.theta[m];
-    }
-    __syncthreads();
-    const int cnt = min(kNT, c.n_modes - m0);
-    for (int j = 0; j < cnt; ++j) acc += sin(sk[j] * x + sth[j]) * sg[j];
-    __syncthreads();
+  for (int m = lane; m < c.n_modes; m += 64) {
+    const double g = c.lam[m] * c.omega[m] * (q[m] + c.lam[m] * F[m] / c.omega[m]);
+    acc += sin(c.k[m] * x + c.theta[m]) * g;
   }
-  if (n < c.n_units) field[n] = acc;
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if (lane == 0) field[n] = acc;
 }
 
 __global__ __launch_bounds__(kNT) void init_photons_kernel(const CavArgs c, const double* __restrict__ F,
@@ -266,69 +262,88 @@ __global__ __launch_bounds__(kNT) void photon_kernel(int nm, const double* __res
   pm[m] = p;
 }
 
-// one workgroup: fixed-order totals for the observables of one step, written to
-// row *obs_row of obs; the row counter then advances (one launch per MD step, so
-// the same launch can be replayed from a captured graph)
-__global__ __launch_bounds__(kNT) void observables_kernel(int nu, int na, int nm, const int32_t* __restrict__ uoff,
-                                                          const double* __restrict__ mass,
-                                                          const double* __restrict__ p,
-                                                          const double* __restrict__ energy,
-                                                          const double* __restrict__ qm,
-                                                          const double* __restrict__ pm,
-                                                          const double* __restrict__ omega,
-                                                          const double* __restrict__ lam,
-                                                          const double* __restrict__ F,
-                                                          const double* __restrict__ mu_pol,
-                                                          const int32_t* __restrict__ status,
-                                                          const int32_t* __restrict__ iters, int n_jobs,
-                                                          double* __restrict__ obs,
-                                                          unsigned int* __restrict__ obs_row) {
-  __shared__ double red[kNT];
-  double ke = 0.0, v = 0.0, eph = 0.0, tsum = 0.0, nbad = 0.0, its = 0.0, mus = 0.0;
-  for (int u = threadIdx.x; u < nu; u += kNT) {
-    const int a0 = uoff[u], a1 = uoff[u + 1];
-    double pc[3] = {0.0, 0.0, 0.0}, mt = 0.0, k2 = 0.0;
-    for (int a = a0; a < a1; ++a) {
-      mt += mass[a];
-      for (int g = 0; g < 3; ++g) {
-        pc[g] += p[a * 3 + g];
-        k2 += p[a * 3 + g] * p[a * 3 + g] / (2.0 * mass[a]);
-      }
+// kinetic energy and the temperature term of unit u: 2 (K - K_com) / (dof k_B)
+__device__ inline void unit_kinetic(int u, const int32_t* __restrict__ uoff, const double* __restrict__ mass,
+                                    const double* __restrict__ p, double& ke, double& tterm) {
+  const int a0 = uoff[u], a1 = uoff[u + 1];
+  double pc[3] = {0.0, 0.0, 0.0}, mt = 0.0, k2 = 0.0;
+  for (int a = a0; a < a1; ++a) {
+    mt += mass[a];
+    for (int g = 0; g < 3; ++g) {
+      pc[g] += p[a * 3 + g];
+      k2 += p[a * 3 + g] * p[a * 3 + g] / (2.0 * mass[a]);
     }
-    ke += k2;
-    const double kcm = (pc[0] * pc[0] + pc[1] * pc[1] + pc[2] * pc[2]) / (2.0 * mt);
-    const int dof = 3 * (a1 - a0) - 3;
-    if (dof > 0) tsum += 2.0 * (k2 - kcm) / (dof * 3.166811563e-6);
-    v += energy[u];
-    nbad += status[u] != 0 ? 1.0 : 0.0;
-    mus += mu_pol[u];
   }
-  for (int m = threadIdx.x; m < nm; m += kNT) {
-    const double x = qm[m] + lam[m] * F[m] / omega[m];
-    eph += 0.5 * pm[m] * pm[m] + 0.5 * omega[m] * omega[m] * x * x;
+  ke = k2;
+  const double kcm = (pc[0] * pc[0] + pc[1] * pc[1] + pc[2] * pc[2]) / (2.0 * mt);
+  const int dof = 3 * (a1 - a0) - 3;
+  tterm = dof > 0 ? 2.0 * (k2 - kcm) / (dof * 3.166811563e-6) : 0.0;
+}
+
+// first pass of the step observables: workgroup b takes units, modes and jobs
+// b*kNT .. b*kNT + kNT - 1 (one each per thread) and writes its fixed-order
+// partial sums (kinetic, matter, photon, temperature term, flagged units, SCC
+// iterations, e.mu) to part[b][0..6]
+__global__ __launch_bounds__(kNT) void observables_part_kernel(int nu, int nm, const int32_t* __restrict__ uoff,
+                                                               const double* __restrict__ mass,
+                                                               const double* __restrict__ p,
+                                                               const double* __restrict__ energy,
+                                                               const double* __restrict__ qm,
+                                                               const double* __restrict__ pm,
+                                                               const double* __restrict__ omega,
+                                                               const double* __restrict__ lam,
+                                                               const double* __restrict__ F,
+                                                               const double* __restrict__ mu_pol,
+                                                               const int32_t* __restrict__ status,
+                                                               const int32_t* __restrict__ iters, int n_jobs,
+                                                               double* __restrict__ part) {
+  __shared__ double red[kNT];
+  const int i = blockIdx.x * kNT + threadIdx.x;
+  double ke = 0.0, v = 0.0, eph = 0.0, tsum = 0.0, nbad = 0.0, its = 0.0, mus = 0.0;
+  if (i < nu) {
+    unit_kinetic(i, uoff, mass, p, ke, tsum);
+    v = energy[i];
+    nbad = status[i] != 0 ? 1.0 : 0.0;
+    mus = mu_pol[i];
   }
-  for (int j = threadIdx.x; j < n_jobs; j += kNT) its += iters[j];
-  ke = wg_sum(ke, red);
-  v = wg_sum(v, red);
-  eph = wg_sum(eph, red);
-  tsum = wg_sum(tsum, red);
-  nbad = wg_sum(nbad, red);
-  its = wg_sum(its, red);
-  mus = wg_sum(mus, red);
+  if (i < nm) {
+    const double x = qm[i] + lam[i] * F[i] / omega[i];
+    eph = 0.5 * pm[i] * pm[i] + 0.5 * omega[i] * omega[i] * x * x;
+  }
+  if (i < n_jobs) its = iters[i];
+  const double vals[7] = {ke, v, eph, tsum, nbad, its, mus};
+  for (int q = 0; q < 7; ++q) {
+    const double t = wg_sum(vals[q], red);
+    if (threadIdx.x == 0) part[blockIdx.x * 8 + q] = t;
+  }
+}
+
+// second pass, one workgroup: totals over the n_part partial rows in a fixed
+// order, written to row *obs_row of obs; the row counter then advances (one
+// launch per MD step, so the same launches can be replayed from a captured graph)
+__global__ __launch_bounds__(kNT) void observables_finish_kernel(int n_part, int nu, const double* __restrict__ part,
+                                                                 double* __restrict__ obs,
+                                                                 unsigned int* __restrict__ obs_row) {
+  __shared__ double red[kNT];
+  double tot[7];
+  for (int q = 0; q < 7; ++q) {
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < n_part; b += kNT) acc += part[b * 8 + q];
+    tot[q] = wg_sum(acc, red);
+  }
   if (threadIdx.x == 0) {
     const unsigned int row = *obs_row;
     double* o = obs + (size_t)row * 8;
-    o[0] = ke;
-    o[1] = v;
-    o[2] = eph;
-    o[3] = ke + v + eph;
-    o[4] = tsum / nu;
-    o[5] = nbad;
-    o[6] = its;
-    o[7] = mus;
+    o[0] = tot[0];
+    o[1] = tot[1];
+    o[2] = tot[2];
+    o[3] = tot[0] + tot[1] + tot[2];
+    o[4] = tot[3] / nu;
+    o[5] = tot[4];
+    o[6] = tot[5];
+    o[7] = tot[6];
     *obs_row = row + 1u;
   }
-  (void)na;
 }
 
 // ---- real-space cavity (one photon pair per cell, coupling local in real space)
@@ -452,65 +467,38 @@ __global__ __launch_bounds__(kNT) void dft_direct_kernel(int n, double sign, con
   y[k] = make_double2(re, im);
 }
 
-// observables of the real-space scheme: kinetic, matter, photon (free part in
-// k-space plus the local coupling and dipole self-energy), total, temperature,
-// flagged units, SCC iterations, sum of e.mu (same layout as the mode-space
-// observables); row *obs_row of obs, then the row counter advances
-__global__ __launch_bounds__(kNT) void rs_observables_kernel(int nu, const int32_t* __restrict__ uoff,
-                                                             const double* __restrict__ mass,
-                                                             const double* __restrict__ p,
-                                                             const double* __restrict__ energy,
-                                                             const double* __restrict__ q,
-                                                             const double* __restrict__ mu_pol,
-                                                             const double* __restrict__ qk,
-                                                             const double* __restrict__ pk,
-                                                             const double* __restrict__ wk, double eta, double w0,
-                                                             const int32_t* __restrict__ status,
-                                                             const int32_t* __restrict__ iters,
-                                                             double* __restrict__ obs,
-                                                             unsigned int* __restrict__ obs_row) {
+// first pass of the observables of the real-space scheme (same partial rows as
+// observables_part_kernel), the photon term of cell n being its free part in
+// k-space, (p_k^2 + omega_k^2 q_k^2)/2 at k = n, plus the local coupling and the
+// dipole self-energy of cell n
+__global__ __launch_bounds__(kNT) void rs_observables_part_kernel(int nu, const int32_t* __restrict__ uoff,
+                                                                  const double* __restrict__ mass,
+                                                                  const double* __restrict__ p,
+                                                                  const double* __restrict__ energy,
+                                                                  const double* __restrict__ q,
+                                                                  const double* __restrict__ mu_pol,
+                                                                  const double* __restrict__ qk,
+                                                                  const double* __restrict__ pk,
+                                                                  const double* __restrict__ wk, double eta, double w0,
+                                                                  const int32_t* __restrict__ status,
+                                                                  const int32_t* __restrict__ iters,
+                                                                  double* __restrict__ part) {
   __shared__ double red[kNT];
+  const int u = blockIdx.x * kNT + threadIdx.x;
   double ke = 0.0, v = 0.0, eph = 0.0, tsum = 0.0, nbad = 0.0, its = 0.0, mus = 0.0;
-  for (int u = threadIdx.x; u < nu; u += kNT) {
-    const int a0 = uoff[u], a1 = uoff[u + 1];
-    double pc[3] = {0.0, 0.0, 0.0}, mt = 0.0, k2 = 0.0;
-    for (int a = a0; a < a1; ++a) {
-      mt += mass[a];
-      for (int g = 0; g < 3; ++g) {
-        pc[g] += p[a * 3 + g];
-        k2 += p[a * 3 + g] * p[a * 3 + g] / (2.0 * mass[a]);
-      }
-    }
-    ke += k2;
-    const double kcm = (pc[0] * pc[0] + pc[1] * pc[1] + pc[2] * pc[2]) / (2.0 * mt);
-    const int dof = 3 * (a1 - a0) - 3;
-    if (dof > 0) tsum += 2.0 * (k2 - kcm) / (dof * 3.166811563e-6);
-    v += energy[u];
-    nbad += status[u] != 0 ? 1.0 : 0.0;
-    its += iters[u];
-    mus += mu_pol[u];
-    eph += 0.5 * (pk[u] * pk[u] + wk[u] * wk[u] * qk[u] * qk[u]) + eta * q[u] * mu_pol[u] +
-           eta * eta * mu_pol[u] * mu_pol[u] / (2.0 * w0 * w0);
+  if (u < nu) {
+    unit_kinetic(u, uoff, mass, p, ke, tsum);
+    v = energy[u];
+    nbad = status[u] != 0 ? 1.0 : 0.0;
+    its = iters[u];
+    mus = mu_pol[u];
+    eph = 0.5 * (pk[u] * pk[u] + wk[u] * wk[u] * qk[u] * qk[u]) + eta * q[u] * mu_pol[u] +
+          eta * eta * mu_pol[u] * mu_pol[u] / (2.0 * w0 * w0);
   }
-  ke = wg_sum(ke, red);
-  v = wg_sum(v, red);
-  eph = wg_sum(eph, red);
-  tsum = wg_sum(tsum, red);
-  nbad = wg_sum(nbad, red);
-  its = wg_sum(its, red);
-  mus = wg_sum(mus, red);
-  if (threadIdx.x == 0) {
-    const unsigned int row = *obs_row;
-    double* o = obs + (size_t)row * 8;
-    o[0] = ke;
-    o[1] = v;
-    o[2] = eph;
-    o[3] = ke + v + eph;
-    o[4] = tsum / nu;
-    o[5] = nbad;
-    o[6] = its;
-    o[7] = mus;
-    *obs_row = row + 1u;
+  const double vals[7] = {ke, v, eph, tsum, nbad, its, mus};
+  for (int c = 0; c < 7; ++c) {
+    const double t = wg_sum(vals[c], red);
+    if (threadIdx.x == 0) part[blockIdx.x * 8 + c] = t;
   }
 }
 
@@ -538,7 +526,7 @@ hipError_t launch_cav_scatter(const CavArgs& c, const double* mu_pol, double* F,
 
 hipError_t launch_cav_gather(const CavArgs& c, const double* q, const double* F, double* field, hipStream_t s) {
   if (c.n_units <= 0) return hipSuccess;
-  hipLaunchKernelGGL(gather_kernel, dim3(nblk(c.n_units)), dim3(kNT), 0, s, c, q, F, field);
+  hipLaunchKernelGGL(gather_kernel, dim3((c.n_units + kNT / 64 - 1) / (kNT / 64)), dim3(kNT), 0, s, c, q, F, field);
   return hipGetLastError();
 }
 
@@ -627,13 +615,21 @@ hipError_t launch_photon_kick(int n_modes, const double* omega, const double* la
   return hipGetLastError();
 }
 
+int observables_part_rows(int n) { return nblk(n > 0 ? n : 1); }
+
 hipError_t launch_observables(int n_units, int n_atoms, int n_modes, const int32_t* unit_off, const double* mass,
                               const double* p, const double* energy, const double* qm, const double* pm,
                               const double* omega, const double* lam, const double* F, const double* mu_pol,
-                              const int32_t* status, const int32_t* job_iters, int n_jobs, double* obs,
-                              unsigned int* obs_row, hipStream_t s) {
-  hipLaunchKernelGGL(observables_kernel, dim3(1), dim3(kNT), 0, s, n_units, n_atoms, n_modes, unit_off, mass, p,
-                     energy, qm, pm, omega, lam, F, mu_pol, status, job_iters, n_jobs, obs, obs_row);
+                              const int32_t* status, const int32_t* job_iters, int n_jobs, double* part,
+                              int part_rows, double* obs, unsigned int* obs_row, hipStream_t s) {
+  (void)n_atoms;
+  const int g = observables_part_rows(std::max(n_units, std::max(n_modes, n_jobs)));
+  if (g > part_rows) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(observables_part_kernel, dim3(g), dim3(kNT), 0, s, n_units, n_modes, unit_off, mass, p, energy,
+                     qm, pm, omega, lam, F, mu_pol, status, job_iters, n_jobs, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(observables_finish_kernel, dim3(1), dim3(kNT), 0, s, g, n_units, part, obs, obs_row);
   return hipGetLastError();
 }
 
@@ -718,9 +714,15 @@ hipError_t launch_rs_photon_step(int n, const double* wk, double w0, double dt, 
 hipError_t launch_rs_observables(int n_units, const int32_t* unit_off, const double* mass, const double* p,
                                  const double* energy, const double* q, const double* mu_pol, const double* qk,
                                  const double* pk, const double* wk, double eta, double w0, const int32_t* status,
-                                 const int32_t* job_iters, double* obs, unsigned int* obs_row, hipStream_t s) {
-  hipLaunchKernelGGL(rs_observables_kernel, dim3(1), dim3(kNT), 0, s, n_units, unit_off, mass, p, energy, q, mu_pol,
-                     qk, pk, wk, eta, w0, status, job_iters, obs, obs_row);
+                                 const int32_t* job_iters, double* part, int part_rows, double* obs,
+                                 unsigned int* obs_row, hipStream_t s) {
+  const int g = observables_part_rows(n_units);
+  if (g > part_rows) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(rs_observables_part_kernel, dim3(g), dim3(kNT), 0, s, n_units, unit_off, mass, p, energy, q,
+                     mu_pol, qk, pk, wk, eta, w0, status, job_iters, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(observables_finish_kernel, dim3(1), dim3(kNT), 0, s, g, n_units, part, obs, obs_row);
   return hipGetLastError();
 }
 
