@@ -4,11 +4,13 @@
 // bottleneck of the method (Results; Conclusion).  These kernels evaluate and
 // train the replacement: radial descriptors and atom-local frames, a per-species
 // 32 -> 128 -> 128 -> 9 SiLU network ensemble with BF16 operands and FP32
-// accumulation, the ensemble mean/spread with the acoustic-sum projection, and
+// accumulation (the hidden layers of the forward pass on the matrix cores), the ensemble mean/spread with the acoustic-sum projection, and
 // the Adam update of the FP32 master weights.  Every reduction has a fixed
 // order (per-tile partial sums reduced in tile order), so results do not depend
 // on scheduling.
 #include <math.h>
+
+#include <algorithm>
 
 #include "internal.h"
 
@@ -20,6 +22,7 @@ constexpr int OFF_W1 = 0, OFF_B1 = OFF_W1 + NIN * NHID, OFF_W2 = OFF_B1 + NHID, 
               OFF_W3 = OFF_B2 + NHID, OFF_B3 = OFF_W3 + NHID * NOUT, NPAR = OFF_B3 + NOUT;
 static_assert(NPAR == CAVDFTB_SG_N_PARAM, "parameter layout");
 constexpr int TILE = 64;  // atoms per workgroup
+constexpr int kForwardGrid = 512;  // persistent workgroups of the forward pass (two fit in a CU's LDS)
 constexpr int NT = 256;
 
 constexpr double kAng = 1.8897261246;
@@ -160,54 +163,93 @@ __global__ __launch_bounds__(NT) void prep_kernel(int n, int width, const int32_
 }
 
 // ---------------------------------------------------------------- network
-// one hidden layer for a 64-atom tile: out[a][j] = sum_k bf16(in[a][k]) bf16(W[k][j]) + b[j]
-template <int K>
-__device__ void dense_hidden(const float* __restrict__ in, int ldin, const float* __restrict__ W,
-                             const float* __restrict__ b, float* __restrict__ zout, float* __restrict__ hout) {
-  const int og = threadIdx.x & 15, ag = threadIdx.x >> 4;  // 8 outputs x 4 atoms per thread
-  float acc[4][8];
-  for (int i = 0; i < 4; ++i)
-    for (int j = 0; j < 8; ++j) acc[i][j] = 0.0f;
-  for (int k = 0; k < K; ++k) {
-    float av[4], wv[8];
-    for (int i = 0; i < 4; ++i) av[i] = bf16r(in[(ag * 4 + i) * ldin + k]);
-    for (int j = 0; j < 8; ++j) wv[j] = bf16r(W[k * NHID + og * 8 + j]);
-    for (int i = 0; i < 4; ++i)
-      for (int j = 0; j < 8; ++j) acc[i][j] = fmaf(av[i], wv[j], acc[i][j]);
-  }
-  for (int i = 0; i < 4; ++i)
-    for (int j = 0; j < 8; ++j) {
-      const float z = acc[i][j] + b[og * 8 + j];
-      zout[(ag * 4 + i) * NHID + og * 8 + j] = z;
-      hout[(ag * 4 + i) * NHID + og * 8 + j] = silu(z);
-    }
+// bfloat16 bits of x, round to nearest even (the rounding of bf16r)
+__device__ __forceinline__ unsigned short bf16_bits(float x) {
+  const unsigned int u = __float_as_uint(x);
+  return (unsigned short)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
 }
 
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// LDS row strides (bf16 elements) of the forward pass: 4 extra elements per
+// row spread the 8-byte operand reads of neighbouring rows over the banks
+constexpr int LDX = NIN + 4, LDH = NHID + 4;
+
+// one hidden layer of a 64-atom tile on the matrix cores:
+// z[a][j] = sum_k in[a][k] W[k][j] + b[j] with bf16 operands (in: bf16 rows
+// of stride ldin, Wt: W transposed in bf16, rows of stride ldw) and FP32
+// accumulation by v_mfma_f32_16x16x16_bf16; wave w takes atoms 16w..16w+15 and
+// all NHID outputs (8 tiles of 16x16).  z goes to act (pre-activation, for the
+// backward pass) and bf16(silu(z)) to hout.
+template <int K>
+__device__ void dense_hidden_mfma(const unsigned short* __restrict__ in, int ldin,
+                                  const unsigned short* __restrict__ Wt, int ldw, const float* __restrict__ b,
+                                  float* __restrict__ act, int m, unsigned short* __restrict__ hout) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r16 = lane & 15, kq = (lane >> 4) * 4;
+  f32x4 acc[NHID / 16];
+#pragma unroll
+  for (int t = 0; t < NHID / 16; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    const bf16x4 av = *reinterpret_cast<const bf16x4*>(in + (16 * w + r16) * ldin + k0 + kq);
+    bf16x4 bv[NHID / 16];
+#pragma unroll
+    for (int t = 0; t < NHID / 16; ++t) bv[t] = *reinterpret_cast<const bf16x4*>(Wt + (16 * t + r16) * ldw + k0 + kq);
+#pragma unroll
+    for (int t = 0; t < NHID / 16; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv[t], acc[t], 0, 0, 0);
+  }
+  // lane holds rows 16w + kq + i (i = 0..3) of output column 16t + r16
+#pragma unroll
+  for (int t = 0; t < NHID / 16; ++t) {
+    const int j = 16 * t + r16;
+    const float bj = b[j];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int a = 16 * w + kq + i;
+      const float z = acc[t][i] + bj;
+      if (act && a < m) act[(int64_t)a * 2 * NHID + j] = z;
+      hout[a * LDH + j] = bf16_bits(silu(z));
+    }
+  }
+}
+
+// forward pass of one member over n atoms: y = W3 h2 + b3, h2 = silu(W2 h1 + b2),
+// h1 = silu(W1 x + b1), every product with bf16 operands and FP32 accumulation.
+// Persistent workgroups: the weights are converted to transposed bf16 in LDS
+// once, then the workgroup takes 64-atom tiles blockIdx.x, blockIdx.x + gridDim.x, ...
+// act (or null) receives the pre-activations z1, z2 per atom for the backward pass.
 __global__ __launch_bounds__(NT) void forward_kernel(const float* __restrict__ P, const float* __restrict__ x, int n,
                                                      float* __restrict__ y, float* __restrict__ act) {
-  __shared__ float sx[TILE * NIN];
-  __shared__ float sz[TILE * NHID];
-  __shared__ float sh1[TILE * NHID];
-  __shared__ float sh2[TILE * NHID];
-  const int t0 = blockIdx.x * TILE;
-  const int m = min(TILE, n - t0);
-  for (int e = threadIdx.x; e < TILE * NIN; e += NT) sx[e] = (e / NIN) < m ? x[(int64_t)t0 * NIN + e] : 0.0f;
-  __syncthreads();
-  dense_hidden<NIN>(sx, NIN, P + OFF_W1, P + OFF_B1, sz, sh1);
-  __syncthreads();
-  if (act)
-    for (int e = threadIdx.x; e < m * NHID; e += NT) act[(int64_t)(t0 + e / NHID) * 2 * NHID + e % NHID] = sz[e];
-  __syncthreads();
-  dense_hidden<NHID>(sh1, NHID, P + OFF_W2, P + OFF_B2, sz, sh2);
-  __syncthreads();
-  if (act)
-    for (int e = threadIdx.x; e < m * NHID; e += NT)
-      act[(int64_t)(t0 + e / NHID) * 2 * NHID + NHID + e % NHID] = sz[e];
-  for (int e = threadIdx.x; e < m * NOUT; e += NT) {
-    const int a = e / NOUT, o = e % NOUT;
-    float s = 0.0f;
-    for (int k = 0; k < NHID; ++k) s = fmaf(bf16r(sh2[a * NHID + k]), bf16r(P[OFF_W3 + k * NOUT + o]), s);
-    y[(int64_t)(t0 + a) * NOUT + o] = s + P[OFF_B3 + o];
+  __shared__ __align__(16) unsigned short sW1t[NHID * LDX];
+  __shared__ __align__(16) unsigned short sW2t[NHID * LDH];
+  __shared__ __align__(16) unsigned short sH1[TILE * LDH];
+  __shared__ __align__(16) unsigned short sXH2[TILE * LDH];  // x tile (stride LDX) for layer 1, then h2
+  for (int e = threadIdx.x; e < NIN * NHID; e += NT) sW1t[(e % NHID) * LDX + e / NHID] = bf16_bits(P[OFF_W1 + e]);
+  for (int e = threadIdx.x; e < NHID * NHID; e += NT) sW2t[(e % NHID) * LDH + e / NHID] = bf16_bits(P[OFF_W2 + e]);
+  const int n_tiles = (n + TILE - 1) / TILE;
+  for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+    const int t0 = tile * TILE;
+    const int m = min(TILE, n - t0);
+    for (int e = threadIdx.x; e < TILE * NIN; e += NT) {
+      const int a = e / NIN, k = e % NIN;
+      sXH2[a * LDX + k] = a < m ? bf16_bits(x[(int64_t)t0 * NIN + e]) : (unsigned short)0;
+    }
+    __syncthreads();
+    dense_hidden_mfma<NIN>(sXH2, LDX, sW1t, LDX, P + OFF_B1, act ? act + (int64_t)t0 * 2 * NHID : nullptr, m, sH1);
+    __syncthreads();
+    dense_hidden_mfma<NHID>(sH1, LDH, sW2t, LDH, P + OFF_B2, act ? act + (int64_t)t0 * 2 * NHID + NHID : nullptr, m,
+                            sXH2);
+    __syncthreads();
+    for (int e = threadIdx.x; e < m * NOUT; e += NT) {
+      const int a = e / NOUT, o = e % NOUT;
+      float s = 0.0f;
+      for (int k = 0; k < NHID; ++k)
+        s = fmaf(__uint_as_float((unsigned int)sXH2[a * LDH + k] << 16), bf16r(P[OFF_W3 + k * NOUT + o]), s);
+      y[(int64_t)(t0 + a) * NOUT + o] = s + P[OFF_B3 + o];
+    }
+    __syncthreads();
   }
 }
 
@@ -534,7 +576,8 @@ hipError_t launch_sg_prep(int n, int width, const int32_t* idx, const double* v,
 }
 hipError_t launch_sg_forward(const float* P, const float* x, int n, float* y, float* act, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(forward_kernel, dim3((n + TILE - 1) / TILE), dim3(NT), 0, s, P, x, n, y, act);
+  const int n_tiles = (n + TILE - 1) / TILE;
+  hipLaunchKernelGGL(forward_kernel, dim3(std::min(n_tiles, kForwardGrid)), dim3(NT), 0, s, P, x, n, y, act);
   return hipGetLastError();
 }
 hipError_t launch_sg_backward(const float* P, const float* x, const float* act, const float* dy, int n, float* grad,
