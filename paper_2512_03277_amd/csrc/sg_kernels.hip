@@ -216,7 +216,8 @@ __device__ void dense_hidden_mfma(const unsigned short* __restrict__ in, int ldi
 }
 
 // forward pass of one member over n atoms: y = W3 h2 + b3, h2 = silu(W2 h1 + b2),
-// h1 = silu(W1 x + b1), every product with bf16 operands and FP32 accumulation.
+// h1 = silu(W1 x + b1), every product with bf16 operands and FP32 accumulation
+// on the matrix cores (the 9 outputs padded to one 16-wide tile).
 // Persistent workgroups: the weights are converted to transposed bf16 in LDS
 // once, then the workgroup takes 64-atom tiles blockIdx.x, blockIdx.x + gridDim.x, ...
 // act (or null) receives the pre-activations z1, z2 per atom for the backward pass.
@@ -226,8 +227,16 @@ __global__ __launch_bounds__(NT) void forward_kernel(const float* __restrict__ P
   __shared__ __align__(16) unsigned short sW2t[NHID * LDH];
   __shared__ __align__(16) unsigned short sH1[TILE * LDH];
   __shared__ __align__(16) unsigned short sXH2[TILE * LDH];  // x tile (stride LDX) for layer 1, then h2
+  __shared__ __align__(16) unsigned short sW3t[16 * LDH];     // W3 transposed, outputs 9..15 zero
   for (int e = threadIdx.x; e < NIN * NHID; e += NT) sW1t[(e % NHID) * LDX + e / NHID] = bf16_bits(P[OFF_W1 + e]);
   for (int e = threadIdx.x; e < NHID * NHID; e += NT) sW2t[(e % NHID) * LDH + e / NHID] = bf16_bits(P[OFF_W2 + e]);
+  for (int e = threadIdx.x; e < 16 * NHID; e += NT) {
+    const int o = e / NHID, k = e % NHID;
+    sW3t[o * LDH + k] = o < NOUT ? bf16_bits(P[OFF_W3 + k * NOUT + o]) : (unsigned short)0;
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int r16 = lane & 15, kq = (lane >> 4) * 4;
+  const float b3 = r16 < NOUT ? P[OFF_B3 + r16] : 0.0f;
   const int n_tiles = (n + TILE - 1) / TILE;
   for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
     const int t0 = tile * TILE;
@@ -242,13 +251,20 @@ __global__ __launch_bounds__(NT) void forward_kernel(const float* __restrict__ P
     dense_hidden_mfma<NHID>(sH1, LDH, sW2t, LDH, P + OFF_B2, act ? act + (int64_t)t0 * 2 * NHID + NHID : nullptr, m,
                             sXH2);
     __syncthreads();
-    for (int e = threadIdx.x; e < m * NOUT; e += NT) {
-      const int a = e / NOUT, o = e % NOUT;
-      float s = 0.0f;
-      for (int k = 0; k < NHID; ++k)
-        s = fmaf(__uint_as_float((unsigned int)sXH2[a * LDH + k] << 16), bf16r(P[OFF_W3 + k * NOUT + o]), s);
-      y[(int64_t)(t0 + a) * NOUT + o] = s + P[OFF_B3 + o];
+    // output layer: wave w takes atoms 16w..16w+15, one 16x16 tile over K = NHID
+    f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int k0 = 0; k0 < NHID; k0 += 16) {
+      const bf16x4 av = *reinterpret_cast<const bf16x4*>(sXH2 + (16 * wv + r16) * LDH + k0 + kq);
+      const bf16x4 bv = *reinterpret_cast<const bf16x4*>(sW3t + r16 * LDH + k0 + kq);
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
     }
+    if (r16 < NOUT)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int a = 16 * wv + kq + i;
+        if (a < m) y[(int64_t)(t0 + a) * NOUT + r16] = acc[i] + b3;
+      }
     __syncthreads();
   }
 }
