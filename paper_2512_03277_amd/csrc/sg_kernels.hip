@@ -97,9 +97,16 @@ __global__ __launch_bounds__(NT) void features_kernel(int n_atoms, const int32_t
     if (r >= rc) continue;
     const double fc = 0.5 * (cos(M_PI * r / rc) + 1.0);
     const int s = species[b];
+    // Gaussians exp(-(v - k)^2 / 2) at v = (r - r0) / dr for k = 0..15 by the
+    // exact product recurrence g_{k+1} = g_k exp(v - k - 1/2): two exponentials
+    // per pair instead of sixteen
+    const double v = (r - r0) / dr;
+    double gk = exp(-0.5 * v * v) * fc, ck = exp(v - 0.5);
+    constexpr double kInvE = 0.36787944117144233;  // exp(-1)
     for (int k = 0; k < 16; ++k) {
-      const double t = r - (r0 + k * dr);
-      g[s * 16 + k] += exp(-t * t / (2.0 * dr * dr)) * fc;
+      g[s * 16 + k] += gk;
+      gk *= ck;
+      ck *= kInvE;
     }
   }
   if (feat)
