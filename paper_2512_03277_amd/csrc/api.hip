@@ -88,6 +88,8 @@ struct cavdftb_ctx {
   double* d_ws_C = nullptr;
   double* d_ws_dq = nullptr;
   double* d_ws_dq_hist = nullptr;
+  double* d_fd_dq = nullptr;        // charges of the +h displaced jobs (3 n_a^2 per unit)
+  int64_t* d_fd_dq_off = nullptr;   // [U] offsets into d_fd_dq
   int md_hist = 0;  // consecutive MD evaluations whose charges are stored
   int64_t* d_hist_off = nullptr;
   double* d_hist = nullptr;
@@ -333,8 +335,15 @@ int eval_fd(cavdftb_ctx* c, const double* pos, double h, double* born, const int
     a.job_status = c->d_fjob_status + b.fjob0;
     a.job_iters = c->d_fjob_iters + b.fjob0;
     a.flags = JF_WARM_C | JF_WARM_DQ;  // fresh mixer: the stored history belongs to undisplaced SCCs
-    int rc = run_scc(c, b, a);
-    if (rc) return rc;
+    // +h jobs first; the -h jobs then start from the +h charges reflected
+    // through the centre, second order in h instead of first
+    a.fd_dq = c->d_fd_dq;
+    a.fd_dq_off = c->d_fd_dq_off;
+    for (int pass = 1; pass <= 2; ++pass) {
+      a.fd_pass = pass;
+      int rc = run_scc(c, b, a);
+      if (rc) return rc;
+    }
     hipError_t e = launch_born_fd_assemble(c->d_unit_off, b.d_fd_unit, job0, b.n_units,
                                            c->d_mu_job + (int64_t)b.fjob0 * 3, h, c->pol,
                                            c->d_fjob_status + b.fjob0, unit_flag, born, c->d_zpol, c->d_status,
@@ -684,6 +693,18 @@ int cavdftb_create(const cavdftb_params* params, const cavdftb_layout* L, void* 
   CK(dalloc(c, &c->d_ws_C, ws_total));
   CK(dalloc(c, &c->d_ws_dq, NA));
   CK(dalloc(c, &c->d_ws_dq_hist, 2 * (size_t)NA));
+  {
+    std::vector<int64_t> off(U);
+    int64_t tot = 0;
+    for (int u = 0; u < U; ++u) {
+      const int64_t na = c->h_unit_off[u + 1] - c->h_unit_off[u];
+      off[u] = tot;
+      tot += 3 * na * na;
+    }
+    CK(dalloc(c, &c->d_fd_dq_off, (size_t)U));
+    CK(dalloc(c, &c->d_fd_dq, (size_t)tot));
+    CK(hipMemcpy(c->d_fd_dq_off, off.data(), U * sizeof(int64_t), hipMemcpyHostToDevice));
+  }
   CK(dalloc(c, &c->d_hist_off, U));
   CK(dalloc(c, &c->d_hist, hist_total));
   CK(dalloc(c, &c->d_energy, U));
