@@ -336,7 +336,8 @@ int eval_fd(cavdftb_ctx* c, const double* pos, double h, double* born, const int
     a.job_iters = c->d_fjob_iters + b.fjob0;
     a.flags = JF_WARM_C | JF_WARM_DQ;  // fresh mixer: the stored history belongs to undisplaced SCCs
     // +h jobs first; the -h jobs then start from the +h charges reflected
-    // through the centre, second order in h instead of first
+    // through the centre, second order in h instead of first (fallback lists
+    // too, so that their results equal the full route's bit for bit)
     a.fd_dq = c->d_fd_dq;
     a.fd_dq_off = c->d_fd_dq_off;
     for (int pass = 1; pass <= 2; ++pass) {
@@ -376,8 +377,13 @@ int eval_field(cavdftb_ctx* c, const double* pos, double e_field, double* born, 
     a.job_status = c->d_fjob_status + b.fjob0;  // 6 n_units <= the bucket's displaced-job slots
     a.job_iters = c->d_fjob_iters + b.fjob0;
     a.flags = JF_FORCES | JF_WARM_C | JF_WARM_DQ;  // fresh mixer, as for displaced jobs
-    int rc = run_scc(c, b, a);
-    if (rc) return rc;
+    a.fd_dq = c->d_fd_dq;  // -field jobs start from the +field charges reflected through the centre
+    a.fd_dq_off = c->d_fd_dq_off;
+    for (int pass = 1; pass <= 2; ++pass) {  // also for fallback lists: their results equal the full route's
+      a.fd_pass = pass;
+      int rc = run_scc(c, b, a);
+      if (rc) return rc;
+    }
   }
   hipError_t e = launch_born_field_assemble(c->NA, c->d_atom_unit, c->d_unit_off, c->d_f_job, e_field, c->pol,
                                             c->d_f_status, unit_flag, born, c->d_zpol, c->d_status, c->stream);

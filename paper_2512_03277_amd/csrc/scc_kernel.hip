@@ -702,8 +702,12 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
       continue;
     }
     const int disp = a.job_disp ? a.job_disp[job] : -1;
-    if (a.fd_pass && disp >= 0 && (disp & 1) != (a.fd_pass == 2 ? 1 : 0)) continue;  // the other sign's pass
     const int fcode = disp <= -2 ? -2 - disp : -1;  // field job: dir*2 + (field < 0)
+    // sign and slot of a perturbed job of a central difference: the +h (+field)
+    // job of slot (3 atom + dir) (dir) runs in pass 1, its -h partner in pass 2
+    const int pm_sign = disp >= 0 ? (disp & 1) : (fcode >= 0 ? (fcode & 1) : -1);
+    const int64_t pm_slot = disp >= 0 ? (disp >> 1) : (fcode >> 1);
+    if (a.fd_pass && pm_sign >= 0 && pm_sign != (a.fd_pass == 2 ? 1 : 0)) continue;  // the other sign's pass
     const int a0 = a.unit_off[u];
     const int na = a.unit_off[u + 1] - a0;
     const int d_atom = disp >= 0 ? (disp >> 1) / 3 : -1;
@@ -767,8 +771,8 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
         const double d1 = a.ws_dq_hist[a0 + t], d2 = a.ws_dq_hist[(int64_t)a.n_atoms + a0 + t];
         dq0 = a.n_extrap >= 3 ? 3.0 * dq0 - 3.0 * d1 + d2 : 2.0 * dq0 - d1;
       }
-      if (a.fd_pass == 2 && disp >= 0) {  // -h job: the +h job's charges reflected through the centre
-        const double qp = a.fd_dq[a.fd_dq_off[u] + (int64_t)(disp >> 1) * na + t];
+      if (a.fd_pass == 2 && pm_sign == 1) {  // -h job: the +h job's charges reflected through the centre
+        const double qp = a.fd_dq[a.fd_dq_off[u] + pm_slot * na + t];
         if (isfinite(qp)) dq0 = 2.0 * dq0 - qp;
       }
       sDqIn[t] = dq0;
@@ -1368,8 +1372,8 @@ __global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
       for (int t = tid; t < na; t += NT)
         if (a.charges) a.charges[a0 + t] = -sDqOut[t];
     }
-    if (a.fd_pass == 1 && disp >= 0)
-      for (int t = tid; t < na; t += NT) a.fd_dq[a.fd_dq_off[u] + (int64_t)(disp >> 1) * na + t] = sDqOut[t];
+    if (a.fd_pass == 1 && pm_sign == 0)
+      for (int t = tid; t < na; t += NT) a.fd_dq[a.fd_dq_off[u] + pm_slot * na + t] = sDqOut[t];
     if ((a.flags & JF_FORCES) && disp < 0) {  // undisplaced and field jobs
       // W = 2 C_occ diag(eps_occ) C_occ^T = 1/2 P H P with H of the last iteration
       // (sV still holds its V; X_occ spans the occupied eigenspace, so no

@@ -79,9 +79,11 @@ def test_realspace_md_steps_match_the_oracle(params, units):
     ctx.close()
 
 
-def test_free_photons_rotate_with_their_dispersion_at_1024_cells(params):
-    s = make_system(5, n_units=1024)
-    n, steps = 1024, 40
+@pytest.mark.parametrize("n", [1024, 3000])
+def test_free_photons_rotate_with_their_dispersion_at_scale(params, n):
+    # 1024 cells: radix-2 transform stages; 3000 cells: direct sums
+    s = make_system(5, n_units=n)
+    steps = 40
     masses = params["mass"][s["species"]]
     ctx = cd.context_from_system(params, s)
     ctx.set_scc(1e-10, 200, 0.2)
