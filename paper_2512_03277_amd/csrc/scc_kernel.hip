@@ -643,7 +643,11 @@ struct Shared {
 
 
 template <int NMAX, int NT>
-__global__ __launch_bounds__(NT, 2) void scc_kernel(const SccArgs a) {
+// Four workgroups per CU for the 32-orbital bucket (its LDS allows it): the
+// compiler then keeps 128 VGPRs and spills a few hundred bytes per lane, and
+// the extra waves hide more latency than the spills cost (workload 5: 26.4 ->
+// 24.6 ms per step).  The larger LDS buckets are held to two by their LDS.
+__global__ __launch_bounds__(NT, NMAX == 32 ? 4 : 2) void scc_kernel(const SccArgs a) {
   constexpr int LD = Cfg<NMAX, NT>::LD;
   constexpr int RG = Cfg<NMAX, NT>::RG;
   constexpr int HALF = NMAX / 2;
