@@ -166,13 +166,16 @@ int cavdftb_eval_units(cavdftb_ctx* ctx, const double* pos, double* energy, doub
 /* Born charges born[A][a][b] = d mu_a / d R_{A b} (device [n_atoms][3][3]) at
  * positions pos (device).  mode CAVDFTB_BORN_MULLIKEN: Q_A delta_ab from one
  * SCC per unit; CAVDFTB_BORN_FD: central differences with step h (bohr) of the
- * converged SCC dipole, 6 n_atoms displaced SCCs per unit batched in one
- * launch, warm-started from the undisplaced solution (Results: the Born
- * charges are the bottleneck and are taken by finite differences);
+ * converged SCC dipole, 6 n_atoms displaced SCCs per unit, warm-started from
+ * the undisplaced solution, in two launches per orbital bucket: every +h SCC,
+ * then every -h SCC started from the +h charges reflected through the
+ * undisplaced ones (Results: the Born charges are the bottleneck and are taken
+ * by finite differences);
  * CAVDFTB_BORN_FIELD: the same tensor from the Maxwell relation
  * d mu_a / d R_Ab = d F_Ab / d field_a, as central differences of the SCC
  * forces in a uniform field +-h e_a (h in atomic units of field, e.g. 1e-4):
- * 6 field-perturbed SCCs per unit instead of 6 n_atoms, same warm start;
+ * 6 field-perturbed SCCs per unit instead of 6 n_atoms, same warm start and
+ * the same two launches (+field, then -field);
  * CAVDFTB_BORN_FD_FORWARD: forward differences (mu_a(R + h e_Ab) - mu_a(R)) / h
  * against the undisplaced dipole, 3 n_atoms displaced SCCs per unit, first
  * order in h (Computational details: the paper's finite differences);
