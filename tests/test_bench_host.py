@@ -38,6 +38,10 @@ def test_profiled_traffic_follows_the_kernel_source_hash(tmp_path):
         expect = float(lines["traffic_bytes_per_launch"]) if lines["kernel_source_sha256_16"].strip() == sha else None
         assert b.profiled_traffic(*key) == expect
     assert b.profiled_traffic(99, "mulliken") is None
+    for key in b.PROFILES:
+        ex = b.profiled_value(*key, "executed_fp64_flops_per_launch")
+        assert ex is None or ex > 0
+    assert b.profiled_value(2, "mulliken", "no_such_figure") is None
     # a summary for another source is not used
     fake = tmp_path / "p.md"
     fake.write_text("traffic_bytes_per_launch: 123\nkernel_source_sha256_16: 0000000000000000\n")
