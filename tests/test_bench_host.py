@@ -39,8 +39,8 @@ def test_profiled_traffic_follows_the_kernel_source_hash(tmp_path):
         assert b.profiled_traffic(*key) == expect
     assert b.profiled_traffic(99, "mulliken") is None
     for key in b.PROFILES:
-        ex = b.profiled_value(*key, "executed_fp64_flops_per_launch")
-        assert ex is None or ex > 0
+        ex = b.profiled_value(*key, "executed_per_algorithmic_fp64")
+        assert ex is None or 0.5 < ex < 3.0
     assert b.profiled_value(2, "mulliken", "no_such_figure") is None
     # a summary for another source is not used
     fake = tmp_path / "p.md"
