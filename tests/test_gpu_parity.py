@@ -158,6 +158,27 @@ def test_full_size_eight_water_workload_sampled(params):
     assert np.max(np.abs(F.sum(1))) < 1e-10
 
 
+def test_full_size_fd_born_workload_sampled(params):
+    # 1024 units of 8 waters with central-difference Born charges (147,456
+    # displaced SCCs, +h then -h launches), the roofline shape; sampled units
+    # against the oracle's central differences, the acoustic sum at any size
+    s = make_system(3)
+    ctx = make_ctx(params, s, tol=1e-12)
+    born = torch.zeros(ctx.n_atoms, 3, 3, dtype=torch.float64, device=DEV)
+    st = torch.zeros(ctx.n_units, dtype=torch.int32, device=DEV)
+    ctx.born_charges(_t(s["pos"]), cd.BORN_FD, 1e-3, born, st)
+    ctx.sync()
+    Z = born.cpu().numpy()
+    assert np.all(st.cpu().numpy() == 0)
+    off = s["unit_off"]
+    for u in (0, 1023):
+        a0, a1 = off[u], off[u + 1]
+        c = scc_unit(params, s["species"][a0:a1], s["pos"][a0:a1], tol=1e-12)
+        Zr, _ = born_fd(params, s["species"][a0:a1], s["pos"][a0:a1], h=1e-3, tol=1e-12, dq_center=c["dq"])
+        assert np.max(np.abs(Z[a0:a1] - Zr)) <= 1e-8
+    assert np.max(np.abs(Z.reshape(1024, 24, 3, 3).sum(1))) < 1e-5
+
+
 def test_throughput_tolerance_matches_oracle_within_scc_error(params):
     # the benchmark runs SCC to 1e-8; results stay within the SCC error of the exact fixed point
     s = make_system(2, n_units=8)
