@@ -145,6 +145,38 @@ def test_surrogate_born_matches_oracle_prediction(params):
     assert ctx.read_counters()["surrogate_fallback_units"] == 0
 
 
+def test_surrogate_born_full_size_sampled(params):
+    # 65536 units (about 870k atoms, the surrogate benchmark's shape): the
+    # forward pass runs over hundreds of thousands of atoms per species and
+    # member; sampled units against the oracle's prediction, the acoustic sum
+    # rule at every unit
+    s = make_system(5)
+    _, _, P, N = _random_ensemble(4)
+    nets = [[np.asarray(P[sp, m].cpu().numpy(), dtype=np.float64) for m in range(4)] for sp in (0, 1)]
+    Nh = N.cpu().numpy().astype(np.float64)
+    norms = [{"x_mean": Nh[sp, :32], "x_std": Nh[sp, 32:64], "y_mean": Nh[sp, 64:73], "y_scale": Nh[sp, 73:82]}
+             for sp in (0, 1)]
+    ctx = cd.context_from_system(params, s)
+    ctx.set_scc(1e-12, 300, 0.2)
+    ctx.set_surrogate(P.view(-1), N.view(-1), 1e9)
+    Z = torch.empty(ctx.n_atoms, 9, dtype=torch.float64, device=DEV)
+    std = torch.empty(ctx.n_atoms, dtype=torch.float64, device=DEV)
+    st = torch.zeros(ctx.n_units, dtype=torch.int32, device=DEV)
+    ctx.born_charges(_t(s["pos"]), cd.BORN_SURROGATE, 1e-3, Z, st, std)
+    ctx.sync()
+    Zg = Z.cpu().numpy().reshape(-1, 3, 3)
+    off = s["unit_off"]
+    U = ctx.n_units
+    for u in (0, 12345, 40000, U - 1):
+        a0, a1 = off[u], off[u + 1]
+        q = eval_units(params, s["species"][a0:a1], s["pos"][a0:a1], np.array([0, a1 - a0], dtype=np.int32),
+                       tol=1e-12, want_forces=False)["charges"]
+        zr, _ = osg.predict_unit(s["species"][a0:a1], s["pos"][a0:a1], nets, norms, q, emulate_bf16=True)
+        assert np.max(np.abs(Zg[a0:a1] - zr)) <= 1e-3 * np.max(np.abs(zr))
+    sums = np.add.reduceat(Zg, off[:-1], axis=0)
+    assert np.max(np.abs(sums)) < 1e-11
+
+
 @pytest.mark.parametrize("route,h", [(cd.BORN_FD, 1e-3), (cd.BORN_FIELD, 1e-4)])
 def test_fallback_reproduces_exact_route(params, route, h):
     s = make_system(5, n_units=6)
