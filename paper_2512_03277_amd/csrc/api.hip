@@ -46,6 +46,8 @@ struct Bucket {
   int per_cu_max = 1;   // resident workgroups per CU the scratch was sized for
   int64_t scratch_per_wg = 0;
   int32_t* d_units = nullptr;  // center jobs: unit list
+  int32_t* d_order = nullptr;  // center jobs of MD evaluations: the units by the cost of their last evaluation
+  int32_t* d_order_tmp = nullptr;
   int cjob0 = 0;               // offset of this bucket's center jobs in the center job arrays
   // finite-difference Born jobs
   int n_fd_jobs = 0;
@@ -81,6 +83,7 @@ struct cavdftb_ctx {
   std::vector<int32_t> h_unit_off;
   int32_t* d_unit_off = nullptr;
   int8_t* d_species = nullptr;
+  float* d_cost_scale = nullptr;  // [U] (orbitals / bucket nmax)^3: relative cost of one SCC iteration
   double *d_unit_x = nullptr, *d_omega = nullptr, *d_k = nullptr, *d_theta = nullptr, *d_lam = nullptr;
   int32_t* d_atom_unit = nullptr;
   double *d_mass = nullptr, *d_inv_mass = nullptr;
@@ -292,7 +295,9 @@ int eval_center(cavdftb_ctx* c, const double* pos, bool forces, bool md = false)
       a.ws_dq_hist = c->d_ws_dq_hist;
       a.n_extrap = extrap ? (c->md_hist < 3 ? c->md_hist : 3) : 0;
     }
-    a.job_unit = b.d_units;
+    // MD evaluations take the units in the order of their last cost (largest
+    // first); the job arrays then follow that order
+    a.job_unit = md ? b.d_order : b.d_units;
     a.job_disp = nullptr;
     a.n_jobs = b.n_units;
     a.energy = c->d_energy;
@@ -305,6 +310,11 @@ int eval_center(cavdftb_ctx* c, const double* pos, bool forces, bool md = false)
     a.flags = flags;
     int rc = run_scc(c, b, a);
     if (rc) return rc;
+    if (md && c->dynamic_jobs) {
+      hipError_t e = launch_order_by_cost(b.n_units, b.d_order, a.job_iters, c->d_cost_scale, b.d_order_tmp,
+                                          c->stream);
+      if (e != hipSuccess) return hip_fail(c, e, "job order");
+    }
   }
   c->md_hist = (md && extrap) ? c->md_hist + 1 : (md && c->warm_enabled ? 1 : 0);
   c->warm_valid = c->warm_enabled != 0;
@@ -785,6 +795,7 @@ int cavdftb_create(const cavdftb_params* params, const cavdftb_layout* L, void* 
 
   // ---- buckets: unit lists, scratch, finite-difference job lists
   int cj = 0, fj = 0;
+  std::vector<float> cost_scale(U, 0.0f);
   for (int k = 0; k < kNumBuckets; ++k) {
     if (bunits[k].empty()) continue;
     Bucket b;
@@ -799,6 +810,15 @@ int cavdftb_create(const cavdftb_params* params, const cavdftb_layout* L, void* 
     b.n_wg = n_cu * per_cu;
     CK(dalloc(c, &b.d_units, b.n_units));
     CK(hipMemcpy(b.d_units, bunits[k].data(), b.n_units * sizeof(int32_t), hipMemcpyHostToDevice));
+    for (int u : bunits[k]) {
+      int norb = 0;
+      for (int a = c->h_unit_off[u]; a < c->h_unit_off[u + 1]; ++a) norb += L->species[a] == 0 ? 4 : 1;
+      const double f = (double)norb / b.nmax;
+      cost_scale[u] = (float)(f * f * f);
+    }
+    CK(dalloc(c, &b.d_order, b.n_units));
+    CK(dalloc(c, &b.d_order_tmp, b.n_units));
+    CK(hipMemcpy(b.d_order, bunits[k].data(), b.n_units * sizeof(int32_t), hipMemcpyHostToDevice));
     CK(dalloc(c, &b.d_scratch, (size_t)b.n_wg * b.scratch_per_wg));
     std::vector<int32_t> jun, jdisp, fdu, fdj0;
     for (int u : bunits[k]) {
@@ -860,6 +880,8 @@ int cavdftb_create(const cavdftb_params* params, const cavdftb_layout* L, void* 
     }
     c->buckets.push_back(b);
   }
+  CK(dalloc(c, &c->d_cost_scale, (size_t)U));
+  CK(hipMemcpy(c->d_cost_scale, cost_scale.data(), U * sizeof(float), hipMemcpyHostToDevice));
   c->n_fd_total = fj;
   CK(dalloc(c, &c->d_mu_job, (size_t)fj * 3));
   CK(dalloc(c, &c->d_fjob_status, fj));

@@ -157,6 +157,11 @@ hipError_t launch_rs_observables(int n_units, const int32_t* unit_off, const dou
                                  const double* pk, const double* wk, double eta, double w0, const int32_t* status,
                                  const int32_t* job_iters, double* part, int part_rows, double* obs,
                                  unsigned int* obs_row, hipStream_t s);
+// reorders `order` (n units of a bucket) by the cost of their last evaluation,
+// iters[j] cost_scale[order[j]] with cost_scale[u] = (orbitals / bucket nmax)^3,
+// largest first; tmp: [n] scratch
+hipError_t launch_order_by_cost(int n, int32_t* order, const int32_t* iters, const float* cost_scale, int32_t* tmp,
+                                hipStream_t s);
 // *c = v by a one-thread kernel (a kernel node, not a memset, inside captured graphs)
 hipError_t launch_set_u32(unsigned int* c, unsigned int v, hipStream_t s);
 

@@ -633,6 +633,55 @@ hipError_t launch_observables(int n_units, int n_atoms, int n_modes, const int32
   return hipGetLastError();
 }
 
+// job order of the next MD evaluation of a bucket: the units of `order` sorted by
+// the cost of their last evaluation, iterations x cost_scale = (orbitals / nmax)^3, largest
+// first (longest-processing-time order for the device job queue).  One
+// workgroup: a 256-bin histogram, bin starts, then a scatter by LDS atomics
+// (order within a bin is immaterial: every unit's result is independent of
+// when it runs).
+__global__ __launch_bounds__(1024) void order_by_cost_kernel(int n, const int32_t* __restrict__ order,
+                                                            const int32_t* __restrict__ iters,
+                                                            const float* __restrict__ cost_scale,
+                                                            int32_t* __restrict__ out) {
+  __shared__ int cnt[256];
+  __shared__ int start[256];
+  const int tid = threadIdx.x;
+  for (int b = tid; b < 256; b += 1024) cnt[b] = 0;
+  __syncthreads();
+  auto bin = [&](int j) {
+    const float cost = (float)iters[j] * cost_scale[order[j]];  // iterations at the bucket's nmax orbitals
+    const int k = (int)(cost * 2.5f);
+    return k < 0 ? 0 : (k > 255 ? 255 : k);
+  };
+  for (int j = tid; j < n; j += 1024) atomicAdd(&cnt[bin(j)], 1);
+  __syncthreads();
+  if (tid == 0) {
+    int s = 0;
+    for (int k = 255; k >= 0; --k) {
+      start[k] = s;
+      s += cnt[k];
+    }
+  }
+  __syncthreads();
+  for (int j = tid; j < n; j += 1024) out[atomicAdd(&start[bin(j)], 1)] = order[j];
+}
+
+__global__ __launch_bounds__(kNT) void copy_i32_kernel(int n, const int32_t* __restrict__ src,
+                                                       int32_t* __restrict__ dst) {
+  const int i = blockIdx.x * kNT + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+hipError_t launch_order_by_cost(int n, int32_t* order, const int32_t* iters, const float* cost_scale, int32_t* tmp,
+                                hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(order_by_cost_kernel, dim3(1), dim3(1024), 0, s, n, order, iters, cost_scale, tmp);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(copy_i32_kernel, dim3(nblk(n)), dim3(kNT), 0, s, n, tmp, order);
+  return hipGetLastError();
+}
+
 hipError_t launch_set_u32(unsigned int* c, unsigned int v, hipStream_t s) {
   hipLaunchKernelGGL(set_u32_kernel, dim3(1), dim3(64), 0, s, c, v);
   return hipGetLastError();
