@@ -120,7 +120,7 @@ int cavdftb_create(const cavdftb_params* params, const cavdftb_layout* layout, v
                    cavdftb_ctx** out);
 int cavdftb_destroy(cavdftb_ctx* ctx);
 
-/* SCC controls (defaults tol 1e-8, max_iter 200, mix_alpha 0.5): Johnson's
+/* SCC controls (defaults tol 1e-8, max_iter 200, mix_alpha 0.6): Johnson's
  * modified Broyden mixing of the atomic charges with inverse-Jacobian weight
  * w0 = 0.01 and at most 20 stored iterations; converged when
  * max_A |Dq_out - Dq_in| < tol. */

@@ -44,7 +44,7 @@ def tune(params, system, born_mode=B.BORN_MULLIKEN, h=1e-3, steps=4, warmup=2, t
     for values in itertools.product(*(CANDIDATES[k] for k in keys)):
         setting = dict(zip(keys, values))
         ctx = B.context_from_system(params, system)
-        ctx.set_scc(tol, 200, 0.5)
+        ctx.set_scc(tol, 200, 0.6)
         apply(ctx, setting)
         r = torch.tensor(system["pos"], device=dev)
         p = torch.tensor(system["vel"] * masses[:, None], device=dev)

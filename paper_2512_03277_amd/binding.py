@@ -193,7 +193,7 @@ class Context:
             pass
 
     # ---- entry points (same names as the C ABI without the prefix)
-    def set_scc(self, tol, max_iter=200, mix_alpha=0.5):
+    def set_scc(self, tol, max_iter=200, mix_alpha=0.6):
         self._check(self.lib.cavdftb_set_scc(self.ctx, float(tol), int(max_iter), float(mix_alpha)), "set_scc")
 
     def set_tuning(self, jacobi_res_factor=1e-3, keep_mixer_history=True):

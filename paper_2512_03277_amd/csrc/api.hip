@@ -131,7 +131,7 @@ struct cavdftb_ctx {
   // controls
   double tol = 1e-8;
   int32_t max_iter = 200;
-  double alpha = 0.5;
+  double alpha = 0.6;
   double w0 = 0.01;
   double jac_factor = 1.0e-3;
   int keep_hist = 1;
