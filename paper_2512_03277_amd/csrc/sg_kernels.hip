@@ -21,6 +21,7 @@ constexpr int NIN = CAVDFTB_SG_N_IN, NHID = CAVDFTB_SG_N_HID, NOUT = CAVDFTB_SG_
 constexpr int OFF_W1 = 0, OFF_B1 = OFF_W1 + NIN * NHID, OFF_W2 = OFF_B1 + NHID, OFF_B2 = OFF_W2 + NHID * NHID,
               OFF_W3 = OFF_B2 + NHID, OFF_B3 = OFF_W3 + NHID * NOUT, NPAR = OFF_B3 + NOUT;
 static_assert(NPAR == CAVDFTB_SG_N_PARAM, "parameter layout");
+static_assert(NIN == 32, "descriptors: 16 radial Gaussians for each of the two species");
 constexpr int TILE = 64;  // atoms per workgroup
 constexpr int kForwardGrid = 512;  // persistent workgroups of the forward pass (two fit in a CU's LDS)
 constexpr int NT = 256;
@@ -88,8 +89,14 @@ __global__ __launch_bounds__(NT) void features_kernel(int n_atoms, const int32_t
   const int a0 = unit_off[u], a1 = unit_off[u + 1];
   const double rc = 6.0 * kAng;
   const double r0 = 0.5 * kAng, dr = (6.0 - 0.5) * kAng / 15.0;
-  double g[NIN];
-  for (int k = 0; k < NIN; ++k) g[k] = 0.0;
+  // the 16 Gaussians of each neighbour species in two register arrays indexed
+  // at compile time only (a runtime-indexed array would live in scratch memory)
+  double gO[16], gH[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    gO[k] = 0.0;
+    gH[k] = 0.0;
+  }
   for (int b = a0; b < a1; ++b) {
     if (b == a) continue;
     const double dx = pos[b * 3] - pos[a * 3], dy = pos[b * 3 + 1] - pos[a * 3 + 1], dz = pos[b * 3 + 2] - pos[a * 3 + 2];
@@ -103,14 +110,28 @@ __global__ __launch_bounds__(NT) void features_kernel(int n_atoms, const int32_t
     const double v = (r - r0) / dr;
     double gk = exp(-0.5 * v * v) * fc, ck = exp(v - 0.5);
     constexpr double kInvE = 0.36787944117144233;  // exp(-1)
-    for (int k = 0; k < 16; ++k) {
-      g[s * 16 + k] += gk;
-      gk *= ck;
-      ck *= kInvE;
+    if (s == 0) {
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        gO[k] += gk;
+        gk *= ck;
+        ck *= kInvE;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        gH[k] += gk;
+        gk *= ck;
+        ck *= kInvE;
+      }
     }
   }
   if (feat)
-    for (int k = 0; k < NIN; ++k) feat[(int64_t)a * NIN + k] = g[k];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      feat[(int64_t)a * NIN + k] = gO[k];
+      feat[(int64_t)a * NIN + 16 + k] = gH[k];
+    }
   if (!frames) return;
   double e1[3] = {1, 0, 0}, e2[3] = {0, 1, 0}, e3[3];
   if (species[a] == 0) {
