@@ -74,18 +74,36 @@ def peak(freq, I, lo, hi):
     return float(freq[k] + d * (freq[k + 1] - freq[k]))
 
 
+def centroid(freq, I, lo, hi):
+    """First moment sum(f I) / sum(I) of the spectrum over lo <= freq <= hi (a
+    band position that does not jump between neighbouring maxima of a broad,
+    noisy band the way the largest value can)."""
+    freq = np.asarray(freq)
+    I = np.asarray(I)
+    m = (freq >= lo) & (freq <= hi)
+    if not np.any(m):
+        raise ValueError("no frequencies in the band")
+    w = I[m]
+    return float(np.sum(freq[m] * w) / np.sum(w))
+
+
 def resolution_cm(n_samples, dt):
     """Frequency resolution 2 pi / (T dt) of a run of n_samples steps, in cm^-1."""
     return 2.0 * np.pi / (n_samples * dt) * HARTREE_CM
 
 
-def peak_report(series_a, series_b, dt, lo, hi):
-    """Spectra of two runs recorded from the same start (series [T, K]) and the
-    shift of their largest peak in [lo, hi] cm^-1."""
+def peak_report(series_a, series_b, dt, lo, hi, centroid_halfwidth=250.0):
+    """Spectra of two runs recorded from the same start (series [T, K]), the
+    shift of their largest peak in [lo, hi] cm^-1, and the shift of their band
+    centroids over the same window, centred on run b's peak with the given
+    half width."""
     fa, Ia = spectrum(autocorrelation(series_a), dt)
     fb, Ib = spectrum(autocorrelation(series_b), dt)
     pa, pb = peak(fa, Ia, lo, hi), peak(fb, Ib, lo, hi)
+    wlo, whi = pb - centroid_halfwidth, pb + centroid_halfwidth
+    ca, cb = centroid(fa, Ia, wlo, whi), centroid(fb, Ib, wlo, whi)
     return {"peak_a_cm": pa, "peak_b_cm": pb, "shift_cm": pa - pb,
+            "centroid_a_cm": ca, "centroid_b_cm": cb, "centroid_shift_cm": ca - cb,
             "resolution_cm": resolution_cm(len(series_a), dt)}
 
 

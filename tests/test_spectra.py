@@ -93,7 +93,7 @@ def test_harmonic_polariton_lines_from_an_oracle_trajectory():
         assert spectra.peak(f, I, 500.0, mid) == pytest.approx(lines[0], abs=2.0)
         assert spectra.peak(f, I, mid, 4000.0) == pytest.approx(lines[1], abs=2.0)
     rep = spectra.peak_report(np.array(z)[:, None], np.array(z)[:, None], DT, 500.0, 4000.0)
-    assert rep["shift_cm"] == 0.0
+    assert rep["shift_cm"] == 0.0 and rep["centroid_shift_cm"] == 0.0
 
 
 def test_per_series_spectra_and_top_peaks():
@@ -142,3 +142,17 @@ def test_near_normal_average_resolves_the_polariton_pair_of_an_oracle_run():
     assert np.allclose(lines, exact, atol=0.15 * res)
     with pytest.raises(ValueError):
         spectra.averaged_spectrum(qk, dt, [])
+
+
+def test_centroid_of_a_line_and_of_two_lines():
+    t = np.arange(8000) * DT
+    nu0 = 1650.0
+    f, I = spectra.spectrum(spectra.autocorrelation(np.cos(nu0 / spectra.HARTREE_CM * t)), DT, omega_squared=False)
+    # a symmetric line centred in a symmetric window: the centroid is its centre
+    assert spectra.centroid(f, I, nu0 - 300.0, nu0 + 300.0) == pytest.approx(nu0, abs=1.0)
+    # two equal lines: the centroid lies midway, where neither maximum is
+    x = np.cos(1600.0 / spectra.HARTREE_CM * t) + np.cos(1700.0 / spectra.HARTREE_CM * t)
+    f, I = spectra.spectrum(spectra.autocorrelation(x), DT, omega_squared=False)
+    assert spectra.centroid(f, I, 1350.0, 1950.0) == pytest.approx(1650.0, abs=1.0)
+    with pytest.raises(ValueError):
+        spectra.centroid(f, I, -2.0, -1.0)
