@@ -349,7 +349,7 @@ int cavdftb_step(cavdftb_ctx* ctx, double* r, double* p, double* qm, double* pm,
  * CAVDFTB_BORN_FD_FORWARD, CAVDFTB_BORN_FIELD): with every = k > 1, cavdftb_step
  * recomputes them at the first matter evaluation after priming and then on
  * every k-th one, and reuses the last e . Z in between (the paper refreshes its
- * Born charges every 3 steps, Computational details).  Other modes and
+ * Born charges every 3 steps, Theory, Step 1).  Other modes and
  * cavdftb_born_charges are not affected.  Steps with k > 1 and an exact mode run
  * eagerly (no graph replay).  Returns CAVDFTB_EINVAL for every < 1. */
 int cavdftb_set_born_interval(cavdftb_ctx* ctx, int32_t every);

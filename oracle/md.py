@@ -33,6 +33,7 @@ import numpy as np
 from . import cavity as cav
 from .born import born_fd, born_fd_forward, born_field, born_mulliken
 from .scc import scc_unit
+from .surrogate import predict_unit
 from cavgen.constants import KB
 
 
@@ -43,15 +44,25 @@ class DFTBBackend:
     born="field": central, of the forces in a uniform field, step h in atomic
     units of field).  With born_every = k > 1 the exact Born charges are
     recomputed on every k-th evaluation only (the first included) and reused in
-    between (the paper refreshes them every 3 steps, Computational details)."""
+    between (the paper refreshes them every 3 steps, Theory, Step 1).
 
-    def __init__(self, params, species, unit_off, born="mulliken", tol=1e-12, h=1e-3, max_iter=200, born_every=1):
+    born="surrogate": the learned ensemble's prediction (surrogate.predict_unit
+    with the Mulliken charges of the same SCC), and, for a unit whose largest
+    per-atom, per-component ensemble standard deviation exceeds
+    surrogate["threshold"], the exact route surrogate["fallback"] ("field" or
+    "fd") with step h instead.  surrogate = {"nets", "norms", "threshold",
+    "fallback", "emulate_bf16"} in the form predict_unit takes."""
+
+    def __init__(self, params, species, unit_off, born="mulliken", tol=1e-12, h=1e-3, max_iter=200, born_every=1,
+                 surrogate=None):
         self.params, self.species, self.unit_off = params, np.asarray(species), np.asarray(unit_off)
         self.born, self.tol, self.h, self.max_iter = born, tol, h, max_iter
         self.n_units = len(unit_off) - 1
         self.born_every = int(born_every)
         self.calls = 0
         self.Z_last = None
+        self.surrogate = surrogate
+        self.fallback_units = []
 
     def evaluate(self, r):
         U = self.n_units
@@ -68,17 +79,27 @@ class DFTBBackend:
             out["mu"][u] = res["dipole"]
             out["charges"][a0:a1] = res["charges"]
             refresh = self.calls % self.born_every == 0
-            if self.born in ("fd", "fd_forward", "field") and not refresh:
+            born = self.born
+            if born == "surrogate":
+                sg = self.surrogate
+                Z, sd = predict_unit(sp, r[a0:a1], sg["nets"], sg["norms"], res["charges"],
+                                     emulate_bf16=sg.get("emulate_bf16", False))
+                if float(sd.max()) > sg["threshold"]:
+                    born = sg["fallback"]
+                    self.fallback_units.append((self.calls, u))
+            if born == "surrogate":
+                pass
+            elif self.born in ("fd", "fd_forward", "field") and not refresh:
                 Z = self.Z_last[a0:a1]
-            elif self.born == "fd":
+            elif born == "fd":
                 Z, st = born_fd(self.params, sp, r[a0:a1], h=self.h, tol=self.tol, max_iter=self.max_iter,
                                 dq_center=res["dq"])
                 out["status"][u] |= st
-            elif self.born == "fd_forward":
+            elif born == "fd_forward":
                 Z, st = born_fd_forward(self.params, sp, r[a0:a1], res["dipole"], h=self.h, tol=self.tol,
                                         max_iter=self.max_iter, dq_center=res["dq"])
                 out["status"][u] |= st
-            elif self.born == "field":
+            elif born == "field":
                 Z, st = born_field(self.params, sp, r[a0:a1], e=self.h, tol=self.tol, max_iter=self.max_iter,
                                    dq_center=res["dq"])
                 out["status"][u] |= st

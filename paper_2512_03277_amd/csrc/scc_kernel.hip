@@ -192,17 +192,63 @@ __device__ void pair_band_grad(const DevParams& P, int spA, int spB, const doubl
   for (int k = 0; k < 3; ++k) g[k] += rad * u[k] + gv[k] * ir;
 }
 
-// Elstner gamma and d gamma / dR for distinct sites.
+// Elstner gamma and d gamma / dR for distinct sites: gamma = 1/R - S with
+// S(ta, tb, R) from the Coulomb integral of two exponential densities
+// (tau = 16 U / 5).  The closed form for ta != tb is a removable singularity
+// at ta = tb whose two terms cancel like 1/(ta - tb)^3, so near-equal
+// exponents use its expansion about t = (ta + tb)/2 instead: with
+// y = t R, x = (ta - tb)/(ta + tb),
+//   S     = t   e^{-y} sum_k c_k(y) x^k,     k = 0, 2, ..., 14,
+//   dS/dR = t^2 e^{-y} sum_k (c_k' - c_k)(y) x^k,
+// c_0 = (y^3 + 9y^2 + 33y + 48)/(48y) being the equal-exponent form.  The
+// c_k are polynomials in y (numerators below, ascending powers, over the
+// denominators kGsDen), derived by expanding the closed form in
+// delta = (ta - tb)/2.  For x < 0.1 the truncation error is below 1e-15 of
+// 1/R; above it the closed form loses less than 1e-14 of 1/R.
+__constant__ double kGsNum[7][17] = {
+    {180, 180, 75, 15, 1},
+    {-840, -840, 0, 280, 133, 21, 1},
+    {0, 0, -7560, -7560, -2268, 252, 207, 27, 1},
+    {0, 0, 0, 0, -33264, -33264, -9504, 0, 297, 33, 1},
+    {0, 0, 0, 0, 0, 0, -102960, -102960, -25740, -572, 403, 39, 1},
+    {0, 0, 0, 0, 0, 0, 0, 0, -257400, -257400, -56160, -1560, 525, 45, 1},
+    {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, -556920, -556920, -107100, -3060, 663, 51, 1}};
+__constant__ double kGdNum[7][17] = {
+    {0, -30, -30, -11, -1},
+    {0, 840, 840, 252, -28, -15, -1},
+    {0, -15120, -15120, -1512, 3528, 990, -18, -19, -1},
+    {0, 0, 0, -133056, -133056, -23760, 9504, 2376, 0, -23, -1},
+    {0, 0, 0, 0, 0, -617760, -617760, -102960, 20592, 4602, 26, -27, -1},
+    {0, 0, 0, 0, 0, 0, 0, -2059200, -2059200, -304200, 39000, 7860, 60, -31, -1},
+    {0, 0, 0, 0, 0, 0, 0, 0, 0, -5569200, -5569200, -728280, 67320, 12342, 102, -35, -1}};
+__constant__ double kGsDen[7] = {480.0, 13440.0, 725760.0, 63866880.0, 8302694400.0, 1494484992000.0,
+                                 355687428096000.0};
+constexpr double kGammaSeriesX = 0.1;
+
 __device__ void gamma_pair(double ua, double ub, double r, double& g, double& dg) {
   const double ta = 3.2 * ua, tb = 3.2 * ub;  // 16 U / 5
+  const double x = (ta - tb) / (ta + tb);
   double s, ds;
-  if (fabs(ta - tb) < 1e-10 * fmax(ta, tb)) {
-    const double t = 0.5 * (ta + tb);
-    const double e = exp(-t * r);
+  if (fabs(x) < kGammaSeriesX) {
+    const double t = 0.5 * (ta + tb), y = t * r, e = exp(-y), x2 = x * x;
+    double ss = 0.0, sd = 0.0;  // sum over k >= 2, Horner in x^2 from the top
+    for (int k = 6; k >= 0; --k) {
+      double ps = 0.0, pd = 0.0;
+      for (int j = 16; j >= 0; --j) {
+        ps = fma(ps, y, kGsNum[k][j]);
+        pd = fma(pd, y, kGdNum[k][j]);
+      }
+      ss = fma(ss, x2, ps / kGsDen[k]);
+      sd = fma(sd, x2, pd / kGsDen[k]);
+    }
+    ss *= x2;
+    sd *= x2;
+    // k = 0 in the equal-exponent form
     const double poly = 1.0 / r + 11.0 * t / 16.0 + 3.0 * t * t * r / 16.0 + t * t * t * r * r / 48.0;
-    const double dpoly = -1.0 / (r * r) + 3.0 * t * t / 16.0 + t * t * t * r / 24.0;
-    s = e * poly;
-    ds = -t * s + e * dpoly;
+    const double dpoly = -1.0 / (r * r) - t / r - 0.5 * t * t - 7.0 * t * t * t * r / 48.0 -
+                         t * t * t * t * r * r / 48.0;
+    s = e * (poly + t * ss);
+    ds = e * (dpoly + t * t * sd);
   } else {
     s = 0.0;
     ds = 0.0;

@@ -1,5 +1,6 @@
 """The C-ABI library loads and exports every entry point the header declares
-(CPU only: no compute calls)."""
+(no compute calls).  The checks run on the CPU when the library is built here,
+and again, marked gpu, on the GPU machine, where the built library must exist."""
 import ctypes
 import os
 import re
@@ -22,8 +23,7 @@ def test_header_declares_the_four_hot_path_calls():
         assert n in names
 
 
-@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
-def test_library_exports_every_declared_symbol():
+def _exports():
     lib = ctypes.CDLL(LIB)
     missing = [n for n in declared() if not hasattr(lib, n)]
     assert not missing, missing
@@ -31,17 +31,31 @@ def test_library_exports_every_declared_symbol():
     assert b"gfx950" in lib.cavdftb_version()
 
 
-@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
-def test_binding_covers_the_header():
+def _binding():
     from paper_2512_03277_amd.binding import SYMBOLS
     assert sorted(SYMBOLS) == declared()
 
 
-@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
-def test_invalid_arguments_rejected_without_gpu():
+def _invalid_arguments():
     lib = ctypes.CDLL(LIB)
     lib.cavdftb_create.restype = ctypes.c_int
     out = ctypes.c_void_p()
     assert lib.cavdftb_create(None, None, None, ctypes.byref(out)) == -1
     assert lib.cavdftb_destroy(None) == -1
     assert lib.cavdftb_eval_units(None, None, None, None, None, None, None) == -1
+
+
+CHECKS = [_exports, _binding, _invalid_arguments]
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+@pytest.mark.parametrize("check", CHECKS, ids=lambda f: f.__name__)
+def test_library_abi_on_cpu(check):
+    check()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("check", CHECKS, ids=lambda f: f.__name__)
+def test_library_abi_on_gpu_box(check):
+    assert os.path.exists(LIB), "libcavdftb.so is not built"
+    check()

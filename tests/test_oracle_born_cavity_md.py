@@ -259,3 +259,32 @@ def test_thermal_photon_start_is_boltzmann_about_the_relaxed_start():
     st_cold = md.init_state(be, cavity, r, np.zeros((n_units, 3)), m, np.arange(n_units), photons="thermal", kT=0.0,
                             xi=xi)
     assert np.array_equal(st_cold["q"], st0["q"]) and not np.any(st_cold["pm"])
+
+
+def test_unit_temperature_matches_equipartition():
+    # Momenta drawn here from the Maxwell-Boltzmann distribution at 300 K
+    # (p ~ N(0, m kT) per component, no centre-of-mass correction) for units of
+    # 1, 2 and 5 atoms-of-water sizes.  With the centre-of-mass motion removed
+    # a unit keeps 3 N - 3 quadratic momentum terms, so equipartition gives
+    # <2 KE_rel / ((3N - 3) k_B)> = T exactly.  Counting 3N terms, or keeping the
+    # centre-of-mass motion, biases the mean by a factor (3N-3)/3N or 3N/(3N-3)
+    # (x0.67 / x1.5 for a monomer); the statistical error here is 0.3 %.
+    from cavgen.constants import KB, MASS_AMU
+    rng = np.random.default_rng(2024)
+    T = 300.0
+    for waters, n_units in ((1, 20000), (2, 10000), (5, 4000)):
+        sp = np.tile([0, 1, 1], waters)
+        na = len(sp)
+        unit_off = np.arange(n_units + 1) * na
+        m_unit = np.array(MASS_AMU)[sp] * AMU
+        m = np.tile(m_unit, n_units)
+        p = rng.normal(size=(n_units * na, 3)) * np.sqrt(m * KB * T)[:, None]
+        st = {"p": p, "masses": m, "q": np.zeros(1), "pm": np.zeros(1), "F": np.zeros(1),
+              "ev": {"energy": np.zeros(n_units)}}
+        cavity = md.Cavity(np.ones(1), np.zeros(1), np.zeros(1), np.zeros(1), np.zeros(n_units),
+                           np.array([0.0, 0.0, 1.0]))
+        got = md.observables(st, cavity, unit_off)["temperature"]
+        dof = 3 * na - 3
+        sigma = T * np.sqrt(2.0 / (dof * n_units))
+        assert abs(got - T) < 4.0 * sigma, (waters, got, sigma)
+        assert abs(got - T * dof / (3 * na)) > 10 * sigma and abs(got - T * 3 * na / dof) > 10 * sigma

@@ -128,3 +128,57 @@ def test_gamma_matrix_onsite(params):
     s = make_system(1, n_units=1)
     G = gamma_matrix(params, s["species"], s["pos"])
     assert G[0, 0] == 0.5 and G[1, 1] == 0.42 and np.array_equal(G, G.T)
+
+
+def _gamma_fourier(ua, ub, r):
+    """Coulomb integral of two normalised exponential densities
+    rho(x) = tau^3 e^{-tau |x|} / (8 pi) by quadrature in Fourier space:
+    rho^(k) = (1 + k^2/tau^2)^-2 and
+      gamma(R)    = (2/pi) int_0^inf rho_a^ rho_b^ sin(kR)/(kR) dk,
+      dgamma/dR   = (2/pi) int_0^inf rho_a^ rho_b^ [cos(kR)/R - sin(kR)/(k R^2)] dk,
+    Gauss-Legendre (40 nodes) on panels no wider than 0.5 and pi/R, up to
+    k = 200 (the integrand falls as k^-9; the tail is below 1e-17)."""
+    ta, tb = tau_of(ua), tau_of(ub)
+    w = min(0.5, math.pi / r)
+    edges = np.arange(0.0, 200.0 + w, w)
+    x, wt = np.polynomial.legendre.leggauss(40)
+    half = 0.5 * np.diff(edges)
+    k = (0.5 * (edges[1:] + edges[:-1]))[:, None] + half[:, None] * x[None, :]
+    wk = half[:, None] * wt[None, :]
+    f = (1.0 + k * k / (ta * ta)) ** -2 * (1.0 + k * k / (tb * tb)) ** -2
+    kr = k * r
+    g = 2.0 / math.pi * np.sum(wk * f * np.sin(kr) / kr)
+    dg = 2.0 / math.pi * np.sum(wk * f * (np.cos(kr) / r - np.sin(kr) / (kr * r)))
+    return g, dg
+
+
+@pytest.mark.parametrize("pair", [(0.5, 0.5), (0.5, 0.42), (0.42, 0.42), (0.5, 0.5 * (1 + 1e-6)),
+                                  (0.5, 0.5 * (1 + 2e-7)), (0.5, 0.5 * (1 + 1e-3)), (0.3, 0.9)])
+@pytest.mark.parametrize("r", [0.3, 1.0, 2.0, 4.0])
+def test_gamma_against_fourier_quadrature(pair, r):
+    # fixes the whole curve at finite R, not only its limits: a wrong term of
+    # either closed form, or cancellation at near-equal exponents, fails here
+    g, dg = gamma_r(pair[0], pair[1], r)
+    gq, dgq = _gamma_fourier(pair[0], pair[1], r)
+    assert abs(g - gq) <= 2e-13 and abs(dg - dgq) <= 2e-13, (g, gq, dg, dgq)
+
+
+@pytest.mark.parametrize("x_switch", [1e-9, 0.15])
+@pytest.mark.parametrize("r", [0.7, 1.9, 3.6])
+def test_gamma_continuous_across_branch_switches(x_switch, r):
+    # exponents ta = t (1 + x), tb = t (1 - x) just below and just above each
+    # switch of the evaluation (x -+ 1e-12 x): the jump between the two sides
+    # equals the change along the curve (slope from a wide central difference
+    # on one side) to rounding
+    t = 1.4
+
+    def g_at(x):
+        return gamma_r(t * (1 + x) * 5 / 16, t * (1 - x) * 5 / 16, r)
+
+    lo, hi = g_at(x_switch * (1 - 1e-12)), g_at(x_switch * (1 + 1e-12))
+    dx = 2e-12 * x_switch
+    for c in (0, 1):
+        slope = (g_at(x_switch * 1.02)[c] - g_at(x_switch * 1.01)[c]) / (0.01 * x_switch)
+        assert abs(hi[c] - lo[c] - slope * dx) <= 1e-14, (c, hi[c] - lo[c], slope * dx)
+    gq, dgq = _gamma_fourier(t * (1 + x_switch) * 5 / 16, t * (1 - x_switch) * 5 / 16, r)
+    assert abs(hi[0] - gq) <= 2e-13 and abs(hi[1] - dgq) <= 2e-13
