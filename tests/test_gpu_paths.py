@@ -171,11 +171,14 @@ def test_md_ten_steps_mulliken_parity(params, which):
 
 
 def test_md_two_steps_central_fd_eight_water_parity(params):
+    # the photon variables follow the unit dipoles, whose bar is the charge bar
+    # carried through mu = sum Q R: 1e-10 e x sum_A |R_A| (about 2e-8 a.u. for 24
+    # atoms) on |mu| of order 0.5 a.u., so q_m and p_m get 1e-7 relative
     s = make_system(2, n_units=2)
     (r, p, qm, pm, _), _ = _gpu_md(params, s, cd.BORN_FD, 2, graph=False)
     st, _, _ = _oracle_md(params, s, "fd", 2)
     assert _rel(r, st["r"]) <= 1e-9 and _rel(p, st["p"]) <= 1e-8
-    assert _rel(qm, st["q"]) <= 1e-8 and _rel(pm, st["pm"]) <= 1e-8
+    assert _rel(qm, st["q"]) <= 1e-7 and _rel(pm, st["pm"]) <= 1e-7
 
 
 def _ensemble(seed):
@@ -300,8 +303,12 @@ def test_uneven_workload_full_shape_sampled(params):
         r = scc_unit(params, s["species"][a0:a1], s["pos"][a0:a1], tol=1e-12, max_iter=300)
         assert r["status"] == 0
         unit_parity(g, r, u, a0, a1)
+    # neutrality and zero net force: the sum of N_a charges each within the
+    # 1e-10 e bar, the sum of N_a forces each within 1e-9 max|F|
+    na = np.diff(off)
     q = np.add.reduceat(g["charges"], off[:-1])
-    F = np.add.reduceat(g["forces"], off[:-1], axis=0)
-    assert np.max(np.abs(q[ok])) < 1e-10
-    assert np.max(np.abs(F[ok])) < 1e-9
+    F = np.abs(np.add.reduceat(g["forces"], off[:-1], axis=0)).max(1)
+    fmax = np.maximum.reduceat(np.abs(g["forces"]).max(1), off[:-1])
+    assert np.all(np.abs(q[ok]) <= 1e-10 * na[ok]), np.max(np.abs(q[ok]) / na[ok])
+    assert np.all(F[ok] <= 1e-9 * na[ok] * fmax[ok])
     ctx.close()
