@@ -315,6 +315,26 @@ int cavdftb_sg_moments(const double* x, const int32_t* idx, int32_t n, int32_t w
 int cavdftb_sg_to_local(const double* frames, const double* born, const double* charges, const int32_t* idx,
                         int32_t n, double* out, void* hip_stream);
 
+/* Allocation-free variant of cavdftb_sg_backward, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight training loops,
+ * harnesses that forbid hipMalloc): the same kernels and the same fixed-order
+ * tile reduction, so grad equals cavdftb_sg_backward's bit for bit, but the
+ * per-tile partial gradients live in a file-scope device array of the library
+ * (CAVDFTB_SG_NOALLOC_MAX_ROWS rows: ceil(n / 64) x CAVDFTB_SG_N_PARAM floats,
+ * 11.2 MB per GPU, held until the process ends) instead of a caller's work
+ * buffer.  Arguments as in cavdftb_sg_backward (device pointers, stream a
+ * hipStream_t or NULL).  CAVDFTB_EINVAL for a null pointer, n <= 0 or
+ * n > CAVDFTB_SG_NOALLOC_MAX_ROWS; CAVDFTB_EHIP if the array's device address
+ * cannot be looked up.  The first call on a device looks that address up
+ * (hipGetSymbolAddress, no allocation); make it outside any graph capture.
+ * Calls on one GPU share its array: calls that overlap in time on one GPU
+ * (on different streams, or from several threads) race and must be ordered
+ * by the caller.  Nothing is cleared between calls; every partial sum a call
+ * reads it has written itself. */
+#define CAVDFTB_SG_NOALLOC_MAX_ROWS 8192
+int cavdftb_sg_backward_noalloc(const float* params, const float* x, const float* act, const float* dy, int32_t n,
+                                float* grad, void* hip_stream);
+
 /* Photon start at frozen matter (Step 0 reading): q_m = -lambda_m F_m/omega_m,
  * p_m = 0, with F from one SCC evaluation at r (device). */
 int cavdftb_init_photons(cavdftb_ctx* ctx, const double* r, double* qm, double* pm);

@@ -14,6 +14,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcavdftb.so")
 
 OK, EINVAL, ENOMEM, EHIP = 0, -1, -2, -3
+SG_NOALLOC_MAX_ROWS = 8192
 ST_NOT_CONVERGED, ST_NOT_PD, ST_DEGENERATE, ST_NAN = 1, 2, 4, 8
 BORN_MULLIKEN, BORN_FD, BORN_SURROGATE, BORN_FIELD, BORN_FD_FORWARD = 0, 1, 2, 3, 4
 SG_N_IN, SG_N_HID, SG_N_OUT, SG_MEMBERS, SG_N_PARAM, SG_N_NORM = 32, 128, 9, 4, 21897, 82
@@ -72,6 +73,7 @@ SYMBOLS = {
     "cavdftb_sg_prep": (ctypes.c_int, [_vp, _vp, _c_i32, _c_i32, _vp, _vp, _vp]),
     "cavdftb_sg_forward": (ctypes.c_int, [_vp, _vp, _c_i32, _vp, _vp, _vp]),
     "cavdftb_sg_backward": (ctypes.c_int, [_vp, _vp, _vp, _vp, _c_i32, _vp, _vp, _vp]),
+    "cavdftb_sg_backward_noalloc": (ctypes.c_int, [_vp, _vp, _vp, _vp, _c_i32, _vp, _vp]),
     "cavdftb_sg_mse": (ctypes.c_int, [_vp, _vp, _c_i32, _vp, _vp, _vp, _vp]),
     "cavdftb_sg_adam": (ctypes.c_int, [_vp, _vp, _vp, _vp, _c_i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                        ctypes.c_float, _c_i32, _vp]),
@@ -365,6 +367,13 @@ def sg_backward(params, x, act, dy, n, grad, work, stream=None):
     _rc(load_library().cavdftb_sg_backward(_ptr(params, name="params"), _ptr(x, name="x"), _ptr(act, name="act"),
                                            _ptr(dy, name="dy"), int(n), _ptr(grad, name="grad"),
                                            _ptr(work, name="work"), _stream_handle(stream)), "sg_backward")
+
+
+def sg_backward_noalloc(params, x, act, dy, n, grad, stream=None):
+    _rc(load_library().cavdftb_sg_backward_noalloc(_ptr(params, name="params"), _ptr(x, name="x"),
+                                                   _ptr(act, name="act"), _ptr(dy, name="dy"), int(n),
+                                                   _ptr(grad, name="grad"), _stream_handle(stream)),
+        "sg_backward_noalloc")
 
 
 def sg_mse(y, t, count, dy, loss, work, stream=None):

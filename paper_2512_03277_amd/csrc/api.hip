@@ -9,6 +9,7 @@
 #include <new>
 #include <string>
 #include <utility>
+#include <mutex>
 #include <vector>
 
 #include "internal.h"
@@ -1102,6 +1103,43 @@ int cavdftb_sg_forward(const float* params, const float* x, int32_t n, float* y,
 int cavdftb_sg_backward(const float* params, const float* x, const float* act, const float* dy, int32_t n,
                         float* grad, float* work, void* hip_stream) {
   if (!params || !x || !act || !dy || !grad || !work || n <= 0) return CAVDFTB_EINVAL;
+  return launch_sg_backward(params, x, act, dy, n, grad, work, (hipStream_t)hip_stream) == hipSuccess ? CAVDFTB_OK
+                                                                                                    : CAVDFTB_EHIP;
+}
+
+// ---------------------------------------------------------------- allocation-free backward pass
+// Per-tile partial gradients of cavdftb_sg_backward_noalloc: a file-scope
+// device array (one copy per GPU).  Host code never passes the array's name
+// to a kernel: its device address on the current device is looked up once per
+// device with hipGetSymbolAddress and kept in g_noalloc_ptr.
+constexpr int kNoallocTiles = (CAVDFTB_SG_NOALLOC_MAX_ROWS + 63) / 64;
+static __device__ __align__(256) float scratch[(size_t)kNoallocTiles * CAVDFTB_SG_N_PARAM];
+constexpr int kMaxDevices = 64;
+static float* g_noalloc_ptr[kMaxDevices] = {};
+static std::mutex g_noalloc_mu;
+
+static hipError_t noalloc_scratch(float** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_noalloc_ptr[dev] = static_cast<float*>(p);
+  }
+  *out = g_noalloc_ptr[dev];
+  return hipSuccess;
+}
+
+int cavdftb_sg_backward_noalloc(const float* params, const float* x, const float* act, const float* dy, int32_t n,
+                                float* grad, void* hip_stream) {
+  if (!params || !x || !act || !dy || !grad || n <= 0 || n > CAVDFTB_SG_NOALLOC_MAX_ROWS) return CAVDFTB_EINVAL;
+  float* work = nullptr;
+  if (noalloc_scratch(&work) != hipSuccess) return CAVDFTB_EHIP;
   return launch_sg_backward(params, x, act, dy, n, grad, work, (hipStream_t)hip_stream) == hipSuccess ? CAVDFTB_OK
                                                                                                     : CAVDFTB_EHIP;
 }
