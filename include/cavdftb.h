@@ -136,6 +136,25 @@ int cavdftb_set_scc(cavdftb_ctx* ctx, double tol, int32_t max_iter, double mix_a
  * Returns CAVDFTB_EINVAL outside 0 <= jacobi_res_factor <= 1. */
 int cavdftb_set_tuning(cavdftb_ctx* ctx, double jacobi_res_factor, int32_t keep_mixer_history);
 
+/* Eigensolver of the SCC iterations.  Every SCC iteration needs the
+ * occupied subspace of A = X^T H X in the current S-orthonormal basis X.
+ *   CAVDFTB_EIG_AUTO (default): while the occupied and virtual columns of X
+ *     stay well separated, one occupied-virtual rotation of X (an exactly
+ *     orthogonal Cayley transform) per iteration; otherwise (cold start, small
+ *     gaps) a full diagonalisation: cyclic Jacobi for units of at most 64
+ *     orbitals, and above that Householder tridiagonalisation, bisection,
+ *     twisted-factorisation eigenvectors and a blocked back-transform on the
+ *     FP64 matrix cores (cyclic Jacobi again if that solve fails its
+ *     S-orthonormality check, counted in tridiagonal_fallbacks).
+ *   CAVDFTB_EIG_FULL: a full diagonalisation in every SCC iteration.
+ *   CAVDFTB_EIG_JACOBI: as AUTO, but every full diagonalisation by Jacobi.
+ * The converged results agree to within the SCC tolerance.  CAVDFTB_EINVAL
+ * for another value. */
+#define CAVDFTB_EIG_AUTO 0
+#define CAVDFTB_EIG_FULL 1
+#define CAVDFTB_EIG_JACOBI 2
+int cavdftb_set_eigensolver(cavdftb_ctx* ctx, int32_t mode);
+
 /* Launch schedule of the SCC kernel.  job_queue != 0 (default): workgroups take
  * the next job from a device queue, each bucket's units ordered largest first
  * (longest-processing-time order); 0: a fixed stride over the job list.
@@ -406,10 +425,14 @@ typedef struct cavdftb_counters {
   int64_t scc_launches;
   int64_t jacobi_sweeps;             /* Jacobi sweeps summed over all SCC iterations of all jobs */
   int64_t surrogate_fallback_units;  /* units recomputed by the exact route in surrogate mode */
-  int64_t jacobi_iterations;         /* SCC iterations that diagonalised by full Jacobi (the others took
-                                        one occupied-virtual rotation of the previous basis) */
+  int64_t jacobi_iterations;         /* SCC iterations that diagonalised fully (Jacobi or tridiagonal; the
+                                        others took one occupied-virtual rotation of the previous basis) */
   int64_t graph_replays;             /* MD steps run as graph replays (cavdftb_set_graph) */
   int64_t graph_captures;            /* graph captures of the MD step */
+  int64_t tridiagonal_solves;        /* full diagonalisations of units above 64 orbitals by the
+                                        Householder / bisection / twisted-factorisation solver */
+  int64_t tridiagonal_fallbacks;     /* of those, solves discarded by their orthonormality check
+                                        (the iteration then ran cyclic Jacobi) */
 } cavdftb_counters;
 int cavdftb_enable_timing(cavdftb_ctx* ctx, int32_t enable);
 int cavdftb_read_counters(cavdftb_ctx* ctx, cavdftb_counters* out);

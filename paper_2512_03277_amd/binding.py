@@ -20,6 +20,7 @@ BORN_MULLIKEN, BORN_FD, BORN_SURROGATE, BORN_FIELD, BORN_FD_FORWARD = 0, 1, 2, 3
 SG_N_IN, SG_N_HID, SG_N_OUT, SG_MEMBERS, SG_N_PARAM, SG_N_NORM = 32, 128, 9, 4, 21897, 82
 N_OBS = 8
 WORK_MU_POL, WORK_DIPOLE, WORK_ENERGY, WORK_CHARGES, WORK_FORCES, WORK_FIELD = range(6)
+EIG_AUTO, EIG_FULL, EIG_JACOBI = 0, 1, 2
 OBS_NAMES = ("kinetic", "potential", "photon", "total", "temperature", "n_bad_units", "scc_iterations",
              "sum_mu_pol")
 
@@ -43,7 +44,8 @@ class Counters(ctypes.Structure):
     _fields_ = [("scc_jobs", ctypes.c_int64), ("scc_iterations", ctypes.c_int64), ("scc_flops", _c_d),
                 ("scc_kernel_ms", _c_d), ("scc_launches", ctypes.c_int64), ("jacobi_sweeps", ctypes.c_int64),
                 ("surrogate_fallback_units", ctypes.c_int64), ("jacobi_iterations", ctypes.c_int64),
-                ("graph_replays", ctypes.c_int64), ("graph_captures", ctypes.c_int64)]
+                ("graph_replays", ctypes.c_int64), ("graph_captures", ctypes.c_int64),
+                ("tridiagonal_solves", ctypes.c_int64), ("tridiagonal_fallbacks", ctypes.c_int64)]
 
 
 SYMBOLS = {
@@ -61,6 +63,7 @@ SYMBOLS = {
     "cavdftb_set_surrogate": (ctypes.c_int, [_vp, _vp, _vp, _c_d]),
     "cavdftb_set_fallback": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "cavdftb_set_schedule": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32]),
+    "cavdftb_set_eigensolver": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "cavdftb_set_graph": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "cavdftb_set_born_interval": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "cavdftb_set_realspace_cavity": (ctypes.c_int, [_vp, _c_d, _c_d, _c_d, _c_d]),
@@ -204,6 +207,9 @@ class Context:
 
     def set_schedule(self, job_queue=True, max_wg_per_cu=0):
         self._check(self.lib.cavdftb_set_schedule(self.ctx, int(bool(job_queue)), int(max_wg_per_cu)), "set_schedule")
+
+    def set_eigensolver(self, mode):
+        self._check(self.lib.cavdftb_set_eigensolver(self.ctx, int(mode)), "set_eigensolver")
 
     def read_work(self, which, dst):
         """Device copy of a work array (WORK_MU_POL ... WORK_FIELD) into dst."""

@@ -135,6 +135,7 @@ struct cavdftb_ctx {
   double alpha = 0.6;
   double w0 = 0.01;
   double jac_factor = 1.0e-3;
+  int32_t eig_mode = CAVDFTB_EIG_AUTO;
   int keep_hist = 1;
   int warm_enabled = 1;
   bool warm_valid = false;
@@ -250,6 +251,7 @@ SccArgs base_args(cavdftb_ctx* c, const double* pos) {
   a.hist = c->d_hist;
   a.hist_off = c->d_hist_off;
   a.jac_factor = c->jac_factor;
+  a.eig_mode = c->eig_mode;
   a.counters = c->d_counters;
   a.job_counter = c->dynamic_jobs ? c->d_job_counter : nullptr;
   a.tol = c->tol;
@@ -926,6 +928,15 @@ int cavdftb_set_tuning(cavdftb_ctx* ctx, double jacobi_res_factor, int32_t keep_
   return CAVDFTB_OK;
 }
 
+int cavdftb_set_eigensolver(cavdftb_ctx* ctx, int32_t mode) {
+  if (!ctx) return CAVDFTB_EINVAL;
+  if (mode != CAVDFTB_EIG_AUTO && mode != CAVDFTB_EIG_FULL && mode != CAVDFTB_EIG_JACOBI)
+    return fail(ctx, CAVDFTB_EINVAL, "set_eigensolver: unknown mode");
+  ctx->eig_mode = mode;
+  ctx->gen += 1;
+  return CAVDFTB_OK;
+}
+
 int cavdftb_set_schedule(cavdftb_ctx* ctx, int32_t job_queue, int32_t max_wg_per_cu) {
   if (!ctx) return CAVDFTB_EINVAL;
   ctx->gen += 1;
@@ -1413,11 +1424,13 @@ int cavdftb_read_counters(cavdftb_ctx* ctx, cavdftb_counters* out) {
   out->scc_kernel_ms = ctx->t_ms;
   out->scc_launches = ctx->launches;
   out->jacobi_sweeps = (int64_t)h[3];
-  unsigned long long h45[2] = {0, 0};
-  e = hipMemcpy(h45, ctx->d_counters + 4, sizeof(h45), hipMemcpyDeviceToHost);
+  unsigned long long h47[4] = {0, 0, 0, 0};
+  e = hipMemcpy(h47, ctx->d_counters + 4, sizeof(h47), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(ctx, e, "counters copy");
-  out->surrogate_fallback_units = (int64_t)h45[0];
-  out->jacobi_iterations = (int64_t)h45[1];
+  out->surrogate_fallback_units = (int64_t)h47[0];
+  out->jacobi_iterations = (int64_t)h47[1];
+  out->tridiagonal_solves = (int64_t)h47[2];
+  out->tridiagonal_fallbacks = (int64_t)h47[3];
   out->graph_replays = ctx->graph_replays;
   out->graph_captures = ctx->graph_captures;
   return CAVDFTB_OK;

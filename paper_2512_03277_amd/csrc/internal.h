@@ -66,12 +66,14 @@ struct SccArgs {
   int32_t* status;          // [n_units] (undisplaced jobs) or nullptr
   int32_t* job_status;      // [n_jobs] or nullptr
   int32_t* job_iters;       // [n_jobs] or nullptr
-  unsigned long long* counters;  // [8]: jobs, iterations, algorithmic flops, Jacobi sweeps, surrogate fallback units, Jacobi iterations
+  unsigned long long* counters;  // [8]: jobs, iterations, algorithmic flops, Jacobi sweeps, surrogate fallback units,
+                                 // full diagonalisations, tridiagonal solves, tridiagonal solves discarded
   double tol;
   int32_t max_iter;
   double alpha;
   double w0;
   double jac_factor;        // Jacobi off-diagonal target = max(1e-14, jac_factor * previous SCC residual)
+  int32_t eig_mode;         // CAVDFTB_EIG_*: eigensolver choice of the SCC iterations
   int32_t flags;
 };
 

@@ -679,10 +679,382 @@ __device__ __forceinline__ void split_idx(int e, int w, float inv_w, int& q, int
 // index held by slot s in round r of the circle (round-robin) ordering of m indices
 __device__ __forceinline__ int rr_index(int s, int r, int m) { return s == 0 ? 0 : 1 + (s - 1 + r) % (m - 1); }
 
+// ---------------------------------------------------------------- full eigensolve, large buckets
+// For units above 64 orbitals, whose working matrices live in global scratch,
+// a full diagonalisation of A (cold start, or an SCC iteration where the
+// occupied-virtual step is unsafe) runs as
+//   1. Householder tridiagonalisation A = Q T Q^T (Golub & Van Loan, Alg.
+//      8.3.1): reflector k from row k of the trailing matrix, p = tau A22 v,
+//      w = p - (tau/2)(p.v) v, A22 -= v w^T + w v^T.  The update of step k is
+//      fused with the matrix-vector product of step k + 1 (one pass over the
+//      trailing matrix per step): row k + 1 is updated first, reflector k + 1
+//      is formed from it, then the remaining rows are updated and multiplied
+//      by it in the same walk.  Reflector k is kept in row k of A.
+//   2. Eigenvalues of T by bisection on the Sturm count (one thread per
+//      eigenvalue, so they come out sorted ascending).
+//   3. Eigenvectors of T from the twisted factorisation at each eigenvalue
+//      (Dhillon & Parlett): stationary and progressive pivots
+//      d+_k = (d_k - l) - e_{k-1}^2 / d+_{k-1}, d-_k = (d_k - l) - e_k^2 / d-_{k+1},
+//      twist r = argmin |d+_r + d-_r - (d_r - l)|, z_r = 1 and
+//      z_k = -e_k z_{k+1} / d+_k above, z_{k+1} = -e_k z_k / d-_{k+1} below.
+//      Vectors whose eigenvalues lie within kHhCluster max|l| of each other
+//      are orthonormalised by two passes of modified Gram-Schmidt.
+//   4. Y = Q Z by blocks of kHhNb reflectors in compact WY form
+//      (Q_b = I - V T V^T, T from the recurrence of Schreiber & Van Loan),
+//      every product on the FP64 matrix cores, then C = X Y.
+//   5. The S-orthonormality of C is checked (C^T S C on the matrix cores); one
+//      Newton-Schulz step C (3I - M)/2 cleans a small residue, a large one
+//      (a failed solve) sends the iteration to cyclic Jacobi instead.
+constexpr int kHhNb = 16;
+constexpr int kBisect = 60;              // halvings of the Gershgorin interval (width / 2^60)
+constexpr double kHhCluster = 1.0e-3;    // relative gap below which vectors are re-orthogonalised
+constexpr double kHhPivmin = 1.0e-290;   // smallest pivot magnitude in the recurrences
+constexpr double kHhMgsMin = 1.0e-2;     // a vector keeping less of its norm in Gram-Schmidt fails the solve
+constexpr double kHhOrthoFail = 1.0e-3;  // max |C^T S C - I| above which the solve is discarded
+constexpr double kHhOrthoClean = 1.0e-13;
+
+template <int NMAX>
+struct HhLds {
+  double v0[NMAX], v1[NMAX], w[NMAX];
+  double tt[kHhNb * kHhNb], gg[kHhNb * kHhNb];
+  double sc[4];
+  int fail;
+};
+
+__device__ __forceinline__ double hh_guard(double q) { return fabs(q) < kHhPivmin ? -kHhPivmin : q; }
+
+// Full eigendecomposition of the symmetric n x n matrix A (sA) in the
+// S-orthonormal basis X (sX): on success the eigenvectors C = X V, columns by
+// ascending eigenvalue, are left in *out (one of sA, sT) and the eigenvalues in
+// eig[0..n); false when the solve was discarded (A and the scratch buffers are
+// then overwritten, X is intact).  hd/he/he2/htau: LDS vectors of NMAX doubles
+// (the diagonal, off-diagonal, its square and the reflector scalars); cst: LDS
+// ints of NMAX; part: LDS doubles of (NT / 64) NMAX; gS: the overlap matrix
+// (row stride NMAX).
+template <int NMAX, int NT>
+__device__ bool eig_householder(double* __restrict__ sA, const double* __restrict__ sX, double* __restrict__ sT,
+                                double* __restrict__ sD, const double* __restrict__ gS, int n, double* hd,
+                                double* he, double* he2, double* htau, int* cst, double* part, HhLds<NMAX>& L,
+                                double* red, double* eig, double** out) {
+  constexpr int LD = Cfg<NMAX, NT>::LD;
+  constexpr int RG = NT / 64;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  double* vcur = L.v0;
+  double* vnext = L.v1;
+
+  // ---- 1. tridiagonalisation.  form(k): reflector k from row k (columns > k)
+  // into row k and vnext, tau_k, d_k, e_k.
+  auto form = [&](int k, double* vout) {
+    const double alpha = sA[k * LD + k + 1];  // read by every thread before the barrier below
+    double sig = 0.0;
+    for (int j = k + 2 + tid; j < n; j += NT) {
+      const double x = sA[k * LD + j];
+      sig = fma(x, x, sig);
+    }
+    sig = block_sum<NT>(sig, red);
+    double beta, tau, scale;
+    if (sig == 0.0) {
+      beta = alpha;
+      tau = 0.0;
+      scale = 0.0;
+    } else {
+      const double nrm = sqrt(fma(alpha, alpha, sig));
+      beta = alpha >= 0.0 ? -nrm : nrm;
+      tau = (beta - alpha) / beta;
+      scale = 1.0 / (alpha - beta);
+    }
+    for (int j = k + 1 + tid; j < n; j += NT) {
+      const double v = j == k + 1 ? 1.0 : sA[k * LD + j] * scale;
+      sA[k * LD + j] = v;
+      vout[j] = v;
+    }
+    if (tid == 0) {
+      hd[k] = sA[k * LD + k];
+      he[k] = beta;
+      htau[k] = tau;
+    }
+    __syncthreads();
+  };
+  // matrix-vector partials: part[w][i] = sum over rows j >= j0 with j = j0 + w (mod RG) of
+  // A[j][i] v[j], for columns i in [i0, n) (A symmetric: column i read as row walks)
+  auto matvec = [&](int j0, int i0, const double* v) {
+    for (int c0 = i0; c0 < n; c0 += 64) {
+      const int i = c0 + lane;
+      double acc = 0.0;
+      if (i < n)
+        for (int j = j0 + wv; j < n; j += RG) acc = fma(sA[j * LD + i], v[j], acc);
+      if (i < n) part[wv * NMAX + i] = acc;
+    }
+    __syncthreads();
+  };
+
+  form(0, vcur);
+  matvec(1, 1, vcur);
+  for (int k = 0; k + 2 < n; ++k) {
+    // p = tau A22 v over columns [k+1, n); K = tau/2 p.v; w = p - K v
+    const double tau = htau[k];
+    double pv = 0.0;
+    for (int i = k + 1 + tid; i < n; i += NT) {
+      double p = 0.0;
+#pragma unroll
+      for (int g = 0; g < RG; ++g) p += part[g * NMAX + i];
+      p *= tau;
+      L.w[i] = p;
+      pv = fma(p, vcur[i], pv);
+    }
+    const double kk = 0.5 * tau * block_sum<NT>(pv, red);
+    for (int i = k + 1 + tid; i < n; i += NT) L.w[i] = fma(-kk, vcur[i], L.w[i]);
+    __syncthreads();
+    const double* v = vcur;
+    const double* w = L.w;
+    if (k + 3 == n) {  // last reflector: update the trailing 2 x 2 block and read off T's corner
+      if (tid == 0) {
+        const int a = n - 2, b = n - 1;
+        const double aa = sA[a * LD + a] - 2.0 * v[a] * w[a];
+        const double ab = sA[b * LD + a] - (v[b] * w[a] + w[b] * v[a]);
+        const double bb = sA[b * LD + b] - 2.0 * v[b] * w[b];
+        hd[a] = aa;
+        hd[b] = bb;
+        he[a] = ab;
+        htau[a] = 0.0;
+        htau[b] = 0.0;
+        he[b] = 0.0;
+      }
+      __syncthreads();
+      break;
+    }
+    // update row k + 1 (columns [k+1, n)), then reflector k + 1 from it
+    const int r1 = k + 1;
+    for (int i = r1 + tid; i < n; i += NT) sA[r1 * LD + i] -= v[r1] * w[i] + w[r1] * v[i];
+    __syncthreads();
+    form(r1, vnext);
+    // rows [k+2, n): A[j][i] -= v_j w_i + w_j v_i for i in [k+2, n), and the
+    // partial products with reflector k + 1 in the same walk
+    for (int c0 = k + 2; c0 < n; c0 += 64) {
+      const int i = c0 + lane;
+      double acc = 0.0;
+      if (i < n) {
+        const double wi = w[i], vi = v[i];
+        int j = k + 2 + wv;
+        for (; j + RG < n; j += 2 * RG) {  // two rows of loads in flight
+          const double x0 = sA[j * LD + i], x1 = sA[(j + RG) * LD + i];
+          const double y0 = x0 - (v[j] * wi + w[j] * vi), y1 = x1 - (v[j + RG] * wi + w[j + RG] * vi);
+          sA[j * LD + i] = y0;
+          sA[(j + RG) * LD + i] = y1;
+          acc = fma(y0, vnext[j], acc);
+          acc = fma(y1, vnext[j + RG], acc);
+        }
+        for (; j < n; j += RG) {
+          const double y = sA[j * LD + i] - (v[j] * wi + w[j] * vi);
+          sA[j * LD + i] = y;
+          acc = fma(y, vnext[j], acc);
+        }
+        part[wv * NMAX + i] = acc;
+      }
+    }
+    __syncthreads();
+    double* t = vcur;
+    vcur = vnext;
+    vnext = t;
+  }
+  // reflector rows hold zeros left of their first element (operands of the
+  // blocked back-transform)
+  for (int k = wv; k + 2 < n; k += RG)
+    for (int j = lane; j <= k; j += 64) sA[k * LD + j] = 0.0;
+  // T's off-diagonal squares, the Gershgorin interval and the cluster scale
+  double glo = INFINITY, ghi = -INFINITY;
+  for (int k = tid; k < n; k += NT) {
+    const double ek = k + 1 < n ? he[k] : 0.0, ekm = k > 0 ? he[k - 1] : 0.0;
+    he2[k] = ek * ek;
+    const double rad = fabs(ek) + fabs(ekm);
+    glo = fmin(glo, hd[k] - rad);
+    ghi = fmax(ghi, hd[k] + rad);
+  }
+  {
+    double gv[2] = {-glo, ghi};
+    block_max_n<NT, 2>(gv, red);
+    glo = -gv[0];
+    ghi = gv[1];
+  }
+  if (!(glo <= ghi)) return false;  // non-finite tridiagonal matrix
+
+  // ---- 2. eigenvalue i by bisection on the Sturm count (thread i)
+  double lam = 0.0;
+  if (tid < n) {
+    double lo = glo, hi = ghi;
+    for (int it = 0; it < kBisect; ++it) {
+      const double x = 0.5 * (lo + hi);
+      double q = hh_guard(hd[0] - x);
+      int cnt = q < 0.0 ? 1 : 0;
+      for (int k = 1; k < n; ++k) {
+        q = hh_guard((hd[k] - x) - he2[k - 1] / q);
+        cnt += q < 0.0 ? 1 : 0;
+      }
+      if (cnt > tid)
+        hi = x;
+      else
+        lo = x;
+    }
+    lam = 0.5 * (lo + hi);
+    eig[tid] = lam;
+  }
+  // ---- 3. eigenvector i of T by the twisted factorisation (thread i): d+ into
+  // column i of sD, d- then the vector into column i of sT
+  bool ok = true;
+  if (tid < n) {
+    const int i = tid;
+    double dp = hh_guard(hd[0] - lam);
+    sD[i] = dp;
+    for (int k = 0; k + 1 < n; ++k) {
+      dp = hh_guard((hd[k + 1] - lam) - he2[k] / dp);
+      sD[(k + 1) * LD + i] = dp;
+    }
+    double dm = hh_guard(hd[n - 1] - lam);
+    sT[(n - 1) * LD + i] = dm;
+    double best = fabs(dp + dm - (hd[n - 1] - lam));
+    int r = n - 1;
+    for (int k = n - 2; k >= 0; --k) {
+      dm = hh_guard((hd[k] - lam) - he2[k] / dm);
+      const double g = fabs(sD[k * LD + i] + dm - (hd[k] - lam));
+      if (g < best) {
+        best = g;
+        r = k;
+      }
+      sT[k * LD + i] = dm;
+    }
+    double z = 1.0, nrm2 = 1.0;
+    sT[r * LD + i] = 1.0;
+    for (int k = r - 1; k >= 0; --k) {
+      z = -(he[k] / sD[k * LD + i]) * z;
+      sT[k * LD + i] = z;
+      nrm2 = fma(z, z, nrm2);
+    }
+    z = 1.0;
+    for (int k = r; k + 1 < n; ++k) {
+      z = -(he[k] / sT[(k + 1) * LD + i]) * z;
+      sT[(k + 1) * LD + i] = z;
+      nrm2 = fma(z, z, nrm2);
+    }
+    const double inv = 1.0 / sqrt(nrm2);
+    ok = inv > 0.0 && inv < INFINITY;
+    for (int k = 0; k < n; ++k) sT[k * LD + i] *= inv;
+  }
+  if (tid == 0) L.fail = 0;
+  __syncthreads();
+  if (!ok) L.fail = 1;
+  // clusters of close eigenvalues: cst[i] = 1 where a new cluster starts
+  const double ctol = kHhCluster * fmax(fabs(eig[0]), fabs(eig[n - 1]));
+  for (int i = tid; i < n; i += NT) cst[i] = (i == 0 || eig[i] - eig[i - 1] > ctol) ? 1 : 0;
+  __syncthreads();
+  // modified Gram-Schmidt within each cluster, twice; wave w takes the clusters
+  // whose index is w (mod RG), lanes over the vector elements
+  {
+    int ci = -1;
+    for (int c0 = 0; c0 < n; ++c0) {
+      if (!cst[c0]) continue;
+      ++ci;
+      int c1 = c0 + 1;
+      while (c1 < n && !cst[c1]) ++c1;
+      if (c1 - c0 < 2 || ci % RG != wv) continue;
+      for (int rep = 0; rep < 2; ++rep)
+        for (int j = c0 + 1; j < c1; ++j) {
+          for (int q = c0; q < j; ++q) {
+            double dt = 0.0;
+            for (int k = lane; k < n; k += 64) dt = fma(sT[k * LD + q], sT[k * LD + j], dt);
+            dt = wave_sum(dt);
+            for (int k = lane; k < n; k += 64) sT[k * LD + j] = fma(-dt, sT[k * LD + q], sT[k * LD + j]);
+          }
+          double nn = 0.0;
+          for (int k = lane; k < n; k += 64) nn = fma(sT[k * LD + j], sT[k * LD + j], nn);
+          nn = wave_sum(nn);
+          if (!(nn > kHhMgsMin * kHhMgsMin)) {
+            if (lane == 0) L.fail = 1;
+            nn = 1.0;
+          }
+          const double inv = 1.0 / sqrt(nn);
+          for (int k = lane; k < n; k += 64) sT[k * LD + j] *= inv;
+        }
+    }
+  }
+  __syncthreads();
+  if (L.fail) return false;
+
+  // ---- 4. Y = Q Z in place on sT, blocks of reflectors from the last one
+  const int nref = n - 2;
+  for (int b = ((nref - 1) / kHhNb) * kHhNb; b >= 0; b -= kHhNb) {
+    const int kb = min(kHhNb, nref - b);
+    const double* V = sA + b * LD;  // row j: reflector b + j (zeros left of column b + j + 1)
+    // Gram matrix G = V^T V (kb x kb)
+    gemm_mt<NMAX, NT, false, true, 1, 1, 4>(V, V, n, V, V, 0, 0.0, kb, kb,
+                                            [&](int r, int c, double x) { L.gg[r * kHhNb + c] = x; });
+    __syncthreads();
+    // T upper triangular: T_jj = tau_j, T[0:j, j] = -tau_j T[0:j, 0:j] G[0:j, j]
+    if (wv == 0) {
+      if (lane < kHhNb * kHhNb) L.tt[lane] = 0.0;
+      for (int l = 64 + lane; l < kHhNb * kHhNb; l += 64) L.tt[l] = 0.0;
+      wave_sync();
+      for (int j = 0; j < kb; ++j) {
+        const double tj = htau[b + j];
+        double s = 0.0;
+        if (lane < j)
+          for (int l = lane; l < j; ++l) s = fma(L.tt[lane * kHhNb + l], L.gg[l * kHhNb + j], s);
+        wave_sync();
+        if (lane < j) L.tt[lane * kHhNb + j] = -tj * s;
+        if (lane == j) L.tt[j * kHhNb + j] = tj;
+        wave_sync();
+      }
+    }
+    // W1 = V Y (kb x n) into sD rows [0, kb)
+    gemm_mt<NMAX, NT, false, false, 1, 2, 4>(V, sT, n, V, V, 0, 0.0, kb, n,
+                                             [&](int r, int c, double x) { sD[r * LD + c] = x; });
+    __syncthreads();
+    // W2 = T W1 into sD rows [kHhNb, kHhNb + kb)
+    for (int e = tid; e < kb * n; e += NT) {
+      const int r = e / n, c = e - r * n;
+      double s = 0.0;
+      for (int l = r; l < kb; ++l) s = fma(L.tt[r * kHhNb + l], sD[l * LD + c], s);
+      sD[(kHhNb + r) * LD + c] = s;
+    }
+    __syncthreads();
+    // Y -= V^T-walk: Y[r][c] -= sum_j V[j][r] W2[j][c]
+    gemm_mt<NMAX, NT, true, false, 2, 2, 1>(V, sD + kHhNb * LD, kb, V, V, 0, 0.0, n, n,
+                                            [&](int r, int c, double x) { sT[r * LD + c] -= x; });
+    __syncthreads();
+  }
+  // C = X Y into sA (the reflectors are no longer needed)
+  gemm_mt<NMAX, NT, false, false, 2, 2, 4>(sX, sT, n, sX, sX, 0, 0.0, n, n,
+                                           [&](int r, int c, double x) { sA[r * LD + c] = x; });
+  __syncthreads();
+  // ---- 5. M = C^T S C; clean with one Newton-Schulz step or discard
+  for (int i = wv; i < n; i += RG)
+    for (int j = lane; j < n; j += 64) sD[i * LD + j] = gS[i * NMAX + j];
+  __syncthreads();
+  gemm_mt<NMAX, NT, false, false, 2, 2, 4>(sD, sA, n, sD, sD, 0, 0.0, n, n,
+                                           [&](int r, int c, double x) { sT[r * LD + c] = x; });
+  __syncthreads();
+  double e = 0.0;
+  gemm_mt<NMAX, NT, true, false, 2, 2, 4>(sA, sT, n, sA, sA, 0, 0.0, n, n, [&](int r, int c, double x) {
+    const double m = x - (r == c ? 1.0 : 0.0);
+    e = fmax(e, m == m ? fabs(m) : INFINITY);
+    sD[r * LD + c] = (r == c ? 1.0 : 0.0) - 0.5 * m;  // (3I - M)/2
+  });
+  e = block_max<NT>(e, red);
+  if (!(e < kHhOrthoFail)) return false;
+  if (e > kHhOrthoClean) {
+    gemm_mt<NMAX, NT, false, false, 2, 2, 4>(sA, sD, n, sA, sA, 0, 0.0, n, n,
+                                             [&](int r, int c, double x) { sT[r * LD + c] = x; });
+    __syncthreads();
+    *out = sT;
+  } else {
+    *out = sA;
+  }
+  return true;
+}
+
 struct Shared {
   int n, nocc, na, notpd;
   int bcount, bhead, sweeps, jac_iters;
-  int next_job, pad2;
+  int next_job, hh_solves, hh_fails, pad2;
   double homo, lumo;
   double fld[3];  // uniform external field of the job (zero except for field jobs)
 };
@@ -713,6 +1085,7 @@ __global__ __launch_bounds__(NT, NMAX == 32 ? 4 : 2) void scc_kernel(const SccAr
   __shared__ double lDF[kMaxHist * NMAX];  // Broyden dF history of the job (LDS copy)
   __shared__ double sBa[kMaxHist * kMaxHist], sBm[kMaxHist * (kMaxHist + 1)], sBc[kMaxHist], sBg[kMaxHist];
   __shared__ Shared sh;
+  __shared__ HhLds<GM ? NMAX : 1> sHh;  // tridiagonal solve of the large buckets
   __shared__ DevParams sPrm;  // LDS copy: the SK helpers never take the address of the kernel arguments
 
   const int tid = threadIdx.x;
@@ -731,6 +1104,7 @@ __global__ __launch_bounds__(NT, NMAX == 32 ? 4 : 2) void scc_kernel(const SccAr
   double* sX = GM ? sU + kMaxHist * NMAX : lX;
   double* sA = GM ? sX + NMAX * LD : lA;
   double* sT = GM ? sA + NMAX * LD : lT;
+  double* sD = GM ? sT + NMAX * LD : nullptr;  // fourth working matrix (large buckets only)
 
   const int n_jobs = a.n_jobs_dev ? *a.n_jobs_dev : a.n_jobs;
   // job queue: with a counter, each workgroup takes the next job when it is free
@@ -808,6 +1182,8 @@ __global__ __launch_bounds__(NT, NMAX == 32 ? 4 : 2) void scc_kernel(const SccAr
       }
       sh.sweeps = 0;
       sh.jac_iters = 0;
+      sh.hh_solves = 0;
+      sh.hh_fails = 0;
       for (int g = 0; g < 3; ++g) sh.fld[g] = 0.0;
       if (fcode >= 0) sh.fld[fcode >> 1] = (fcode & 1) ? -a.fd_h : a.fd_h;
     }
@@ -974,7 +1350,8 @@ __global__ __launch_bounds__(NT, NMAX == 32 ? 4 : 2) void scc_kernel(const SccAr
         // [nv, 2 nv) of sT; the last Sylvester sweep writes the first).  Each
         // unordered pair is read and written by one thread; the diagonal is only read.
         const int nv = n - nocc;
-        const bool ov_try = ordered && nocc > 0 && nv > 0 && 2 * nv <= n;  // K ping-pong needs 2 n_v <= n
+        const bool ov_try = ordered && nocc > 0 && nv > 0 && 2 * nv <= n &&  // K ping-pong needs 2 n_v <= n
+                            a.eig_mode != CAVDFTB_EIG_FULL;
         const int s0 = (kSylvester & 1) ? nv : 0;
         double st[4] = {0.0, 0.0, -INFINITY, -INFINITY};  // off-block, ov, max d_o, -min d_v
         {
@@ -1112,6 +1489,50 @@ __global__ __launch_bounds__(NT, NMAX == 32 ? 4 : 2) void scc_kernel(const SccAr
         if (!use_ov) {
         kmax = 0.0;
         if (tid == 0) sh.jac_iters += 1;
+        bool solved = false;
+        if constexpr (GM) {
+          if (a.eig_mode != CAVDFTB_EIG_JACOBI) {
+            double* cbuf = nullptr;
+            solved = eig_householder<NMAX, NT>(sA, sX, sT, sD, gS, n, sQorb, &sRc[0][0], &sRs[0][0], &sRt[0][0],
+                                               &sRp[0][0], sFbuf, sHh, sRed, sEig, &cbuf);
+            if (solved) {
+              double* tmp = sX;
+              if (cbuf == sA) {
+                sX = sA;
+                sA = tmp;
+              } else {
+                sX = sT;
+                sT = tmp;
+              }
+              if (tid == 0) {
+                sh.hh_solves += 1;
+                sh.homo = sEig[nocc - 1];
+                sh.lumo = nocc < n ? sEig[nocc] : sEig[n - 1];
+              }
+              __syncthreads();
+            } else {
+              // discarded: A = X^T H X again for the Jacobi solve below (X is intact)
+              if (tid == 0) sh.hh_fails += 1;
+              ew_global<NMAX, NT>(gH0, gS, n, [&](int i, int j, double h, double sv) {
+                sA[i * LD + j] = h + 0.5 * sv * (sV[sOrbAtom[i]] + sV[sOrbAtom[j]]);
+              });
+              __syncthreads();
+              gemm<NMAX, NT, false>(sA, sX, sT, n);
+              __syncthreads();
+              gemm<NMAX, NT, true>(sX, sT, sA, n);
+              __syncthreads();
+              for (int i = rgrp; i < n; i += RG)
+                for (int j = lane; j < n; j += 64)
+                  if (j > i) {
+                    const double v = 0.5 * (sA[i * LD + j] + sA[j * LD + i]);
+                    sA[i * LD + j] = v;
+                    sA[j * LD + i] = v;
+                  }
+              __syncthreads();
+            }
+          }
+        }
+        if (!solved) {
         const int half = n / 2;
         double thr = kJacobiThr;
         for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
@@ -1229,8 +1650,9 @@ __global__ __launch_bounds__(NT, NMAX == 32 ? 4 : 2) void scc_kernel(const SccAr
         double* tmp = sX;
         sX = sT;
         sT = tmp;
+        }  // cyclic Jacobi
         ordered = true;
-        }  // full Jacobi
+        }  // full diagonalisation
 
         // ---- aufbau: the first n_occ columns of X are the occupied orbitals
         // ---- P = 2 C_occ C_occ^T into sT; Mulliken populations (P S)_ii = sum_j P_ji S_ji
@@ -1500,6 +1922,8 @@ __global__ __launch_bounds__(NT, NMAX == 32 ? 4 : 2) void scc_kernel(const SccAr
         atomicAdd(&a.counters[2], per_it * (unsigned long long)it + per_geo);
         atomicAdd(&a.counters[3], (unsigned long long)sh.sweeps);
         atomicAdd(&a.counters[5], (unsigned long long)sh.jac_iters);
+        if (sh.hh_solves) atomicAdd(&a.counters[6], (unsigned long long)sh.hh_solves);
+        if (sh.hh_fails) atomicAdd(&a.counters[7], (unsigned long long)sh.hh_fails);
       }
     }
     __syncthreads();
@@ -1509,7 +1933,7 @@ __global__ __launch_bounds__(NT, NMAX == 32 ? 4 : 2) void scc_kernel(const SccAr
 }  // namespace
 
 int64_t scc_scratch_per_wg(int nmax) {
-  return 3LL * nmax * nmax + (2LL + 2LL * kMaxHist) * nmax + (nmax > 64 ? 3LL * nmax * (nmax + 1) : 0);
+  return 3LL * nmax * nmax + (2LL + 2LL * kMaxHist) * nmax + (nmax > 64 ? 4LL * nmax * (nmax + 1) : 0);
 }
 
 __global__ void reset_counter_kernel(unsigned int* c) {

@@ -312,3 +312,62 @@ def test_uneven_workload_full_shape_sampled(params):
     assert np.all(np.abs(q[ok]) <= 1e-10 * na[ok]), np.max(np.abs(q[ok]) / na[ok])
     assert np.all(F[ok] <= 1e-9 * na[ok] * fmax[ok])
     ctx.close()
+
+
+# ---------------------------------------------------------------- large-unit eigensolver
+def _large_units(n_per_bucket=2):
+    full = make_system(4, n_units=300)
+    nw = np.diff(full["unit_off"]) // 3
+    units = []
+    for lo, hi in ((11, 16), (17, 21), (22, 32)):       # orbital buckets 96, 128, 192
+        cand = [u for u in range(300) if lo <= nw[u] <= hi]
+        units += cand[:n_per_bucket]
+    units.append(int(np.argmax(nw)))
+    return subsystem(full, units), nw[units]
+
+
+def test_tridiagonal_solver_forced_parity(params):
+    # every SCC iteration of the 96/128/192-orbital units diagonalised by
+    # Householder tridiagonalisation + bisection + twisted-factorisation vectors
+    # + blocked back-transform; parity with the oracle at tol 1e-12
+    s, nw = _large_units()
+    assert nw.max() >= 29 and nw.min() <= 16
+    ctx = make_ctx(params, s)
+    ctx.set_eigensolver(cd.EIG_FULL)
+    ctx.reset_counters()
+    g = gpu_eval(ctx, s["pos"])
+    cnt = ctx.read_counters()
+    assert cnt["tridiagonal_solves"] >= cnt["scc_iterations"] > 0
+    assert cnt["tridiagonal_fallbacks"] == 0
+    r = eval_units(params, s["species"], s["pos"], s["unit_off"], tol=1e-12)
+    off = s["unit_off"]
+    for u in range(len(off) - 1):
+        a0, a1 = off[u], off[u + 1]
+        assert g["status"][u] == 0, (u, g["status"][u])
+        unit_parity(g, {"energy": r["energy"][u], "forces": r["forces"][a0:a1], "charges": r["charges"][a0:a1]},
+                    u, a0, a1)
+    ctx.close()
+
+
+def test_eigensolver_modes_agree(params):
+    # the default schedule (cold tridiagonal solve, then occupied-virtual steps),
+    # tridiagonal solves every iteration and Jacobi for every full solve reach the
+    # same fixed point; a warm MD-like second evaluation too
+    s, _ = _large_units(1)
+    rng = np.random.default_rng(3)
+    pos2 = s["pos"] + rng.normal(scale=0.01, size=s["pos"].shape)
+    outs = {}
+    for mode in (cd.EIG_AUTO, cd.EIG_FULL, cd.EIG_JACOBI):
+        ctx = make_ctx(params, s)
+        ctx.set_eigensolver(mode)
+        outs[mode] = (gpu_eval(ctx, s["pos"]), gpu_eval(ctx, pos2), ctx.read_counters())
+        ctx.close()
+    assert outs[cd.EIG_AUTO][2]["tridiagonal_solves"] > 0
+    assert outs[cd.EIG_JACOBI][2]["tridiagonal_solves"] == 0
+    for mode in (cd.EIG_FULL, cd.EIG_JACOBI):
+        for k in (0, 1):
+            a, b = outs[cd.EIG_AUTO][k], outs[mode][k]
+            assert np.all(a["status"] == 0) and np.all(b["status"] == 0)
+            assert np.max(np.abs(a["charges"] - b["charges"])) <= 1e-10
+            assert np.max(np.abs(a["energy"] - b["energy"])) <= 1e-12 * np.max(np.abs(a["energy"]))
+            assert np.max(np.abs(a["forces"] - b["forces"])) <= 1e-9 * np.max(np.abs(a["forces"]))
