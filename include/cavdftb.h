@@ -163,6 +163,30 @@ int cavdftb_set_eigensolver(cavdftb_ctx* ctx, int32_t mode);
  * depend on either setting. */
 int cavdftb_set_schedule(cavdftb_ctx* ctx, int32_t job_queue, int32_t max_wg_per_cu);
 
+/* Launch schedule of one orbital bucket (8, 16, 32, 48, 64, 96, 128 or 192
+ * orbitals; units are bucketed by their orbital count at creation):
+ * wg_per_cu resident workgroups per CU (0: the maximum the scratch was sized
+ * for; larger values are clamped to it), eig_mode a CAVDFTB_EIG_* mode for
+ * this bucket's units or -1 for the context's, job_queue 1 (device queue,
+ * units by cost) / 0 (fixed stride) or -1 for the context's.  A bucket the
+ * layout does not use is accepted and has no effect.  The workgroup count and
+ * the job order change no result; the eigensolver changes results within the
+ * SCC tolerance.  CAVDFTB_EINVAL for another bucket size or setting. */
+int cavdftb_set_bucket_schedule(cavdftb_ctx* ctx, int32_t bucket_orbitals, int32_t wg_per_cu, int32_t eig_mode,
+                                int32_t job_queue);
+/* Host outputs (any may be NULL): units in the bucket, the largest and the
+ * current resident workgroups per CU. */
+int cavdftb_bucket_info(cavdftb_ctx* ctx, int32_t bucket_orbitals, int32_t* n_units, int32_t* wg_per_cu_max,
+                        int32_t* wg_per_cu);
+/* Apply a launch table written by the autotuner (paper_2512_03277_amd/autotune.py):
+ * a JSON file whose flat objects {"arch": "gfx950", "bucket": 48,
+ * "wg_per_cu": 2, "eig_mode": 0, "job_queue": 1} each set one bucket through
+ * cavdftb_set_bucket_schedule (missing keys: 0, -1, -1); objects for another
+ * architecture than the current device's are skipped.  Returns the number of
+ * entries applied (>= 0), or CAVDFTB_EINVAL for an unreadable file, an entry
+ * without "bucket" or "arch", or a bad setting. */
+int cavdftb_load_launch_table(cavdftb_ctx* ctx, const char* path);
+
 /* Warm start: when enabled (default 1) each unit evaluation starts from the
  * charges, the molecular-orbital basis and the mixer history its previous
  * evaluation stored.  cavdftb_reset_warm_start forgets them (the next

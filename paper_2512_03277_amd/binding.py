@@ -21,6 +21,7 @@ SG_N_IN, SG_N_HID, SG_N_OUT, SG_MEMBERS, SG_N_PARAM, SG_N_NORM = 32, 128, 9, 4, 
 N_OBS = 8
 WORK_MU_POL, WORK_DIPOLE, WORK_ENERGY, WORK_CHARGES, WORK_FORCES, WORK_FIELD = range(6)
 EIG_AUTO, EIG_FULL, EIG_JACOBI = 0, 1, 2
+BUCKETS = (8, 16, 32, 48, 64, 96, 128, 192)
 OBS_NAMES = ("kinetic", "potential", "photon", "total", "temperature", "n_bad_units", "scc_iterations",
              "sum_mu_pol")
 
@@ -64,6 +65,10 @@ SYMBOLS = {
     "cavdftb_set_fallback": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "cavdftb_set_schedule": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32]),
     "cavdftb_set_eigensolver": (ctypes.c_int, [_vp, ctypes.c_int32]),
+    "cavdftb_set_bucket_schedule": (ctypes.c_int, [_vp, _c_i32, _c_i32, _c_i32, _c_i32]),
+    "cavdftb_bucket_info": (ctypes.c_int, [_vp, _c_i32, ctypes.POINTER(_c_i32), ctypes.POINTER(_c_i32),
+                                           ctypes.POINTER(_c_i32)]),
+    "cavdftb_load_launch_table": (ctypes.c_int, [_vp, ctypes.c_char_p]),
     "cavdftb_set_graph": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "cavdftb_set_born_interval": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "cavdftb_set_realspace_cavity": (ctypes.c_int, [_vp, _c_d, _c_d, _c_d, _c_d]),
@@ -210,6 +215,24 @@ class Context:
 
     def set_eigensolver(self, mode):
         self._check(self.lib.cavdftb_set_eigensolver(self.ctx, int(mode)), "set_eigensolver")
+
+    def set_bucket_schedule(self, bucket, wg_per_cu=0, eig_mode=-1, job_queue=-1):
+        self._check(self.lib.cavdftb_set_bucket_schedule(self.ctx, int(bucket), int(wg_per_cu), int(eig_mode),
+                                                         int(job_queue)), "set_bucket_schedule")
+
+    def bucket_info(self, bucket):
+        """(units, largest resident workgroups per CU, current) of one orbital bucket."""
+        nu, mx, cur = _c_i32(), _c_i32(), _c_i32()
+        self._check(self.lib.cavdftb_bucket_info(self.ctx, int(bucket), ctypes.byref(nu), ctypes.byref(mx),
+                                                 ctypes.byref(cur)), "bucket_info")
+        return nu.value, mx.value, cur.value
+
+    def load_launch_table(self, path):
+        """Entries applied (the library reads and parses the file)."""
+        rc = self.lib.cavdftb_load_launch_table(self.ctx, os.fsencode(path))
+        if rc < 0:
+            self._check(rc, "load_launch_table")
+        return rc
 
     def read_work(self, which, dst):
         """Device copy of a work array (WORK_MU_POL ... WORK_FIELD) into dst."""

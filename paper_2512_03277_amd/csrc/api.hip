@@ -2,6 +2,7 @@
 // schedule.  Every computation is done by the kernels of scc_kernel.hip and
 // md_kernels.hip on the context stream; the host only sequences launches.
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -45,6 +46,8 @@ struct Bucket {
   int n_units = 0;
   int n_wg = 0;         // workgroups of a launch (<= n_cu * per_cu_max)
   int per_cu_max = 1;   // resident workgroups per CU the scratch was sized for
+  int eig_mode = -1;    // CAVDFTB_EIG_* of this bucket's units, -1: the context's
+  int job_queue = -1;   // 1 / 0: device job queue or fixed stride for this bucket, -1: the context's
   int64_t scratch_per_wg = 0;
   int32_t* d_units = nullptr;  // center jobs: unit list
   int32_t* d_order = nullptr;  // center jobs of MD evaluations: the units by the cost of their last evaluation
@@ -261,10 +264,14 @@ SccArgs base_args(cavdftb_ctx* c, const double* pos) {
   return a;
 }
 
+bool bucket_queue(const cavdftb_ctx* c, const Bucket& b) { return b.job_queue >= 0 ? b.job_queue != 0 : c->dynamic_jobs != 0; }
+
 int run_scc(cavdftb_ctx* c, const Bucket& b, SccArgs& a) {
   if (a.n_jobs <= 0) return CAVDFTB_OK;
   a.scratch = b.d_scratch;
   a.scratch_per_wg = b.scratch_per_wg;
+  a.eig_mode = b.eig_mode >= 0 ? b.eig_mode : c->eig_mode;
+  a.job_counter = bucket_queue(c, b) ? c->d_job_counter : nullptr;
   const int n_wg = a.n_jobs < b.n_wg ? a.n_jobs : b.n_wg;
   std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
   if (c->timing) {
@@ -313,7 +320,7 @@ int eval_center(cavdftb_ctx* c, const double* pos, bool forces, bool md = false)
     a.flags = flags;
     int rc = run_scc(c, b, a);
     if (rc) return rc;
-    if (md && c->dynamic_jobs) {
+    if (md && bucket_queue(c, b)) {
       hipError_t e = launch_order_by_cost(b.n_units, b.d_order, a.job_iters, c->d_cost_scale, b.d_order_tmp,
                                           c->stream);
       if (e != hipSuccess) return hip_fail(c, e, "job order");
@@ -947,6 +954,104 @@ int cavdftb_set_schedule(cavdftb_ctx* ctx, int32_t job_queue, int32_t max_wg_per
     b.n_wg = ctx->n_cu * per;
   }
   return CAVDFTB_OK;
+}
+
+int cavdftb_set_bucket_schedule(cavdftb_ctx* ctx, int32_t bucket_orbitals, int32_t wg_per_cu, int32_t eig_mode,
+                                int32_t job_queue) {
+  if (!ctx) return CAVDFTB_EINVAL;
+  if (bucket_of(bucket_orbitals) != bucket_orbitals || wg_per_cu < 0 || eig_mode < -1 ||
+      eig_mode > CAVDFTB_EIG_JACOBI || job_queue < -1 || job_queue > 1)
+    return fail(ctx, CAVDFTB_EINVAL, "set_bucket_schedule: bad bucket or setting");
+  ctx->gen += 1;
+  for (Bucket& b : ctx->buckets) {
+    if (b.nmax != bucket_orbitals) continue;
+    const int per = wg_per_cu > 0 && wg_per_cu < b.per_cu_max ? wg_per_cu : b.per_cu_max;
+    b.n_wg = ctx->n_cu * per;
+    b.eig_mode = eig_mode;
+    b.job_queue = job_queue;
+  }
+  return CAVDFTB_OK;
+}
+
+int cavdftb_bucket_info(cavdftb_ctx* ctx, int32_t bucket_orbitals, int32_t* n_units, int32_t* wg_per_cu_max,
+                        int32_t* wg_per_cu) {
+  if (!ctx || bucket_of(bucket_orbitals) != bucket_orbitals) return CAVDFTB_EINVAL;
+  int32_t nu = 0, mx = 0, cur = 0;
+  for (const Bucket& b : ctx->buckets)
+    if (b.nmax == bucket_orbitals) {
+      nu = b.n_units;
+      mx = b.per_cu_max;
+      cur = b.n_wg / ctx->n_cu;
+    }
+  if (n_units) *n_units = nu;
+  if (wg_per_cu_max) *wg_per_cu_max = mx;
+  if (wg_per_cu) *wg_per_cu = cur;
+  return CAVDFTB_OK;
+}
+
+// value of "key": in [p, q) as an integer or a string (no escapes); false when absent
+static bool json_field(const std::string& t, size_t p, size_t q, const char* key, long* iv, std::string* sv) {
+  const std::string k = std::string("\"") + key + "\"";
+  size_t at = t.find(k, p);
+  if (at == std::string::npos || at >= q) return false;
+  at = t.find(':', at + k.size());
+  if (at == std::string::npos || at >= q) return false;
+  ++at;
+  while (at < q && (t[at] == ' ' || t[at] == '\t' || t[at] == '\n' || t[at] == '\r')) ++at;
+  if (at >= q) return false;
+  if (t[at] == '"') {
+    const size_t e = t.find('"', at + 1);
+    if (e == std::string::npos || e >= q || !sv) return false;
+    *sv = t.substr(at + 1, e - at - 1);
+    return true;
+  }
+  if (!iv) return false;
+  char* end = nullptr;
+  const long v = strtol(t.c_str() + at, &end, 10);
+  if (end == t.c_str() + at) return false;
+  *iv = v;
+  return true;
+}
+
+int cavdftb_load_launch_table(cavdftb_ctx* ctx, const char* path) {
+  if (!ctx) return CAVDFTB_EINVAL;
+  if (!path) return fail(ctx, CAVDFTB_EINVAL, "load_launch_table: null path");
+  FILE* f = fopen(path, "rb");
+  if (!f) return fail(ctx, CAVDFTB_EINVAL, "load_launch_table: cannot open the file");
+  std::string t;
+  char buf[4096];
+  size_t got;
+  while ((got = fread(buf, 1, sizeof(buf), f)) > 0) t.append(buf, got);
+  fclose(f);
+  std::string arch = "gfx950";
+  {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+      arch = prop.gcnArchName;
+      const size_t colon = arch.find(':');
+      if (colon != std::string::npos) arch.resize(colon);
+    }
+  }
+  // every flat object holding a "bucket" key is one entry
+  int applied = 0;
+  for (size_t at = t.find("\"bucket\""); at != std::string::npos; at = t.find("\"bucket\"", at + 1)) {
+    const size_t p = t.rfind('{', at), q = t.find('}', at);
+    if (p == std::string::npos || q == std::string::npos)
+      return fail(ctx, CAVDFTB_EINVAL, "load_launch_table: malformed entry");
+    long bucket = 0, wg = 0, eig = -1, queue = -1;
+    std::string a;
+    if (!json_field(t, p, q, "bucket", &bucket, nullptr) || !json_field(t, p, q, "arch", nullptr, &a))
+      return fail(ctx, CAVDFTB_EINVAL, "load_launch_table: entry without bucket or arch");
+    json_field(t, p, q, "wg_per_cu", &wg, nullptr);
+    json_field(t, p, q, "eig_mode", &eig, nullptr);
+    json_field(t, p, q, "job_queue", &queue, nullptr);
+    if (a != arch) continue;
+    const int rc = cavdftb_set_bucket_schedule(ctx, (int32_t)bucket, (int32_t)wg, (int32_t)eig, (int32_t)queue);
+    if (rc) return rc;
+    ++applied;
+  }
+  return applied;
 }
 
 int cavdftb_set_warm_start(cavdftb_ctx* ctx, int32_t enable) {

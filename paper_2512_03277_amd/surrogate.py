@@ -318,7 +318,9 @@ def main(argv=None):
     data = build_training_set(params, n_units=args.units, n_train=args.train_snapshots, n_val=args.val_snapshots,
                               stride=args.stride, n_sub=args.sub, log=log, route=args.route, workload=args.workload)
     fe, ta = data["train"]
-    log(f"training atoms: O {fe[0].shape[0]}, H {fe[1].shape[0]}")
+    n_sub_geo = sum(len(ss["unit_off"]) - 1 for ss in data["sub_systems"])
+    log(f"training geometries: {args.train_snapshots * args.units} clusters + {n_sub_geo} sub-clusters; "
+        f"atoms: O {fe[0].shape[0]}, H {fe[1].shape[0]}")
     if args.dump:
         rng = np.random.default_rng(1)
         out = {}
@@ -336,8 +338,14 @@ def main(argv=None):
     ev = evaluate(psg, nsg, params, data["system"], data["val_pos"], data["val_born"], good=data["val_good"])
     log(f"held-out: {ev}")
     os.makedirs(os.path.dirname(args.out), exist_ok=True)
+    n_sub_geo = sum(len(ss["unit_off"]) - 1 for ss in data["sub_systems"])
+    n_train_geo = args.train_snapshots * args.units + n_sub_geo
     np.savez(args.out, params=psg.cpu().numpy(), norm=nsg.cpu().numpy(),
-             rmse_surrogate=ev["rmse_surrogate"], rmse_mulliken=ev["rmse_mulliken"])
+             rmse_surrogate=ev["rmse_surrogate"], rmse_mulliken=ev["rmse_mulliken"],
+             rmse_heldout_surrogate=ev["rmse_surrogate"], rmse_heldout_mulliken=ev["rmse_mulliken"],
+             heldout_geometries=args.val_snapshots * args.units, train_geometries=n_train_geo,
+             train_atoms_o=fe[0].shape[0], train_atoms_h=fe[1].shape[0], stride_steps=args.stride,
+             epochs=args.epochs)
     log(f"wrote {args.out}")
     return 0
 

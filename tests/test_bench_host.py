@@ -49,9 +49,27 @@ def test_profiled_traffic_follows_the_kernel_source_hash(tmp_path):
     assert b.profiled_traffic(7, "x") is None
 
 
-def test_cpu_baseline_leg_reports_the_oracle_on_one_thread():
+def test_cpu_baseline_leg_reports_the_oracle_on_one_and_all_cores():
     b = _bench()
     from cavgen import make_params, make_system
-    out = b.cpu_baseline(make_params(), make_system(1), 1e-8, seconds=0.5, min_units=2)
-    assert out["kind"] == "oracle" and out["cores"] == 1 and out["unit"] == "unit-evals/s"
-    assert out["value"] > 0 and "units of the workload" in out["sample"]
+    out = b.cpu_baseline(make_params(), make_system(1), "mulliken", 1e-8, 0.0, seconds=0.5, max_workers=2)
+    assert out["kind"] == "oracle" and out["unit"] == "unit-evals/s"
+    assert out["value_1core"] > 0 and out["nproc"] >= 1 and out["cpu_model"]
+    assert out["cores"] in (1, 2) and out["value"] > 0 and "first units" in out["sample"]
+    if out["value_all_cores"] is not None:
+        assert out["cores"] == min(2, out["cpus_allowed"]) and out["value"] == out["value_all_cores"]
+
+
+def test_launch_table_json_schema():
+    # the library applies every flat object holding "bucket" (with "arch"); the
+    # timing records must not carry that key, or they would be read as entries
+    import json
+    from paper_2512_03277_amd import autotune
+    entries = [{"arch": "gfx950", "bucket": 48, "wg_per_cu": 2, "job_queue": 1, "eig_mode": 0},
+               {"arch": "gfx950", "bucket": 192, "wg_per_cu": 1, "job_queue": 0, "eig_mode": 2}]
+    timings = [{"tried_bucket": None, "setting": None, "ms_per_eval": 3.0},
+               {"tried_bucket": 48, "setting": {"wg_per_cu": 1, "job_queue": 1, "eig_mode": 0}, "ms_per_eval": 3.1}]
+    text = autotune.table_json(entries, timings, 4, "mulliken", 3.0, 2.9)
+    assert text.count('"bucket"') == len(entries)
+    d = json.loads(text)
+    assert d["entries"] == entries and d["tuned_on"] == {"workload": 4, "born": "mulliken"}

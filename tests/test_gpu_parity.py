@@ -483,19 +483,44 @@ def test_failed_unit_does_not_poison_the_cavity(params):
     assert np.max(np.abs(r_nan[keep] - out["clean"][0][keep])) < 1e-6
 
 
-def test_autotune_picks_a_candidate_and_keeps_results(params):
+def test_autotune_launch_table_keeps_results(params, tmp_path):
+    # per-bucket search, written as a launch table, read back by the library;
+    # the tuned context reaches the oracle's fixed point, and entries that keep
+    # the default eigensolver leave every bit of the results unchanged
     from paper_2512_03277_amd import autotune
     s = subsystem(make_system(4, n_units=24), list(range(0, 24, 2)))
-    best, res = autotune.tune(params, s, steps=1, warmup=1)
-    assert len(res) == 12 and all(ms > 0 for _, ms in res)
-    assert best in [st for st, _ in res]
+    entries, timings, base, final = autotune.tune(params, s, steps=1, warmup=1)
+    assert base > 0 and final > 0 and len(timings) > len(entries)
+    path = tmp_path / "table.json"
+    path.write_text(autotune.table_json(entries, timings, 4, "mulliken", base, final))
     ref = gpu_eval(make_ctx(params, s), s["pos"])
     ctx = make_ctx(params, s)
-    autotune.apply(ctx, best)
+    assert ctx.load_launch_table(str(path)) == len(entries)
+    present = set()
+    for e in entries:
+        n_units, wg_max, wg_cur = ctx.bucket_info(e["bucket"])
+        assert n_units > 0 and 1 <= e["wg_per_cu"] <= wg_max and wg_cur == e["wg_per_cu"]
+        present.add(e["bucket"])
+    assert present == {b for b in cd.binding.BUCKETS if ctx.bucket_info(b)[0] > 0}
     g = gpu_eval(ctx, s["pos"])
     r = eval_units(params, s["species"], s["pos"], s["unit_off"], tol=1e-12)
     assert_parity(g, r, pos=s["pos"], unit_off=s["unit_off"])
-    assert np.max(np.abs(g["charges"] - ref["charges"])) <= 1e-10
+    if all(e["eig_mode"] == cd.EIG_AUTO for e in entries):
+        for k in g:
+            assert np.array_equal(g[k], ref[k]), k
+    else:
+        assert np.max(np.abs(g["charges"] - ref["charges"])) <= 1e-10
+    # another architecture's entries are skipped; an entry without "arch" is an error
+    other = tmp_path / "other.json"
+    other.write_text('{"entries": [{"arch": "gfx942", "bucket": 48, "wg_per_cu": 1}]}')
+    assert ctx.load_launch_table(str(other)) == 0
+    bad = tmp_path / "bad.json"
+    bad.write_text('{"entries": [{"bucket": 48, "wg_per_cu": 1}]}')
+    with pytest.raises(cd.CavdftbError):
+        ctx.load_launch_table(str(bad))
+    with pytest.raises(cd.CavdftbError):
+        ctx.set_bucket_schedule(40, 1)
+    ctx.close()
 
 
 def test_read_work_arrays_match_the_evaluation(params):
