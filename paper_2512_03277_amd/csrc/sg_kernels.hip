@@ -4,7 +4,8 @@
 // bottleneck of the method (Results; Conclusion).  These kernels evaluate and
 // train the replacement: radial descriptors and atom-local frames, a per-species
 // 32 -> 128 -> 128 -> 9 SiLU network ensemble with BF16 operands and FP32
-// accumulation (the hidden layers of the forward pass on the matrix cores), the ensemble mean/spread with the acoustic-sum projection, and
+// accumulation (the products of the forward and backward passes on the matrix
+// cores), the ensemble mean/spread with the acoustic-sum projection, and
 // the Adam update of the FP32 master weights.  Every reduction has a fixed
 // order (per-tile partial sums reduced in tile order), so results do not depend
 // on scheduling.
@@ -297,84 +298,158 @@ __global__ __launch_bounds__(NT) void forward_kernel(const float* __restrict__ P
   }
 }
 
-// partial gradients of sum(dy . y) for one 64-atom tile into work[tile][NPAR]
-__global__ __launch_bounds__(NT) void backward_kernel(const float* __restrict__ P, const float* __restrict__ x,
-                                                      const float* __restrict__ act, const float* __restrict__ dy,
-                                                      int n, float* __restrict__ work) {
-  __shared__ float sx[TILE * NIN];
-  __shared__ float sa[TILE * NHID];   // h1, later dz1
-  __shared__ float sb[TILE * NHID];   // h2, later dz2
-  __shared__ float sdy[TILE * NOUT];
+// Partial gradients of sum(dy . y) for one 64-atom tile into work[tile][NPAR],
+// every product on the matrix cores (v_mfma_f32_16x16x16_bf16: bf16 operands,
+// FP32 accumulation), rounded to bf16 at the same points as the forward pass:
+//   dW3 = h2^T dy          dh2 = dy W3^T,  dz2 = dh2 silu'(z2)
+//   dW2 = h1^T dz2         dh1 = dz2 W2^T, dz1 = dh1 silu'(z1)
+//   dW1 = x^T dz1          db = sums of dy, dz2, dz1 (FP32, before rounding)
+// An MFMA lane feeds four consecutive k of one row of A and of one column of B,
+// so the operands of the weight gradients (contractions over atoms) are kept
+// atom-contiguous (transposed) in LDS; rows of 64 atoms have stride LDA.
+// Bias sums: per-lane partials over its four atoms, then a fixed-order sum
+// over the 16 lane groups and waves.
+constexpr int LDA = TILE + 4, LDO = 16 + 4;
+__global__ __launch_bounds__(NT) void backward_mfma_kernel(const float* __restrict__ P, const float* __restrict__ x,
+                                                           const float* __restrict__ act,
+                                                           const float* __restrict__ dy, int n,
+                                                           float* __restrict__ work) {
+  __shared__ __align__(16) unsigned short sW2[NHID * LDH];    // W2[k][j]
+  __shared__ __align__(16) unsigned short sW3[NHID * LDO];    // W3[k][o], o padded to 16
+  __shared__ __align__(16) unsigned short sXT[NIN * LDA];     // x^T
+  __shared__ __align__(16) unsigned short sH1T[NHID * LDA];   // h1^T
+  __shared__ __align__(16) unsigned short sH2T[NHID * LDA];   // h2^T, later dz1^T
+  __shared__ __align__(16) unsigned short sDY[TILE * LDO];    // dy (o padded)
+  __shared__ __align__(16) unsigned short sDYT[16 * LDA];     // dy^T
+  __shared__ __align__(16) unsigned short sDZ2[TILE * LDH];   // dz2
+  __shared__ __align__(16) unsigned short sDZ2T[NHID * LDA];  // dz2^T
+  __shared__ float sPb[2][NT / 64][4][NHID];                  // bias partials of dz2, dz1 [wave][lane group][j]
   float* g = work + (int64_t)blockIdx.x * NPAR;
   const int t0 = blockIdx.x * TILE;
   const int m = min(TILE, n - t0);
-  for (int e = threadIdx.x; e < TILE * NIN; e += NT) sx[e] = (e / NIN) < m ? x[(int64_t)t0 * NIN + e] : 0.0f;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int r16 = lane & 15, kq = (lane >> 4) * 4, grp = lane >> 4;
+  for (int e = threadIdx.x; e < NHID * NHID; e += NT) sW2[(e / NHID) * LDH + e % NHID] = bf16_bits(P[OFF_W2 + e]);
+  for (int e = threadIdx.x; e < NHID * 16; e += NT) {
+    const int k = e / 16, o = e % 16;
+    sW3[k * LDO + o] = o < NOUT ? bf16_bits(P[OFF_W3 + k * NOUT + o]) : (unsigned short)0;
+  }
+  for (int e = threadIdx.x; e < TILE * NIN; e += NT) {
+    const int a = e / NIN, i = e % NIN;
+    sXT[i * LDA + a] = a < m ? bf16_bits(x[(int64_t)t0 * NIN + e]) : (unsigned short)0;
+  }
   for (int e = threadIdx.x; e < TILE * NHID; e += NT) {
     const int a = e / NHID, k = e % NHID;
-    sa[e] = a < m ? silu(act[(int64_t)(t0 + a) * 2 * NHID + k]) : 0.0f;
-    sb[e] = a < m ? silu(act[(int64_t)(t0 + a) * 2 * NHID + NHID + k]) : 0.0f;
+    const float* z = act + (int64_t)(t0 + a) * 2 * NHID;
+    sH1T[k * LDA + a] = a < m ? bf16_bits(silu(z[k])) : (unsigned short)0;
+    sH2T[k * LDA + a] = a < m ? bf16_bits(silu(z[NHID + k])) : (unsigned short)0;
   }
-  for (int e = threadIdx.x; e < TILE * NOUT; e += NT) sdy[e] = (e / NOUT) < m ? dy[(int64_t)t0 * NOUT + e] : 0.0f;
+  for (int e = threadIdx.x; e < TILE * 16; e += NT) {
+    const int a = e / 16, o = e % 16;
+    const unsigned short v = (a < m && o < NOUT) ? bf16_bits(dy[(int64_t)(t0 + a) * NOUT + o]) : (unsigned short)0;
+    sDY[a * LDO + o] = v;
+    sDYT[o * LDA + a] = v;
+  }
+  if (threadIdx.x < NOUT) {  // db3 in atom order
+    float sum = 0.0f;
+    for (int a = 0; a < m; ++a) sum += dy[(int64_t)(t0 + a) * NOUT + threadIdx.x];
+    g[OFF_B3 + threadIdx.x] = sum;
+  }
   __syncthreads();
-  // dW3 = h2^T dy, db3 = sum dy
-  for (int e = threadIdx.x; e < NHID * NOUT + NOUT; e += NT) {
-    float s = 0.0f;
-    if (e < NHID * NOUT) {
-      const int k = e / NOUT, o = e % NOUT;
-      for (int a = 0; a < TILE; ++a) s = fmaf(bf16r(sb[a * NHID + k]), bf16r(sdy[a * NOUT + o]), s);
-      g[OFF_W3 + e] = s;
-    } else {
-      const int o = e - NHID * NOUT;
-      for (int a = 0; a < TILE; ++a) s += sdy[a * NOUT + o];
-      g[OFF_B3 + o] = s;
+  // dW3 (128 x 16 tiles: wave w takes k-tiles w and w + 4) and dh2 -> dz2
+  for (int t = wv; t < NHID / 16; t += NT / 64) {
+    f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int k0 = 0; k0 < TILE; k0 += 16) {
+      const bf16x4 av = *reinterpret_cast<const bf16x4*>(sH2T + (16 * t + r16) * LDA + k0 + kq);
+      const bf16x4 bv = *reinterpret_cast<const bf16x4*>(sDYT + r16 * LDA + k0 + kq);
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+    }
+    if (r16 < NOUT)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) g[OFF_W3 + (16 * t + kq + i) * NOUT + r16] = acc[i];
+  }
+  {
+    const bf16x4 av = *reinterpret_cast<const bf16x4*>(sDY + (16 * wv + r16) * LDO + kq);
+#pragma unroll
+    for (int t = 0; t < NHID / 16; ++t) {
+      const bf16x4 bv = *reinterpret_cast<const bf16x4*>(sW3 + (16 * t + r16) * LDO + kq);
+      const f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, f32x4{0.0f, 0.0f, 0.0f, 0.0f}, 0, 0, 0);
+      const int j = 16 * t + r16;
+      float bsum = 0.0f;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int a = 16 * wv + kq + i;
+        const float dz = a < m ? acc[i] * dsilu(act[(int64_t)(t0 + a) * 2 * NHID + NHID + j]) : 0.0f;
+        bsum += dz;
+        const unsigned short b = bf16_bits(dz);
+        sDZ2[a * LDH + j] = b;
+        sDZ2T[j * LDA + a] = b;
+      }
+      sPb[0][wv][grp][j] = bsum;
     }
   }
   __syncthreads();
-  // dz2 = (dy W3^T) * silu'(z2)   (in place of h2)
-  float tmp[TILE * NHID / NT];
-  for (int r = 0, e = threadIdx.x; e < TILE * NHID; e += NT, ++r) {
-    const int a = e / NHID, k = e % NHID;
-    float s = 0.0f;
-    for (int o = 0; o < NOUT; ++o) s = fmaf(bf16r(sdy[a * NOUT + o]), bf16r(P[OFF_W3 + k * NOUT + o]), s);
-    tmp[r] = a < m ? s * dsilu(act[(int64_t)(t0 + a) * 2 * NHID + NHID + k]) : 0.0f;
+  // dW2 (128 x 128: wave w takes 16 of the 64 tiles) and dh1 -> dz1 (into sH2T)
+  for (int tt = wv; tt < (NHID / 16) * (NHID / 16); tt += NT / 64) {
+    const int ti = tt / (NHID / 16), tj = tt % (NHID / 16);
+    f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int k0 = 0; k0 < TILE; k0 += 16) {
+      const bf16x4 av = *reinterpret_cast<const bf16x4*>(sH1T + (16 * ti + r16) * LDA + k0 + kq);
+      const bf16x4 bv = *reinterpret_cast<const bf16x4*>(sDZ2T + (16 * tj + r16) * LDA + k0 + kq);
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) g[OFF_W2 + (16 * ti + kq + i) * NHID + 16 * tj + r16] = acc[i];
   }
-  // dW2 needs h1 and dz2; h2 is no longer needed
+  {
+    f32x4 acc[NHID / 16];
+#pragma unroll
+    for (int t = 0; t < NHID / 16; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int k0 = 0; k0 < NHID; k0 += 16) {
+      const bf16x4 av = *reinterpret_cast<const bf16x4*>(sDZ2 + (16 * wv + r16) * LDH + k0 + kq);
+#pragma unroll
+      for (int t = 0; t < NHID / 16; ++t) {
+        const bf16x4 bv = *reinterpret_cast<const bf16x4*>(sW2 + (16 * t + r16) * LDH + k0 + kq);
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[t], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < NHID / 16; ++t) {
+      const int k = 16 * t + r16;
+      float bsum = 0.0f;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int a = 16 * wv + kq + i;
+        const float dz = a < m ? acc[t][i] * dsilu(act[(int64_t)(t0 + a) * 2 * NHID + k]) : 0.0f;
+        bsum += dz;
+        sH2T[k * LDA + a] = bf16_bits(dz);
+      }
+      sPb[1][wv][grp][k] = bsum;
+    }
+  }
   __syncthreads();
-  for (int r = 0, e = threadIdx.x; e < TILE * NHID; e += NT, ++r) sb[e] = tmp[r];
-  __syncthreads();
-  // dW2[k][j] = sum_a h1[a][k] dz2[a][j] ; db2 = sum dz2
-  for (int e = threadIdx.x; e < NHID * NHID; e += NT) {
-    const int k = e / NHID, j = e % NHID;
-    float s = 0.0f;
-    for (int a = 0; a < TILE; ++a) s = fmaf(bf16r(sa[a * NHID + k]), bf16r(sb[a * NHID + j]), s);
-    g[OFF_W2 + e] = s;
+  // dW1 (32 x 128: wave w takes 4 of the 16 tiles); the bias sums in fixed order
+  for (int tt = wv; tt < (NIN / 16) * (NHID / 16); tt += NT / 64) {
+    const int ti = tt / (NHID / 16), tj = tt % (NHID / 16);
+    f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int k0 = 0; k0 < TILE; k0 += 16) {
+      const bf16x4 av = *reinterpret_cast<const bf16x4*>(sXT + (16 * ti + r16) * LDA + k0 + kq);
+      const bf16x4 bv = *reinterpret_cast<const bf16x4*>(sH2T + (16 * tj + r16) * LDA + k0 + kq);
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) g[OFF_W1 + (16 * ti + kq + i) * NHID + 16 * tj + r16] = acc[i];
   }
-  for (int j = threadIdx.x; j < NHID; j += NT) {
-    float s = 0.0f;
-    for (int a = 0; a < TILE; ++a) s += sb[a * NHID + j];
-    g[OFF_B2 + j] = s;
-  }
-  // dz1 = (dz2 W2^T) * silu'(z1)
-  for (int r = 0, e = threadIdx.x; e < TILE * NHID; e += NT, ++r) {
-    const int a = e / NHID, k = e % NHID;
-    float s = 0.0f;
-    for (int j = 0; j < NHID; ++j) s = fmaf(bf16r(sb[a * NHID + j]), bf16r(P[OFF_W2 + k * NHID + j]), s);
-    tmp[r] = a < m ? s * dsilu(act[(int64_t)(t0 + a) * 2 * NHID + k]) : 0.0f;
-  }
-  __syncthreads();
-  for (int r = 0, e = threadIdx.x; e < TILE * NHID; e += NT, ++r) sa[e] = tmp[r];
-  __syncthreads();
-  // dW1[i][k] = sum_a x[a][i] dz1[a][k] ; db1 = sum dz1
-  for (int e = threadIdx.x; e < NIN * NHID; e += NT) {
-    const int i = e / NHID, k = e % NHID;
-    float s = 0.0f;
-    for (int a = 0; a < TILE; ++a) s = fmaf(bf16r(sx[a * NIN + i]), bf16r(sa[a * NHID + k]), s);
-    g[OFF_W1 + e] = s;
-  }
-  for (int k = threadIdx.x; k < NHID; k += NT) {
-    float s = 0.0f;
-    for (int a = 0; a < TILE; ++a) s += sa[a * NHID + k];
-    g[OFF_B1 + k] = s;
+  for (int j = threadIdx.x; j < 2 * NHID; j += NT) {
+    const int which = j / NHID, jj = j % NHID;
+    float sum = 0.0f;
+    for (int w = 0; w < NT / 64; ++w)
+      for (int q = 0; q < 4; ++q) sum += sPb[which][w][q][jj];
+    g[(which == 0 ? OFF_B2 : OFF_B1) + jj] = sum;
   }
 }
 
@@ -628,7 +703,7 @@ hipError_t launch_sg_backward(const float* P, const float* x, const float* act, 
                               float* work, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const int tiles = (n + TILE - 1) / TILE;
-  hipLaunchKernelGGL(backward_kernel, dim3(tiles), dim3(NT), 0, s, P, x, act, dy, n, work);
+  hipLaunchKernelGGL(backward_mfma_kernel, dim3(tiles), dim3(NT), 0, s, P, x, act, dy, n, work);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(reduce_tiles_kernel, dim3(nb(NPAR)), dim3(NT), 0, s, work, tiles, NPAR, grad);

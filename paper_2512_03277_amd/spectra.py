@@ -92,19 +92,26 @@ def resolution_cm(n_samples, dt):
     return 2.0 * np.pi / (n_samples * dt) * HARTREE_CM
 
 
-def peak_report(series_a, series_b, dt, lo, hi, centroid_halfwidth=250.0):
-    """Spectra of two runs recorded from the same start (series [T, K]), the
-    shift of their largest peak in [lo, hi] cm^-1, and the shift of their band
-    centroids over the same window, centred on run b's peak with the given
-    half width."""
-    fa, Ia = spectrum(autocorrelation(series_a), dt)
-    fb, Ib = spectrum(autocorrelation(series_b), dt)
+def report_from_acf(Ca, Cb, dt, lo, hi, n_samples):
+    """Peak and band-centroid positions of two runs from their (averaged)
+    autocorrelations: the largest peak in [lo, hi] cm^-1 of each, and the first
+    moment of each spectrum over that same fixed band (it depends on neither
+    run; a peak can jump between neighbouring maxima of a broad noisy band, the
+    centroid cannot).  The resolution 2 pi / (n_samples dt) is returned beside
+    them; neither position is meaningful to much better than a fraction of it."""
+    fa, Ia = spectrum(Ca, dt)
+    fb, Ib = spectrum(Cb, dt)
     pa, pb = peak(fa, Ia, lo, hi), peak(fb, Ib, lo, hi)
-    wlo, whi = pb - centroid_halfwidth, pb + centroid_halfwidth
-    ca, cb = centroid(fa, Ia, wlo, whi), centroid(fb, Ib, wlo, whi)
+    ca, cb = centroid(fa, Ia, lo, hi), centroid(fb, Ib, lo, hi)
     return {"peak_a_cm": pa, "peak_b_cm": pb, "shift_cm": pa - pb,
             "centroid_a_cm": ca, "centroid_b_cm": cb, "centroid_shift_cm": ca - cb,
-            "resolution_cm": resolution_cm(len(series_a), dt)}
+            "band_cm": [lo, hi], "resolution_cm": resolution_cm(n_samples, dt)}
+
+
+def peak_report(series_a, series_b, dt, lo, hi):
+    """report_from_acf for two runs recorded from the same start (series [T, K],
+    the autocorrelation averaged over the K series)."""
+    return report_from_acf(autocorrelation(series_a), autocorrelation(series_b), dt, lo, hi, len(series_a))
 
 
 def spectrum_per_series(x, dt, pad=8, omega_squared=True):

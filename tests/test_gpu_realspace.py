@@ -170,3 +170,53 @@ def test_thermal_mode_start_matches_the_oracle(params):
     with pytest.raises(RuntimeError):
         ctx.init_photons_thermal(r, qm, pm, float("nan"), _t(xi))
     ctx.close()
+
+
+def _rs_run(params, s, eta, steps):
+    n = len(s["unit_off"]) - 1
+    masses = params["mass"][s["species"]]
+    ctx = cd.context_from_system(params, s)
+    ctx.set_scc(1e-12, 300, 0.2)
+    ctx.set_realspace_cavity(eta, W0, C, A)
+    r = _t(s["pos"])
+    p = _t(s["vel"] * masses[:, None])
+    qn = torch.zeros(n, dtype=torch.float64, device=DEV)
+    pn = torch.zeros_like(qn)
+    rec = torch.zeros(steps, n, dtype=torch.float64, device=DEV)
+    ctx.init_photons_realspace(r, qn, pn)
+    ctx.step_realspace(r, p, qn, pn, steps, s["dt"], cd.BORN_MULLIKEN, 0.0, None, rec)
+    assert ctx.sync() == 0
+    out = (p.cpu().numpy(), rec.cpu().numpy())
+    ctx.close()
+    return out
+
+
+def test_realspace_eta_sweep_matches_the_oracle_and_responds_linearly(params):
+    # the coupling sweep of the Rabi-splitting study on the GPU: at each eta the
+    # device scheme equals the oracle's (whose k = 0 polariton pair splits
+    # linearly in eta on harmonic cells, tests/test_oracle_realspace.py), and the
+    # photon response the matter drives is linear in eta: after a few steps from
+    # the relaxed photon start, q_k(eta) / eta is the same at eta, 2 eta and 4 eta
+    # up to a correction of relative size 4e-5 here; the response is odd in eta
+    # (eta -> -eta, q -> -q), so that correction is of order eta^2 and grows
+    # fourfold per doubling (3.99 in the oracle)
+    s = _subsystem(make_system(1), list(range(8)))
+    n, steps = 8, 4
+    masses = params["mass"][s["species"]]
+    recs = {}
+    for eta in (2.5e-3, 5e-3, 1e-2):
+        p_g, rec = _rs_run(params, s, eta, steps)
+        be = omd.DFTBBackend(params, s["species"], s["unit_off"], born="mulliken", tol=1e-12)
+        cav = ors.RealSpaceCavity(eta, W0, ors.dispersion(n, W0, C, A), s["pol"])
+        atom_unit = np.repeat(np.arange(n), np.diff(s["unit_off"]))
+        st = ors.init_state(be, cav, s["pos"], s["vel"] * masses[:, None], masses, atom_unit)
+        qk = []
+        for _ in range(steps):
+            ors.step(st, be, cav, s["dt"])
+            qk.append(st["qk"].copy())
+        assert _rel(p_g, st["p"]) <= 1e-8 and _rel(rec, np.array(qk)) <= 1e-8
+        recs[eta] = rec
+    r1, r2, r4 = recs[2.5e-3] / 2.5e-3, recs[5e-3] / 5e-3, recs[1e-2] / 1e-2
+    d12, d24 = np.max(np.abs(r2 - r1)), np.max(np.abs(r4 - r2))
+    assert d12 <= 1e-3 * np.max(np.abs(r1))                 # linear to 0.1 %
+    assert d24 == pytest.approx(4.0 * d12, rel=0.1)         # the deviation is of order eta^2

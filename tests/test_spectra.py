@@ -156,3 +156,34 @@ def test_centroid_of_a_line_and_of_two_lines():
     assert spectra.centroid(f, I, 1350.0, 1950.0) == pytest.approx(1650.0, abs=1.0)
     with pytest.raises(ValueError):
         spectra.centroid(f, I, -2.0, -1.0)
+
+
+def test_combine_spectra_averages_starts_with_fixed_band():
+    # two starts of the same two-path record: each start's autocorrelations are
+    # saved as the bench does, combined on the host, and the line is found at its
+    # frequency with zero shift between identical paths; the band centroid is
+    # taken over the fixed band, the same for both paths
+    import importlib.util
+    import os
+    spec = importlib.util.spec_from_file_location(
+        "bench_for_spectra", os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    t = np.arange(4000) * DT
+    nu = 1650.0
+    w = nu / spectra.HARTREE_CM
+    per = []
+    rng = np.random.default_rng(3)
+    for start in (0, 1):
+        x = np.cos(w * t[:, None] + rng.uniform(0, 2 * np.pi, size=(1, 6)))
+        q = np.cos(1.3 * w * t[:, None] + rng.uniform(0, 2 * np.pi, size=(1, 4)))
+        C, Cq = spectra.autocorrelation(x), spectra.autocorrelation(q)
+        per.append({"start": start, "units_in_ir_average": 6, "C_ir_surrogate": C, "C_ir_exact": C,
+                    "C_pol_surrogate": Cq, "C_pol_exact": Cq, "md_steps_per_s_surrogate": 1.0,
+                    "md_steps_per_s_exact": 1.0, "bad_units_surrogate": 0, "bad_units_exact": 0,
+                    "steps": len(t), "dt": DT, "units": 6})
+    rep = bench.combine_spectra(per)
+    assert rep["ir_peak_exact_cm"] == pytest.approx(nu, abs=2.0)
+    assert rep["polariton_peak_exact_cm"] == pytest.approx(1.3 * nu, abs=3.0)
+    assert rep["ir_shift_cm"] == 0.0 and rep["ir_centroid_shift_cm"] == 0.0 and rep["ir_band_cm"] == [1000.0, 4500.0]
+    assert rep["ir_shift_single_starts_cm"] == [0.0, 0.0] and rep["starts"] == [0, 1]
