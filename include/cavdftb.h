@@ -186,6 +186,16 @@ int cavdftb_bucket_info(cavdftb_ctx* ctx, int32_t bucket_orbitals, int32_t* n_un
  * entries applied (>= 0), or CAVDFTB_EINVAL for an unreadable file, an entry
  * without "bucket" or "arch", or a bad setting. */
 int cavdftb_load_launch_table(cavdftb_ctx* ctx, const char* path);
+/* Streams that the bucket launches of an undisplaced evaluation of every
+ * unit (cavdftb_eval_units, the MD steps, the centre pass of
+ * cavdftb_born_charges and of the photon starts) are spread over, 1..4 (default 4): the context stream and up to three side
+ * streams of default priority that the library creates.  Buckets go, largest
+ * estimated cost first, to the stream with the least work so far; the side
+ * streams wait for the context stream's earlier work and the context stream
+ * waits for them before its next work, so callers see one stream.  Results
+ * are bit-identical for every count (the buckets hold disjoint units).
+ * Returns CAVDFTB_EINVAL for a count outside 1..4. */
+int cavdftb_set_bucket_streams(cavdftb_ctx* ctx, int32_t n_streams);
 
 /* Warm start: when enabled (default 1) each unit evaluation starts from the
  * charges, the molecular-orbital basis and the mixer history its previous

@@ -66,6 +66,7 @@ SYMBOLS = {
     "cavdftb_set_schedule": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int32]),
     "cavdftb_set_eigensolver": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "cavdftb_set_bucket_schedule": (ctypes.c_int, [_vp, _c_i32, _c_i32, _c_i32, _c_i32]),
+    "cavdftb_set_bucket_streams": (ctypes.c_int, [_vp, _c_i32]),
     "cavdftb_bucket_info": (ctypes.c_int, [_vp, _c_i32, ctypes.POINTER(_c_i32), ctypes.POINTER(_c_i32),
                                            ctypes.POINTER(_c_i32)]),
     "cavdftb_load_launch_table": (ctypes.c_int, [_vp, ctypes.c_char_p]),
@@ -219,6 +220,9 @@ class Context:
     def set_bucket_schedule(self, bucket, wg_per_cu=0, eig_mode=-1, job_queue=-1):
         self._check(self.lib.cavdftb_set_bucket_schedule(self.ctx, int(bucket), int(wg_per_cu), int(eig_mode),
                                                          int(job_queue)), "set_bucket_schedule")
+
+    def set_bucket_streams(self, n_streams):
+        self._check(self.lib.cavdftb_set_bucket_streams(self.ctx, int(n_streams)), "set_bucket_streams")
 
     def bucket_info(self, bucket):
         """(units, largest resident workgroups per CU, current) of one orbital bucket."""

@@ -42,6 +42,8 @@ int bucket_of(int n) {
 }
 
 struct Bucket {
+  int idx = 0;          // position in the context's bucket list (its job counter)
+  double cost = 0.0;    // estimated work of one evaluation: sum of (orbitals / 48)^3 over its units
   int nmax = 0;
   int n_units = 0;
   int n_wg = 0;         // workgroups of a launch (<= n_cu * per_cu_max)
@@ -111,7 +113,14 @@ struct cavdftb_ctx {
   int32_t *d_status = nullptr, *d_cjob_status = nullptr, *d_cjob_iters = nullptr;
   int32_t *d_fjob_status = nullptr, *d_fjob_iters = nullptr;
   unsigned long long* d_counters = nullptr;
-  unsigned int* d_job_counter = nullptr;  // job queue of the SCC launches (one launch at a time per stream)
+  unsigned int* d_job_counter = nullptr;  // job queues of the SCC launches, one per bucket
+  // concurrent bucket launches of the undisplaced evaluations: up to 4 streams
+  // of default priority (the context stream and three side streams), forked
+  // and joined with events on the context stream
+  hipStream_t side[3] = {nullptr, nullptr, nullptr};
+  hipEvent_t ev_fork = nullptr;
+  hipEvent_t ev_join[3] = {nullptr, nullptr, nullptr};
+  int n_streams = 4;
   int dynamic_jobs = 1;
   int n_cu = 256;
   // learned Born-charge surrogate
@@ -204,6 +213,21 @@ void drop_graph(cavdftb_ctx* c) {
 
 void release(cavdftb_ctx* c) {
   if (c->stream) hipStreamSynchronize(c->stream);
+  for (int j = 0; j < 3; ++j)
+    if (c->side[j]) {
+      hipStreamSynchronize(c->side[j]);
+      hipStreamDestroy(c->side[j]);
+      c->side[j] = nullptr;
+    }
+  for (int j = 0; j < 3; ++j)
+    if (c->ev_join[j]) {
+      hipEventDestroy(c->ev_join[j]);
+      c->ev_join[j] = nullptr;
+    }
+  if (c->ev_fork) {
+    hipEventDestroy(c->ev_fork);
+    c->ev_fork = nullptr;
+  }
   drop_graph(c);
   for (void* p : c->allocs) hipFree(p);
   c->allocs.clear();
@@ -256,7 +280,7 @@ SccArgs base_args(cavdftb_ctx* c, const double* pos) {
   a.jac_factor = c->jac_factor;
   a.eig_mode = c->eig_mode;
   a.counters = c->d_counters;
-  a.job_counter = c->dynamic_jobs ? c->d_job_counter : nullptr;
+  a.job_counter = nullptr;  // set per bucket by run_scc
   a.tol = c->tol;
   a.max_iter = c->max_iter;
   a.alpha = c->alpha;
@@ -266,23 +290,23 @@ SccArgs base_args(cavdftb_ctx* c, const double* pos) {
 
 bool bucket_queue(const cavdftb_ctx* c, const Bucket& b) { return b.job_queue >= 0 ? b.job_queue != 0 : c->dynamic_jobs != 0; }
 
-int run_scc(cavdftb_ctx* c, const Bucket& b, SccArgs& a) {
+int run_scc(cavdftb_ctx* c, const Bucket& b, SccArgs& a, hipStream_t stream) {
   if (a.n_jobs <= 0) return CAVDFTB_OK;
   a.scratch = b.d_scratch;
   a.scratch_per_wg = b.scratch_per_wg;
   a.eig_mode = b.eig_mode >= 0 ? b.eig_mode : c->eig_mode;
-  a.job_counter = bucket_queue(c, b) ? c->d_job_counter : nullptr;
+  a.job_counter = bucket_queue(c, b) ? c->d_job_counter + b.idx : nullptr;
   const int n_wg = a.n_jobs < b.n_wg ? a.n_jobs : b.n_wg;
   std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
   if (c->timing) {
     if (c->ev_pending.size() > 4096) harvest_events(c);
     ev = get_events(c);
-    hipEventRecord(ev.first, c->stream);
+    hipEventRecord(ev.first, stream);
   }
-  hipError_t e = launch_scc(b.nmax, n_wg, a, c->stream);
+  hipError_t e = launch_scc(b.nmax, n_wg, a, stream);
   if (e != hipSuccess) return hip_fail(c, e, "scc kernel launch");
   if (c->timing) {
-    hipEventRecord(ev.second, c->stream);
+    hipEventRecord(ev.second, stream);
     c->ev_pending.push_back(ev);
   }
   c->launches += 1;
@@ -296,10 +320,56 @@ int32_t center_flags(cavdftb_ctx* c, bool forces) {
   return flags;
 }
 
+// The bucket launches of one undisplaced evaluation spread over up to
+// n_streams streams: buckets by estimated cost, largest first, each to the
+// stream with the least work so far (stream 0 is the context stream).  The
+// side streams wait for the context stream's earlier work (fork) and the
+// context stream waits for theirs (join); captured into a graph, the event
+// edges become graph dependencies.
+struct BucketFan {
+  cavdftb_ctx* c;
+  int ns;
+  double load[4] = {0.0, 0.0, 0.0, 0.0};
+  std::vector<int> order;
+
+  explicit BucketFan(cavdftb_ctx* ctx) : c(ctx), ns(std::min(ctx->n_streams, (int)ctx->buckets.size())) {
+    order.resize(c->buckets.size());
+    for (size_t k = 0; k < order.size(); ++k) order[k] = (int)k;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return c->buckets[x].cost > c->buckets[y].cost; });
+  }
+  int fork() {
+    if (ns <= 1) return CAVDFTB_OK;
+    hipError_t e = hipEventRecord(c->ev_fork, c->stream);
+    for (int j = 1; j < ns && e == hipSuccess; ++j) e = hipStreamWaitEvent(c->side[j - 1], c->ev_fork, 0);
+    return e == hipSuccess ? CAVDFTB_OK : hip_fail(c, e, "bucket streams fork");
+  }
+  hipStream_t stream_for(const Bucket& b) {
+    int slot = 0;
+    for (int j = 1; j < ns; ++j)
+      if (load[j] < load[slot]) slot = j;
+    load[slot] += b.cost;
+    return slot == 0 ? c->stream : c->side[slot - 1];
+  }
+  int join() {
+    if (ns <= 1) return CAVDFTB_OK;
+    hipError_t e = hipSuccess;
+    for (int j = 1; j < ns && e == hipSuccess; ++j) {
+      e = hipEventRecord(c->ev_join[j - 1], c->side[j - 1]);
+      if (e == hipSuccess) e = hipStreamWaitEvent(c->stream, c->ev_join[j - 1], 0);
+    }
+    return e == hipSuccess ? CAVDFTB_OK : hip_fail(c, e, "bucket streams join");
+  }
+};
+
 int eval_center(cavdftb_ctx* c, const double* pos, bool forces, bool md = false) {
   const int32_t flags = center_flags(c, forces);
   const bool extrap = md && c->warm_enabled && c->warm_valid;
-  for (const Bucket& b : c->buckets) {
+  BucketFan fan(c);
+  if (int rc = fan.fork()) return rc;
+  for (int bi : fan.order) {
+    const Bucket& b = c->buckets[bi];
+    hipStream_t bs = fan.stream_for(b);
     SccArgs a = base_args(c, pos);
     if (md) {
       a.ws_dq_hist = c->d_ws_dq_hist;
@@ -318,14 +388,14 @@ int eval_center(cavdftb_ctx* c, const double* pos, bool forces, bool md = false)
     a.job_status = c->d_cjob_status + b.cjob0;
     a.job_iters = c->d_cjob_iters + b.cjob0;
     a.flags = flags;
-    int rc = run_scc(c, b, a);
+    int rc = run_scc(c, b, a, bs);
     if (rc) return rc;
     if (md && bucket_queue(c, b)) {
-      hipError_t e = launch_order_by_cost(b.n_units, b.d_order, a.job_iters, c->d_cost_scale, b.d_order_tmp,
-                                          c->stream);
+      hipError_t e = launch_order_by_cost(b.n_units, b.d_order, a.job_iters, c->d_cost_scale, b.d_order_tmp, bs);
       if (e != hipSuccess) return hip_fail(c, e, "job order");
     }
   }
+  if (int rc = fan.join()) return rc;
   c->md_hist = (md && extrap) ? c->md_hist + 1 : (md && c->warm_enabled ? 1 : 0);
   c->warm_valid = c->warm_enabled != 0;
   return CAVDFTB_OK;
@@ -362,7 +432,7 @@ int eval_fd(cavdftb_ctx* c, const double* pos, double h, double* born, const int
     a.fd_dq_off = c->d_fd_dq_off;
     for (int pass = 1; pass <= 2; ++pass) {
       a.fd_pass = pass;
-      int rc = run_scc(c, b, a);
+      int rc = run_scc(c, b, a, c->stream);
       if (rc) return rc;
     }
     hipError_t e = launch_born_fd_assemble(c->d_unit_off, b.d_fd_unit, job0, b.n_units,
@@ -401,7 +471,7 @@ int eval_field(cavdftb_ctx* c, const double* pos, double e_field, double* born, 
     a.fd_dq_off = c->d_fd_dq_off;
     for (int pass = 1; pass <= 2; ++pass) {  // also for fallback lists: their results equal the full route's
       a.fd_pass = pass;
-      int rc = run_scc(c, b, a);
+      int rc = run_scc(c, b, a, c->stream);
       if (rc) return rc;
     }
   }
@@ -424,7 +494,7 @@ int eval_fd_forward(cavdftb_ctx* c, const double* pos, double h, double* born) {
     a.job_status = c->d_fjob_status + b.fjob0;
     a.job_iters = c->d_fjob_iters + b.fjob0;
     a.flags = JF_WARM_C | JF_WARM_DQ;  // fresh mixer, as for central differences
-    int rc = run_scc(c, b, a);
+    int rc = run_scc(c, b, a, c->stream);
     if (rc) return rc;
     hipError_t e = launch_born_fd_forward_assemble(c->d_unit_off, b.d_fd_unit, b.d_fw_job0, b.n_units,
                                                    c->d_mu_job + (int64_t)b.fjob0 * 3, c->d_dipole, h, c->pol,
@@ -773,7 +843,12 @@ int cavdftb_create(const cavdftb_params* params, const cavdftb_layout* L, void* 
     CK(hipMemcpy(c->d_n_sp, c->n_sp, 2 * sizeof(int32_t), hipMemcpyHostToDevice));
   }
   CK(dalloc(c, &c->d_counters, 8));
-  CK(dalloc(c, &c->d_job_counter, 1));
+  CK(dalloc(c, &c->d_job_counter, kNumBuckets));
+  for (int j = 0; j < 3; ++j) {
+    CK(hipStreamCreateWithFlags(&c->side[j], hipStreamNonBlocking));
+    CK(hipEventCreateWithFlags(&c->ev_join[j], hipEventDisableTiming));
+  }
+  CK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
   CK(dalloc(c, &c->d_obs_row, 1));
   c->obs_part_rows = observables_part_rows(std::max(U, c->M));
   CK(dalloc(c, &c->d_obs_part, (size_t)c->obs_part_rows * 8));
@@ -809,6 +884,7 @@ int cavdftb_create(const cavdftb_params* params, const cavdftb_layout* L, void* 
   for (int k = 0; k < kNumBuckets; ++k) {
     if (bunits[k].empty()) continue;
     Bucket b;
+    b.idx = (int)c->buckets.size();
     b.nmax = nmaxs[k];
     b.n_units = (int)bunits[k].size();
     b.cjob0 = cj;
@@ -825,6 +901,8 @@ int cavdftb_create(const cavdftb_params* params, const cavdftb_layout* L, void* 
       for (int a = c->h_unit_off[u]; a < c->h_unit_off[u + 1]; ++a) norb += L->species[a] == 0 ? 4 : 1;
       const double f = (double)norb / b.nmax;
       cost_scale[u] = (float)(f * f * f);
+      const double g = (double)norb / 48.0;
+      b.cost += g * g * g;
     }
     CK(dalloc(c, &b.d_order, b.n_units));
     CK(dalloc(c, &b.d_order_tmp, b.n_units));
@@ -973,6 +1051,14 @@ int cavdftb_set_bucket_schedule(cavdftb_ctx* ctx, int32_t bucket_orbitals, int32
   return CAVDFTB_OK;
 }
 
+int cavdftb_set_bucket_streams(cavdftb_ctx* ctx, int32_t n_streams) {
+  if (!ctx) return CAVDFTB_EINVAL;
+  if (n_streams < 1 || n_streams > 4) return fail(ctx, CAVDFTB_EINVAL, "set_bucket_streams: need 1 <= n <= 4");
+  ctx->n_streams = n_streams;
+  ctx->gen += 1;
+  return CAVDFTB_OK;
+}
+
 int cavdftb_bucket_info(cavdftb_ctx* ctx, int32_t bucket_orbitals, int32_t* n_units, int32_t* wg_per_cu_max,
                         int32_t* wg_per_cu) {
   if (!ctx || bucket_of(bucket_orbitals) != bucket_orbitals) return CAVDFTB_EINVAL;
@@ -1077,7 +1163,11 @@ int cavdftb_eval_units(cavdftb_ctx* ctx, const double* pos, double* energy, doub
   ctx->gen += 1;
   const bool want_f = energy || forces;
   const int32_t flags = center_flags(ctx, want_f);
-  for (const Bucket& b : ctx->buckets) {
+  BucketFan fan(ctx);
+  if (int rc = fan.fork()) return rc;
+  for (int bi : fan.order) {
+    const Bucket& b = ctx->buckets[bi];
+    hipStream_t bs = fan.stream_for(b);
     SccArgs a = base_args(ctx, pos);
     a.job_unit = b.d_units;
     a.n_jobs = b.n_units;
@@ -1089,9 +1179,10 @@ int cavdftb_eval_units(cavdftb_ctx* ctx, const double* pos, double* energy, doub
     a.job_status = ctx->d_cjob_status + b.cjob0;
     a.job_iters = ctx->d_cjob_iters + b.cjob0;
     a.flags = flags;
-    int rc = run_scc(ctx, b, a);
+    int rc = run_scc(ctx, b, a, bs);
     if (rc) return rc;
   }
+  if (int rc = fan.join()) return rc;
   ctx->warm_valid = ctx->warm_enabled != 0;
   ctx->primed = false;
   ctx->rs_primed = false;

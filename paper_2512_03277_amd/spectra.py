@@ -87,6 +87,18 @@ def centroid(freq, I, lo, hi):
     return float(np.sum(freq[m] * w) / np.sum(w))
 
 
+def overlap(freq, Ia, Ib, lo, hi):
+    """Normalised overlap sum(Ia Ib) / sqrt(sum(Ia^2) sum(Ib^2)) of two spectra on
+    the same grid over lo <= freq <= hi: 1 for spectra of the same shape, whatever
+    their scale; it weighs the whole band, not only its largest line."""
+    freq = np.asarray(freq)
+    m = (freq >= lo) & (freq <= hi)
+    if not np.any(m):
+        raise ValueError("no frequencies in the band")
+    a, b = np.asarray(Ia)[m], np.asarray(Ib)[m]
+    return float(np.sum(a * b) / np.sqrt(np.sum(a * a) * np.sum(b * b)))
+
+
 def resolution_cm(n_samples, dt):
     """Frequency resolution 2 pi / (T dt) of a run of n_samples steps, in cm^-1."""
     return 2.0 * np.pi / (n_samples * dt) * HARTREE_CM
@@ -97,14 +109,18 @@ def report_from_acf(Ca, Cb, dt, lo, hi, n_samples):
     autocorrelations: the largest peak in [lo, hi] cm^-1 of each, and the first
     moment of each spectrum over that same fixed band (it depends on neither
     run; a peak can jump between neighbouring maxima of a broad noisy band, the
-    centroid cannot).  The resolution 2 pi / (n_samples dt) is returned beside
-    them; neither position is meaningful to much better than a fraction of it."""
+    centroid cannot); the two strongest lines of each (top_peaks) and the
+    normalised overlap of the two spectra over the band.  The resolution
+    2 pi / (n_samples dt) is returned beside them; no position is meaningful to
+    much better than a fraction of it."""
     fa, Ia = spectrum(Ca, dt)
     fb, Ib = spectrum(Cb, dt)
     pa, pb = peak(fa, Ia, lo, hi), peak(fb, Ib, lo, hi)
     ca, cb = centroid(fa, Ia, lo, hi), centroid(fb, Ib, lo, hi)
     return {"peak_a_cm": pa, "peak_b_cm": pb, "shift_cm": pa - pb,
             "centroid_a_cm": ca, "centroid_b_cm": cb, "centroid_shift_cm": ca - cb,
+            "lines_a_cm": top_peaks(fa, Ia, lo, hi), "lines_b_cm": top_peaks(fb, Ib, lo, hi),
+            "overlap": overlap(fa, Ia, Ib, lo, hi),
             "band_cm": [lo, hi], "resolution_cm": resolution_cm(n_samples, dt)}
 
 

@@ -371,3 +371,33 @@ def test_eigensolver_modes_agree(params):
             assert np.max(np.abs(a["charges"] - b["charges"])) <= 1e-10
             assert np.max(np.abs(a["energy"] - b["energy"])) <= 1e-12 * np.max(np.abs(a["energy"]))
             assert np.max(np.abs(a["forces"] - b["forces"])) <= 1e-9 * np.max(np.abs(a["forces"]))
+
+
+def test_bucket_streams_leave_results_unchanged(params):
+    # the bucket launches of an evaluation on 1 stream or spread over 4: the
+    # buckets hold disjoint units, so every result bit is the same, for MD steps
+    # (eager and graph-replayed) and for a plain evaluation
+    s = subsystem(make_system(4, n_units=120), list(range(0, 120, 5)))
+    ctx = make_ctx(params, s)
+    assert sum(ctx.bucket_info(b)[0] > 0 for b in cd.binding.BUCKETS) >= 4
+    with pytest.raises(cd.CavdftbError):
+        ctx.set_bucket_streams(0)
+    with pytest.raises(cd.CavdftbError):
+        ctx.set_bucket_streams(5)
+    ctx.close()
+    runs = {}
+    for n in (1, 4):
+        for graph in (False, True):
+            runs[n, graph] = _gpu_md(params, s, cd.BORN_MULLIKEN, 6, graph=graph,
+                                     setup=lambda c, n=n: c.set_bucket_streams(n))[0]
+    for key, out in runs.items():
+        for name, a, b in zip(("r", "p", "qm", "pm", "obs"), runs[1, False], out):
+            assert np.array_equal(a, b), (key, name)
+    evals = []
+    for n in (1, 4):
+        ctx = make_ctx(params, s)
+        ctx.set_bucket_streams(n)
+        evals.append(gpu_eval(ctx, s["pos"]))
+        ctx.close()
+    for k in evals[0]:
+        assert np.array_equal(evals[0][k], evals[1][k]), k

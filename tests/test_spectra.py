@@ -187,3 +187,20 @@ def test_combine_spectra_averages_starts_with_fixed_band():
     assert rep["polariton_peak_exact_cm"] == pytest.approx(1.3 * nu, abs=3.0)
     assert rep["ir_shift_cm"] == 0.0 and rep["ir_centroid_shift_cm"] == 0.0 and rep["ir_band_cm"] == [1000.0, 4500.0]
     assert rep["ir_shift_single_starts_cm"] == [0.0, 0.0] and rep["starts"] == [0, 1]
+    assert rep["ir_overlap"] == pytest.approx(1.0) and rep["polariton_overlap"] == pytest.approx(1.0)
+    assert len(rep["ir_lines_exact_cm"]) >= 1 and rep["ir_lines_exact_cm"][0] == pytest.approx(nu, abs=2.0)
+
+
+def test_overlap_of_spectra():
+    t = np.arange(4000) * DT
+    f, Ia = spectra.spectrum(spectra.autocorrelation(np.cos(1600.0 / spectra.HARTREE_CM * t)), DT,
+                             omega_squared=False)
+    _, Ib = spectra.spectrum(spectra.autocorrelation(np.cos(1900.0 / spectra.HARTREE_CM * t)), DT,
+                             omega_squared=False)
+    # the same shape at any scale overlaps fully; separated lines hardly at all
+    assert spectra.overlap(f, Ia, 3.0 * Ia, 1000.0, 2500.0) == pytest.approx(1.0)
+    assert spectra.overlap(f, Ia, Ib, 1000.0, 2500.0) < 0.05
+    # a line against itself plus a second, equal line: 1 / sqrt(2) to within the side lobes
+    assert spectra.overlap(f, Ia, Ia + Ib, 1000.0, 2500.0) == pytest.approx(2 ** -0.5, abs=0.03)
+    with pytest.raises(ValueError):
+        spectra.overlap(f, Ia, Ib, -2.0, -1.0)
