@@ -3,18 +3,25 @@
 The exact Born charges are the method's bottleneck (Results: the dipole
 derivatives are evaluated numerically and dominate the cost; Conclusion).  The
 surrogate replaces them by a small ensemble of per-species neural networks on
-rotation-invariant radial descriptors, with exact finite differences as the
+rotation-invariant descriptors, with exact finite differences as the
 fallback where the ensemble disagrees.  Concrete form (the paper gives none;
 each choice below is a reading, not the paper's):
 
-  descriptors  G[A, s*16 + k] = sum_{B != A, species B = s, R_AB < Rc}
-                   exp(-(R_AB - r_k)^2 / (2 sigma^2)) * (cos(pi R_AB / Rc) + 1) / 2
-               16 centres r_k uniform on [0.5, 6] A per neighbour species,
-               sigma = grid spacing, Rc = 6 A: 32 inputs per atom.
   local frame  O: e1 = bisector of the two nearest H, e2 = normal of their
                plane; H: e1 = direction nearest O -> H, e2 = normal of the plane
                of that O and its two nearest H; e3 = e1 x e2.  R = [e1 e2 e3].
-  network      per central species, per member: 32 -> 128 SiLU -> 128 SiLU -> 9,
+               Fragments that lack those atoms take the lab frame (local_frames).
+  descriptors  radial comb, columns s*16 + k:
+                 sum_{B != A, species B = s, R_AB < Rc} g_k(R_AB) fc(R_AB),
+                 g_k(r) = exp(-(r - r_k)^2 / (2 sigma^2)), fc(r) = (cos(pi r / Rc) + 1) / 2,
+                 16 centres r_k uniform on [0.5, 6] A, sigma = their spacing, Rc = 6 A;
+               direction moments in the atom's own frame, columns 32 + s*24 + 3k + i:
+                 sum_B g'_k(R_AB) fc(R_AB) (e_i . u_AB), u_AB the unit vector A -> B,
+                 on 8 centres uniform on [0.5, 6] A (sigma' their spacing).
+               80 inputs per atom.  The moments see where the neighbouring
+               molecules sit relative to the atom's own molecule (hydrogen-bond
+               geometry), which the radial comb cannot.
+  network      per central species, per member: 80 -> 128 SiLU -> 128 SiLU -> 9,
                on standardised inputs x = (G - mu_x) / sd_x; the 9 outputs y
                give dZ_loc = (y * y_scale + y_mean) reshaped 3 x 3 (row-major),
                the correction to the paper's Mulliken replacement Q_A I in the
@@ -28,7 +35,8 @@ each choice below is a reading, not the paper's):
                Adam with FP32 master weights, BF16 operands at every matrix
                product (round to nearest even), FP32 accumulation.
 
-Pinned by: descriptor invariances and cutoff smoothness, orthonormal
+Pinned by: descriptor invariances (rigid motions, permutations), cutoff
+smoothness, the radial comb sum and the moments of one neighbour, orthonormal
 right-handed frames that rotate with the molecule, backward pass against
 central finite differences, equivariance Z(QR) = Q Z(R) Q^T and an exact
 acoustic sum rule, BF16 rounding against torch's bfloat16 conversion, and the
@@ -43,7 +51,10 @@ N_RAD = 16
 RC = 6.0 * ANG
 CENTRES = np.linspace(0.5, 6.0, N_RAD) * ANG
 SIGMA = CENTRES[1] - CENTRES[0]
-N_IN, N_HID, N_OUT = 32, 128, 9
+N_VEC = 8  # Gaussians of the direction moments
+CENTRES_V = np.linspace(0.5, 6.0, N_VEC) * ANG
+SIGMA_V = CENTRES_V[1] - CENTRES_V[0]
+N_IN, N_HID, N_OUT = 2 * N_RAD + 2 * 3 * N_VEC, 128, 9
 # flat parameter layout of one network
 SHAPES = (("W1", (N_IN, N_HID)), ("b1", (N_HID,)), ("W2", (N_HID, N_HID)), ("b2", (N_HID,)),
           ("W3", (N_HID, N_OUT)), ("b3", (N_OUT,)))
@@ -91,21 +102,32 @@ def cutoff(r):
     return np.where(r < RC, 0.5 * (np.cos(np.pi * r / RC) + 1.0), 0.0)
 
 
-def descriptors(species, pos):
+def descriptors(species, pos, frames=None):
+    """G (Na, N_IN): the radial comb of each neighbour species (columns
+    s*16 + k) and the frame-resolved first moments (columns 32 + s*24 + 3k + i)
+    of the neighbours' directions, sum_B g_k(R_AB) fc(R_AB) (e_i(A) . u_AB),
+    u_AB = (R_B - R_A) / R_AB, on an 8-Gaussian comb.  frames: local_frames of
+    the unit (computed when not given)."""
     species = np.asarray(species)
     pos = np.asarray(pos, dtype=np.float64)
     na = len(species)
+    R = local_frames(species, pos) if frames is None else np.asarray(frames)
     G = np.zeros((na, N_IN))
     for a in range(na):
         for b in range(na):
             if a == b:
                 continue
-            r = float(np.linalg.norm(pos[b] - pos[a]))
+            d = pos[b] - pos[a]
+            r = float(np.linalg.norm(d))
             if r >= RC:
                 continue
             fc = 0.5 * (math.cos(math.pi * r / RC) + 1.0)
             g = np.exp(-(r - CENTRES) ** 2 / (2.0 * SIGMA ** 2)) * fc
             G[a, species[b] * N_RAD:(species[b] + 1) * N_RAD] += g
+            ga = np.exp(-(r - CENTRES_V) ** 2 / (2.0 * SIGMA_V ** 2)) * fc
+            u = R[a].T @ (d / r)  # direction in the atom's frame
+            o = 2 * N_RAD + species[b] * 3 * N_VEC
+            G[a, o:o + 3 * N_VEC] += np.outer(ga, u).ravel()
     return G
 
 
@@ -119,8 +141,18 @@ def _nearest(pos, a, cand):
     return [c for _, c in d]
 
 
+def _complete(e1):
+    """A unit e2 normal to e1: the lab y axis (z when y is within 0.9 of e1)
+    with its e1 part removed."""
+    t = np.array([0.0, 1.0, 0.0]) if abs(e1[1]) <= 0.9 else np.array([0.0, 0.0, 1.0])
+    return _unit(t - (t @ e1) * e1)
+
+
 def local_frames(species, pos):
-    """R (Na, 3, 3) with columns e1, e2, e3 in lab coordinates."""
+    """R (Na, 3, 3) with columns e1, e2, e3 in lab coordinates.  Fragments
+    without the atoms a frame needs (an O with fewer than two H, an H without
+    an O) take the lab frame; an H whose O has no second H takes e2 from
+    _complete(e1)."""
     species = np.asarray(species)
     pos = np.asarray(pos, dtype=np.float64)
     na = len(species)
@@ -128,17 +160,23 @@ def local_frames(species, pos):
     Os = [i for i in range(na) if species[i] == 0]
     R = np.zeros((na, 3, 3))
     for a in range(na):
+        e1, e2 = np.array([1.0, 0.0, 0.0]), np.array([0.0, 1.0, 0.0])
         if species[a] == 0:
-            h1, h2 = _nearest(pos, a, Hs)[:2]
-            u1, u2 = _unit(pos[h1] - pos[a]), _unit(pos[h2] - pos[a])
-            e1 = _unit(u1 + u2)
-            e2 = _unit(np.cross(u1, u2))
-        else:
+            near = _nearest(pos, a, Hs)
+            if len(near) >= 2:
+                h1, h2 = near[:2]
+                u1, u2 = _unit(pos[h1] - pos[a]), _unit(pos[h2] - pos[a])
+                e1 = _unit(u1 + u2)
+                e2 = _unit(np.cross(u1, u2))
+        elif Os:
             o = _nearest(pos, a, Os)[0]
             e1 = _unit(pos[a] - pos[o])
-            hh = [h for h in _nearest(pos, o, Hs) if h != a][0]
-            e2 = _unit(np.cross(pos[a] - pos[o], pos[hh] - pos[o]))
-            e2 = _unit(e2 - (e2 @ e1) * e1)
+            others = [h for h in _nearest(pos, o, Hs) if h != a]
+            if others:
+                e2 = _unit(np.cross(pos[a] - pos[o], pos[others[0]] - pos[o]))
+                e2 = _unit(e2 - (e2 @ e1) * e1)
+            else:
+                e2 = _complete(e1)
         e3 = np.cross(e1, e2)
         R[a] = np.stack([e1, e2, e3], axis=1)
     return R
@@ -155,7 +193,7 @@ def dsilu(z):
 
 
 def forward(theta, x, emulate_bf16=False):
-    """x (n, 32) standardised inputs -> y (n, 9); returns (y, cache)."""
+    """x (n, N_IN) standardised inputs -> y (n, 9); returns (y, cache)."""
     p = unpack(theta)
     q = bf16 if emulate_bf16 else (lambda v: v)
     z1 = q(x) @ q(p["W1"]) + p["b1"]
@@ -206,8 +244,8 @@ def predict_unit(species, pos, nets, norms, charges, emulate_bf16=False):
     Returns the ensemble mean Born tensors after the acoustic-sum projection
     (Na,3,3) and the per-atom per-component ensemble standard deviation."""
     species = np.asarray(species)
-    G = descriptors(species, pos)
     R = local_frames(species, pos)
+    G = descriptors(species, pos, R)
     na = len(species)
     members = len(nets[0])
     Zm = np.zeros((members, na, 3, 3))

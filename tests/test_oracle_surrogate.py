@@ -34,9 +34,58 @@ def test_descriptors_invariant_and_cut_off(cluster):
     # one neighbour: the Gaussian comb sums to ~ fc(R) sqrt(2 pi) sigma / spacing in the grid interior
     r = 3.0 * sg.ANG
     two = np.array([[0.0, 0.0, 0.0], [r, 0.0, 0.0]])
-    g = sg.descriptors(np.array([0, 1]), two)[0]
+    G2 = sg.descriptors(np.array([0, 1]), two)
+    g = G2[0]
+    fc = sg.cutoff(np.array([r]))[0]
     assert g[:16].sum() == 0.0
-    assert g[16:].sum() == pytest.approx(sg.cutoff(np.array([r]))[0] * np.sqrt(2 * np.pi), rel=1e-3)
+    assert g[16:32].sum() == pytest.approx(fc * np.sqrt(2 * np.pi), rel=1e-3)
+    # direction moments of that neighbour: the O (one H: lab frame) sees it along +x,
+    # the H (frame e1 = O -> H = +x) sees the O along -x; the 8-Gaussian comb sums
+    # to ~ fc sqrt(2 pi) as well, and the other components vanish
+    vo = g[32:].reshape(2, 8, 3)
+    assert np.all(vo[0] == 0.0) and np.all(vo[1][:, 1:] == 0.0)
+    assert vo[1][:, 0].sum() == pytest.approx(fc * np.sqrt(2 * np.pi), rel=2e-2)
+    vh = G2[1][32:].reshape(2, 8, 3)
+    assert np.all(vh[1] == 0.0)
+    assert vh[0][:, 0].sum() == pytest.approx(-fc * np.sqrt(2 * np.pi), rel=2e-2)
+    assert np.allclose(vh[0][:, 1:], 0.0, atol=1e-15)
+
+
+def test_direction_moments_mirror_across_the_molecular_plane():
+    # a water in the xy plane (bisector +x, normal along z) and one more O above or
+    # below that plane at mirror positions: only the component along the normal
+    # (e2) changes sign; the radial comb and the in-plane components do not
+    a = sg.ANG
+    th = np.deg2rad(52.0)
+    wat = np.array([[0.0, 0.0, 0.0], [0.96 * a * np.cos(th), 0.96 * a * np.sin(th), 0.0],
+                    [0.96 * a * np.cos(th), -0.96 * a * np.sin(th), 0.0]])
+    sp = np.array([0, 1, 1, 0])
+    up = np.vstack([wat, [[2.9 * a, 0.8 * a, 1.1 * a]]])
+    dn = np.vstack([wat, [[2.9 * a, 0.8 * a, -1.1 * a]]])
+    Gu, Gd = sg.descriptors(sp, up)[0], sg.descriptors(sp, dn)[0]
+    R = sg.local_frames(sp, up)[0]
+    assert np.allclose(R[:, 0], [1.0, 0.0, 0.0], atol=1e-14) and abs(abs(R[2, 1]) - 1.0) < 1e-14
+    assert np.array_equal(Gu[:32], Gd[:32])
+    mu, md = Gu[32:].reshape(2, 8, 3), Gd[32:].reshape(2, 8, 3)
+    assert np.allclose(mu[:, :, [0, 2]], md[:, :, [0, 2]], atol=1e-15)
+    assert np.allclose(mu[:, :, 1], -md[:, :, 1], atol=1e-15)
+    assert np.abs(mu[0, :, 1]).max() > 1e-3  # the O neighbour's normal component is there
+
+
+def test_frames_of_fragments():
+    # an O with one H and a lone H take the lab frame; an H whose O has no second
+    # H keeps e1 = O -> H and an e2 normal to it
+    a = sg.ANG
+    sp = np.array([0, 1, 1])
+    pos = np.array([[0.0, 0.0, 0.0], [0.6 * a, 0.7 * a, 0.2 * a], [9.0 * a, 0.0, 0.0]])
+    R = sg.local_frames(sp[:2], pos[:2])
+    assert np.array_equal(R[0], np.eye(3))
+    e1 = pos[1] / np.linalg.norm(pos[1])
+    Rh = R[1]
+    assert np.allclose(Rh[:, 0], e1, atol=1e-15)
+    assert np.allclose(Rh.T @ Rh, np.eye(3), atol=1e-14) and np.linalg.det(Rh) == pytest.approx(1.0, abs=1e-14)
+    Rl = sg.local_frames(np.array([1, 1]), pos[1:])
+    assert np.array_equal(Rl[0], np.eye(3)) and np.array_equal(Rl[1], np.eye(3))
 
 
 def test_frames_orthonormal_right_handed_and_covariant(cluster):
@@ -80,7 +129,7 @@ def test_prediction_equivariant_with_exact_sum_rule(cluster):
     sp, pos = cluster
     rng = np.random.default_rng(4)
     nets = [[sg.init_params(rng) for _ in range(4)] for _ in range(2)]
-    norms = [{"x_mean": np.zeros(32), "x_std": np.ones(32), "y_mean": np.zeros(9), "y_scale": np.full(9, 0.3)}
+    norms = [{"x_mean": np.zeros(sg.N_IN), "x_std": np.ones(sg.N_IN), "y_mean": np.zeros(9), "y_scale": np.full(9, 0.3)}
              for _ in range(2)]
     q = np.where(np.asarray(sp) == 0, -0.5, 0.25)
     Z, std = sg.predict_unit(sp, pos, nets, norms, q)
