@@ -64,16 +64,18 @@ extern "C" {
 #define CAVDFTB_BORN_FIELD 3     /* exact, from the force response to a uniform field (Maxwell relation) */
 #define CAVDFTB_BORN_FD_FORWARD 4 /* forward differences of the SCC dipole (the paper's own scheme) */
 
-/* Surrogate network: per species (O, H) and member, 32 -> 128 SiLU -> 128
- * SiLU -> 9, flat FP32 parameters [W1 (32x128, row = input) | b1 | W2 (128x128)
- * | b2 | W3 (128x9) | b3]; normalisation per species [x_mean 32 | x_std 32 |
- * y_mean 9 | y_scale 9]. */
-#define CAVDFTB_SG_N_IN 32
+/* Surrogate network: per species (O, H) and member, 80 -> 128 SiLU -> 128
+ * SiLU -> 9, flat FP32 parameters [W1 (80x128, row = input) | b1 | W2 (128x128)
+ * | b2 | W3 (128x9) | b3]; normalisation per species [x_mean 80 | x_std 80 |
+ * y_mean 9 | y_scale 9].  The 80 inputs per atom: 16 radial Gaussians per
+ * neighbour species, then 8 Gaussians x 3 frame components of the neighbour
+ * directions per neighbour species (cavdftb_sg_features). */
+#define CAVDFTB_SG_N_IN 80
 #define CAVDFTB_SG_N_HID 128
 #define CAVDFTB_SG_N_OUT 9
 #define CAVDFTB_SG_MEMBERS 4
-#define CAVDFTB_SG_N_PARAM 21897
-#define CAVDFTB_SG_N_NORM 82
+#define CAVDFTB_SG_N_PARAM 28041
+#define CAVDFTB_SG_N_NORM 178
 
 #define CAVDFTB_MAX_ORBITALS 192
 
@@ -329,16 +331,19 @@ int cavdftb_cavity_forces(cavdftb_ctx* ctx, const double* mu_pol, const double* 
  * FP32 [2 species][CAVDFTB_SG_MEMBERS][CAVDFTB_SG_N_PARAM]), norm (device FP32
  * [2][CAVDFTB_SG_N_NORM]), and the fallback threshold on the ensemble standard
  * deviation (elementary charges).
- * cavdftb_sg_features: per atom the 32 radial descriptors (16 Gaussians of
- * width 0.367 A on [0.5, 6] A per neighbour species, cosine cutoff at 6 A) and
- * the local frame R = [e1 e2 e3] (row-major 3x3; O: bisector of its two
- * nearest H and their plane normal, H: nearest O -> H and the plane normal of
- * that water), device FP64 [n_atoms][32] and [n_atoms][9].
+ * cavdftb_sg_features: per atom the local frame R = [e1 e2 e3] (row-major
+ * 3x3; O: bisector of its two nearest H and their plane normal, H: nearest
+ * O -> H and the plane normal of that water; fragments lacking those atoms
+ * take the lab frame) and the 80 descriptors over the unit's atoms within a
+ * cosine cutoff at 6 A: columns s*16 + k, 16 Gaussians of width 0.367 A on
+ * [0.5, 6] A per neighbour species s; columns 32 + s*24 + 3k + i, the
+ * neighbour directions' components along e_i weighted by 8 Gaussians of width
+ * 0.786 A on [0.5, 6] A.  Device FP64 [n_atoms][80] and [n_atoms][9].
  * The remaining calls work on plain device arrays on the given stream (a
  * hipStream_t or NULL) and train one network (BF16 operands, FP32
  * accumulation, FP32 master weights):
  *   sg_prep     x[i][k] = (v[idx[i]][k] - norm[k]) / norm[width + k]  (FP64 in, FP32 out; idx may be NULL)
- *   sg_forward  y [n][9] from x [n][32]; act [n][256] keeps the pre-activations for sg_backward (or NULL)
+ *   sg_forward  y [n][9] from x [n][80]; act [n][256] keeps the pre-activations for sg_backward (or NULL)
  *   sg_backward grad [N_PARAM] of sum(dy . y); work holds ceil(n/64) x N_PARAM partial sums
  *   sg_mse      loss[0] = mean (y - t)^2 over count values, dy = 2 (y - t) / count; work >= ceil(count/256)
  *   sg_adam     Adam (Kingma & Ba) on count parameters, step = 1, 2, ...
@@ -374,7 +379,7 @@ int cavdftb_sg_to_local(const double* frames, const double* born, const double* 
  * tile reduction, so grad equals cavdftb_sg_backward's bit for bit, but the
  * per-tile partial gradients live in a file-scope device array of the library
  * (CAVDFTB_SG_NOALLOC_MAX_ROWS rows: ceil(n / 64) x CAVDFTB_SG_N_PARAM floats,
- * 11.2 MB per GPU, held until the process ends) instead of a caller's work
+ * 14.4 MB per GPU, held until the process ends) instead of a caller's work
  * buffer.  Arguments as in cavdftb_sg_backward (device pointers, stream a
  * hipStream_t or NULL).  CAVDFTB_EINVAL for a null pointer, n <= 0 or
  * n > CAVDFTB_SG_NOALLOC_MAX_ROWS; CAVDFTB_EHIP if the array's device address

@@ -74,6 +74,14 @@ def pack(d):
     return np.concatenate([np.asarray(d[name], dtype=np.float64).ravel() for name, _ in SHAPES])
 
 
+def unpack_norm(v):
+    """The normalisation of one species from its flat layout
+    [x_mean (N_IN) | x_std (N_IN) | y_mean (9) | y_scale (9)]."""
+    v = np.asarray(v, dtype=np.float64)
+    return {"x_mean": v[:N_IN], "x_std": v[N_IN:2 * N_IN], "y_mean": v[2 * N_IN:2 * N_IN + N_OUT],
+            "y_scale": v[2 * N_IN + N_OUT:2 * N_IN + 2 * N_OUT]}
+
+
 def init_params(rng):
     """He-style uniform initialisation of one network."""
     d = {}

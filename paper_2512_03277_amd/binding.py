@@ -17,7 +17,7 @@ OK, EINVAL, ENOMEM, EHIP = 0, -1, -2, -3
 SG_NOALLOC_MAX_ROWS = 8192
 ST_NOT_CONVERGED, ST_NOT_PD, ST_DEGENERATE, ST_NAN = 1, 2, 4, 8
 BORN_MULLIKEN, BORN_FD, BORN_SURROGATE, BORN_FIELD, BORN_FD_FORWARD = 0, 1, 2, 3, 4
-SG_N_IN, SG_N_HID, SG_N_OUT, SG_MEMBERS, SG_N_PARAM, SG_N_NORM = 32, 128, 9, 4, 21897, 82
+SG_N_IN, SG_N_HID, SG_N_OUT, SG_MEMBERS, SG_N_PARAM, SG_N_NORM = 80, 128, 9, 4, 28041, 178
 N_OBS = 8
 WORK_MU_POL, WORK_DIPOLE, WORK_ENERGY, WORK_CHARGES, WORK_FORCES, WORK_FIELD = range(6)
 EIG_AUTO, EIG_FULL, EIG_JACOBI = 0, 1, 2

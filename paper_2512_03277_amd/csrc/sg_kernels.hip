@@ -2,8 +2,8 @@
 //
 // The paper obtains the Born charges by finite differences and names them the
 // bottleneck of the method (Results; Conclusion).  These kernels evaluate and
-// train the replacement: radial descriptors and atom-local frames, a per-species
-// 32 -> 128 -> 128 -> 9 SiLU network ensemble with BF16 operands and FP32
+// train the replacement: radial and frame-resolved direction descriptors and
+// atom-local frames, a per-species 80 -> 128 -> 128 -> 9 SiLU network ensemble with BF16 operands and FP32
 // accumulation (the products of the forward and backward passes on the matrix
 // cores), the ensemble mean/spread with the acoustic-sum projection, and
 // the Adam update of the FP32 master weights.  Every reduction has a fixed
@@ -22,10 +22,13 @@ constexpr int NIN = CAVDFTB_SG_N_IN, NHID = CAVDFTB_SG_N_HID, NOUT = CAVDFTB_SG_
 constexpr int OFF_W1 = 0, OFF_B1 = OFF_W1 + NIN * NHID, OFF_W2 = OFF_B1 + NHID, OFF_B2 = OFF_W2 + NHID * NHID,
               OFF_W3 = OFF_B2 + NHID, OFF_B3 = OFF_W3 + NHID * NOUT, NPAR = OFF_B3 + NOUT;
 static_assert(NPAR == CAVDFTB_SG_N_PARAM, "parameter layout");
-static_assert(NIN == 32, "descriptors: 16 radial Gaussians for each of the two species");
-constexpr int TILE = 64;  // atoms per workgroup
-constexpr int kForwardGrid = 512;  // persistent workgroups of the forward pass (two fit in a CU's LDS)
+static_assert(NIN == 80, "descriptors: per neighbour species 16 radial Gaussians and 8 x 3 direction moments");
+constexpr int TILE = 64;  // atoms per workgroup of the backward pass
 constexpr int NT = 256;
+// forward pass: 512-thread workgroups on 128-atom tiles (16 atoms per wave),
+// one per CU (124 KB of LDS), persistent over the tiles
+constexpr int FNT = 512, FTILE = 128;
+constexpr int kForwardGrid = 256;
 
 constexpr double kAng = 1.8897261246;
 
@@ -79,62 +82,27 @@ __device__ void nearest2(const double* pos, const int8_t* species, int a0, int a
   }
 }
 
-__global__ __launch_bounds__(NT) void features_kernel(int n_atoms, const int32_t* __restrict__ atom_unit,
-                                                      const int32_t* __restrict__ unit_off,
-                                                      const int8_t* __restrict__ species,
-                                                      const double* __restrict__ pos, double* __restrict__ feat,
-                                                      double* __restrict__ frames) {
-  const int a = blockIdx.x * NT + threadIdx.x;
-  if (a >= n_atoms) return;
-  const int u = atom_unit[a];
-  const int a0 = unit_off[u], a1 = unit_off[u + 1];
-  const double rc = 6.0 * kAng;
-  const double r0 = 0.5 * kAng, dr = (6.0 - 0.5) * kAng / 15.0;
-  // the 16 Gaussians of each neighbour species in two register arrays indexed
-  // at compile time only (a runtime-indexed array would live in scratch memory)
-  double gO[16], gH[16];
-#pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    gO[k] = 0.0;
-    gH[k] = 0.0;
+// e2 for an H whose O has no second H: the lab y axis (z when y is within 0.9
+// of e1) with its e1 part removed
+__device__ void complete_frame(const double e1[3], double e2[3]) {
+  const bool use_y = fabs(e1[1]) <= 0.9;
+  const double t[3] = {0.0, use_y ? 1.0 : 0.0, use_y ? 0.0 : 1.0};
+  const double p = t[0] * e1[0] + t[1] * e1[1] + t[2] * e1[2];
+  for (int c = 0; c < 3; ++c) e2[c] = t[c] - p * e1[c];
+  unit3(e2);
+}
+
+// the atom's frame R = [e1 e2 e3].  O: e1 = bisector of the two nearest H,
+// e2 = normal of their plane; H: e1 = nearest O -> H, e2 = normal of the plane
+// of that O, the H and the O's nearest other H.  An O with fewer than two H and
+// an H without an O keep the lab frame; an H whose O has no other H takes e2
+// from complete_frame.
+__device__ void atom_frame(const double* pos, const int8_t* species, int a0, int a1, int a, double e1[3],
+                           double e2[3], double e3[3]) {
+  for (int c = 0; c < 3; ++c) {
+    e1[c] = c == 0 ? 1.0 : 0.0;
+    e2[c] = c == 1 ? 1.0 : 0.0;
   }
-  for (int b = a0; b < a1; ++b) {
-    if (b == a) continue;
-    const double dx = pos[b * 3] - pos[a * 3], dy = pos[b * 3 + 1] - pos[a * 3 + 1], dz = pos[b * 3 + 2] - pos[a * 3 + 2];
-    const double r = sqrt(dx * dx + dy * dy + dz * dz);
-    if (r >= rc) continue;
-    const double fc = 0.5 * (cos(M_PI * r / rc) + 1.0);
-    const int s = species[b];
-    // Gaussians exp(-(v - k)^2 / 2) at v = (r - r0) / dr for k = 0..15 by the
-    // exact product recurrence g_{k+1} = g_k exp(v - k - 1/2): two exponentials
-    // per pair instead of sixteen
-    const double v = (r - r0) / dr;
-    double gk = exp(-0.5 * v * v) * fc, ck = exp(v - 0.5);
-    constexpr double kInvE = 0.36787944117144233;  // exp(-1)
-    if (s == 0) {
-#pragma unroll
-      for (int k = 0; k < 16; ++k) {
-        gO[k] += gk;
-        gk *= ck;
-        ck *= kInvE;
-      }
-    } else {
-#pragma unroll
-      for (int k = 0; k < 16; ++k) {
-        gH[k] += gk;
-        gk *= ck;
-        ck *= kInvE;
-      }
-    }
-  }
-  if (feat)
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      feat[(int64_t)a * NIN + k] = gO[k];
-      feat[(int64_t)a * NIN + 16 + k] = gH[k];
-    }
-  if (!frames) return;
-  double e1[3] = {1, 0, 0}, e2[3] = {0, 1, 0}, e3[3];
   if (species[a] == 0) {
     int h1, h2;
     nearest2(pos, species, a0, a1, a, 1, -1, h1, h2);
@@ -168,14 +136,113 @@ __global__ __launch_bounds__(NT) void features_kernel(int n_atoms, const int32_t
         const double pr = e2[0] * e1[0] + e2[1] * e1[1] + e2[2] * e1[2];
         for (int c = 0; c < 3; ++c) e2[c] -= pr * e1[c];
         unit3(e2);
+      } else {
+        complete_frame(e1, e2);
       }
     }
   }
   cross3(e1, e2, e3);
-  for (int c = 0; c < 3; ++c) {  // R = [e1 e2 e3], row-major R[c][j]
-    frames[(int64_t)a * 9 + c * 3 + 0] = e1[c];
-    frames[(int64_t)a * 9 + c * 3 + 1] = e2[c];
-    frames[(int64_t)a * 9 + c * 3 + 2] = e3[c];
+}
+
+// Descriptors of one atom per thread, over the atoms of its unit within 6 A:
+//   columns s*16 + k        radial comb: sum_B g_k(R_AB) fc(R_AB), 16 Gaussians
+//   columns 32 + s*24 + 3k + i  direction moments in the atom's frame:
+//                           sum_B g'_k(R_AB) fc(R_AB) (e_i . u_AB), 8 Gaussians
+// (s = species of B, u_AB the unit vector A -> B), and the frame itself.
+__global__ __launch_bounds__(NT) void features_kernel(int n_atoms, const int32_t* __restrict__ atom_unit,
+                                                      const int32_t* __restrict__ unit_off,
+                                                      const int8_t* __restrict__ species,
+                                                      const double* __restrict__ pos, double* __restrict__ feat,
+                                                      double* __restrict__ frames) {
+  const int a = blockIdx.x * NT + threadIdx.x;
+  if (a >= n_atoms) return;
+  const int u = atom_unit[a];
+  const int a0 = unit_off[u], a1 = unit_off[u + 1];
+  double e1[3], e2[3], e3[3];
+  atom_frame(pos, species, a0, a1, a, e1, e2, e3);
+  if (frames)
+    for (int c = 0; c < 3; ++c) {  // R = [e1 e2 e3], row-major R[c][j]
+      frames[(int64_t)a * 9 + c * 3 + 0] = e1[c];
+      frames[(int64_t)a * 9 + c * 3 + 1] = e2[c];
+      frames[(int64_t)a * 9 + c * 3 + 2] = e3[c];
+    }
+  if (!feat) return;
+  const double rc = 6.0 * kAng;
+  const double r0 = 0.5 * kAng, dr = (6.0 - 0.5) * kAng / 15.0, drv = (6.0 - 0.5) * kAng / 7.0;
+  // accumulators in register arrays indexed at compile time only (a runtime-
+  // indexed array would live in scratch memory)
+  double gO[16], gH[16], mO[24], mH[24];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    gO[k] = 0.0;
+    gH[k] = 0.0;
+  }
+#pragma unroll
+  for (int k = 0; k < 24; ++k) {
+    mO[k] = 0.0;
+    mH[k] = 0.0;
+  }
+  constexpr double kInvE = 0.36787944117144233;  // exp(-1)
+  for (int b = a0; b < a1; ++b) {
+    if (b == a) continue;
+    const double dx = pos[b * 3] - pos[a * 3], dy = pos[b * 3 + 1] - pos[a * 3 + 1], dz = pos[b * 3 + 2] - pos[a * 3 + 2];
+    const double r = sqrt(dx * dx + dy * dy + dz * dz);
+    if (r >= rc) continue;
+    const double fc = 0.5 * (cos(M_PI * r / rc) + 1.0);
+    const int s = species[b];
+    // Gaussians exp(-(v - k)^2 / 2) at v = (r - r0) / dr for k = 0, 1, ... by the
+    // exact product recurrence g_{k+1} = g_k exp(v - k - 1/2): two exponentials
+    // per pair and comb
+    const double v = (r - r0) / dr;
+    double gk = exp(-0.5 * v * v) * fc, ck = exp(v - 0.5);
+    const double w = (r - r0) / drv;
+    double hk = exp(-0.5 * w * w) * fc, dk = exp(w - 0.5);
+    const double ir = 1.0 / r;
+    const double u1 = (e1[0] * dx + e1[1] * dy + e1[2] * dz) * ir;
+    const double u2 = (e2[0] * dx + e2[1] * dy + e2[2] * dz) * ir;
+    const double u3 = (e3[0] * dx + e3[1] * dy + e3[2] * dz) * ir;
+    if (s == 0) {
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        gO[k] += gk;
+        gk *= ck;
+        ck *= kInvE;
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        mO[3 * k] += hk * u1;
+        mO[3 * k + 1] += hk * u2;
+        mO[3 * k + 2] += hk * u3;
+        hk *= dk;
+        dk *= kInvE;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        gH[k] += gk;
+        gk *= ck;
+        ck *= kInvE;
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        mH[3 * k] += hk * u1;
+        mH[3 * k + 1] += hk * u2;
+        mH[3 * k + 2] += hk * u3;
+        hk *= dk;
+        dk *= kInvE;
+      }
+    }
+  }
+  double* f = feat + (int64_t)a * NIN;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    f[k] = gO[k];
+    f[16 + k] = gH[k];
+  }
+#pragma unroll
+  for (int k = 0; k < 24; ++k) {
+    f[32 + k] = mO[k];
+    f[56 + k] = mH[k];
   }
 }
 
@@ -205,7 +272,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 // row spread the 8-byte operand reads of neighbouring rows over the banks
 constexpr int LDX = NIN + 4, LDH = NHID + 4;
 
-// one hidden layer of a 64-atom tile on the matrix cores:
+// one hidden layer of an atom tile (16 atoms per wave) on the matrix cores:
 // z[a][j] = sum_k in[a][k] W[k][j] + b[j] with bf16 operands (in: bf16 rows
 // of stride ldin, Wt: W transposed in bf16, rows of stride ldw) and FP32
 // accumulation by v_mfma_f32_16x16x16_bf16; wave w takes atoms 16w..16w+15 and
@@ -248,29 +315,29 @@ __device__ void dense_hidden_mfma(const unsigned short* __restrict__ in, int ldi
 // h1 = silu(W1 x + b1), every product with bf16 operands and FP32 accumulation
 // on the matrix cores (the 9 outputs padded to one 16-wide tile).
 // Persistent workgroups: the weights are converted to transposed bf16 in LDS
-// once, then the workgroup takes 64-atom tiles blockIdx.x, blockIdx.x + gridDim.x, ...
+// once, then the workgroup takes 128-atom tiles blockIdx.x, blockIdx.x + gridDim.x, ...
 // act (or null) receives the pre-activations z1, z2 per atom for the backward pass.
-__global__ __launch_bounds__(NT) void forward_kernel(const float* __restrict__ P, const float* __restrict__ x, int n,
+__global__ __launch_bounds__(FNT) void forward_kernel(const float* __restrict__ P, const float* __restrict__ x, int n,
                                                      float* __restrict__ y, float* __restrict__ act) {
   __shared__ __align__(16) unsigned short sW1t[NHID * LDX];
   __shared__ __align__(16) unsigned short sW2t[NHID * LDH];
-  __shared__ __align__(16) unsigned short sH1[TILE * LDH];
-  __shared__ __align__(16) unsigned short sXH2[TILE * LDH];  // x tile (stride LDX) for layer 1, then h2
+  __shared__ __align__(16) unsigned short sH1[FTILE * LDH];
+  __shared__ __align__(16) unsigned short sXH2[FTILE * LDH];  // x tile (stride LDX) for layer 1, then h2
   __shared__ __align__(16) unsigned short sW3t[16 * LDH];     // W3 transposed, outputs 9..15 zero
-  for (int e = threadIdx.x; e < NIN * NHID; e += NT) sW1t[(e % NHID) * LDX + e / NHID] = bf16_bits(P[OFF_W1 + e]);
-  for (int e = threadIdx.x; e < NHID * NHID; e += NT) sW2t[(e % NHID) * LDH + e / NHID] = bf16_bits(P[OFF_W2 + e]);
-  for (int e = threadIdx.x; e < 16 * NHID; e += NT) {
+  for (int e = threadIdx.x; e < NIN * NHID; e += FNT) sW1t[(e % NHID) * LDX + e / NHID] = bf16_bits(P[OFF_W1 + e]);
+  for (int e = threadIdx.x; e < NHID * NHID; e += FNT) sW2t[(e % NHID) * LDH + e / NHID] = bf16_bits(P[OFF_W2 + e]);
+  for (int e = threadIdx.x; e < 16 * NHID; e += FNT) {
     const int o = e / NHID, k = e % NHID;
     sW3t[o * LDH + k] = o < NOUT ? bf16_bits(P[OFF_W3 + k * NOUT + o]) : (unsigned short)0;
   }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int r16 = lane & 15, kq = (lane >> 4) * 4;
   const float b3 = r16 < NOUT ? P[OFF_B3 + r16] : 0.0f;
-  const int n_tiles = (n + TILE - 1) / TILE;
+  const int n_tiles = (n + FTILE - 1) / FTILE;
   for (int tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
-    const int t0 = tile * TILE;
-    const int m = min(TILE, n - t0);
-    for (int e = threadIdx.x; e < TILE * NIN; e += NT) {
+    const int t0 = tile * FTILE;
+    const int m = min(FTILE, n - t0);
+    for (int e = threadIdx.x; e < FTILE * NIN; e += FNT) {
       const int a = e / NIN, k = e % NIN;
       sXH2[a * LDX + k] = a < m ? bf16_bits(x[(int64_t)t0 * NIN + e]) : (unsigned short)0;
     }
@@ -695,8 +762,8 @@ hipError_t launch_sg_prep(int n, int width, const int32_t* idx, const double* v,
 }
 hipError_t launch_sg_forward(const float* P, const float* x, int n, float* y, float* act, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  const int n_tiles = (n + TILE - 1) / TILE;
-  hipLaunchKernelGGL(forward_kernel, dim3(std::min(n_tiles, kForwardGrid)), dim3(NT), 0, s, P, x, n, y, act);
+  const int n_tiles = (n + FTILE - 1) / FTILE;
+  hipLaunchKernelGGL(forward_kernel, dim3(std::min(n_tiles, kForwardGrid)), dim3(FNT), 0, s, P, x, n, y, act);
   return hipGetLastError();
 }
 hipError_t launch_sg_backward(const float* P, const float* x, const float* act, const float* dy, int n, float* grad,

@@ -44,7 +44,7 @@ def _subsystem(s, units):
 def _ensemble(seed=3):
     rng = np.random.default_rng(seed)
     P = np.stack([np.stack([osg.init_params(rng) for _ in range(4)]) for _ in range(2)]).astype(np.float32)
-    N = np.stack([np.concatenate([rng.uniform(0, 1, 32), rng.uniform(0.5, 2, 32), rng.normal(0, 0.2, 9),
+    N = np.stack([np.concatenate([rng.uniform(0, 1, osg.N_IN), rng.uniform(0.5, 2, osg.N_IN), rng.normal(0, 0.2, 9),
                                   rng.uniform(0.05, 0.2, 9)]) for _ in range(2)]).astype(np.float32)
     return _t(P, torch.float32), _t(N, torch.float32)
 

@@ -184,12 +184,11 @@ def test_md_two_steps_central_fd_eight_water_parity(params):
 def _ensemble(seed):
     rng = np.random.default_rng(seed)
     P = np.stack([np.stack([osg.init_params(rng) for _ in range(4)]) for _ in range(2)]).astype(np.float32)
-    N = np.stack([np.concatenate([rng.uniform(0, 1, 32), rng.uniform(0.5, 2, 32), rng.normal(0, 0.2, 9),
+    N = np.stack([np.concatenate([rng.uniform(0, 1, osg.N_IN), rng.uniform(0.5, 2, osg.N_IN), rng.normal(0, 0.2, 9),
                                   rng.uniform(0.05, 0.2, 9)]) for _ in range(2)]).astype(np.float32)
     nets = [[P[sp, m].astype(np.float64) for m in range(4)] for sp in (0, 1)]
     Nh = N.astype(np.float64)
-    norms = [{"x_mean": Nh[sp, :32], "x_std": Nh[sp, 32:64], "y_mean": Nh[sp, 64:73], "y_scale": Nh[sp, 73:82]}
-             for sp in (0, 1)]
+    norms = [osg.unpack_norm(Nh[sp]) for sp in (0, 1)]
     return nets, norms, _t(P, torch.float32), _t(N, torch.float32)
 
 

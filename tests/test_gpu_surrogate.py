@@ -38,7 +38,7 @@ def _t(a, dtype=torch.float64):
 def test_features_and_frames_parity(params):
     s = make_system(5, n_units=10)
     ctx = cd.context_from_system(params, s)
-    feat = torch.empty(ctx.n_atoms, 32, dtype=torch.float64, device=DEV)
+    feat = torch.empty(ctx.n_atoms, osg.N_IN, dtype=torch.float64, device=DEV)
     fr = torch.empty(ctx.n_atoms, 9, dtype=torch.float64, device=DEV)
     ctx.sg_features(_t(s["pos"]), feat, fr)
     ctx.sync()
@@ -59,7 +59,7 @@ def test_network_forward_backward_parity():
     rng = np.random.default_rng(0)
     th = osg.init_params(rng)
     n = 150                                           # two full tiles and a ragged one
-    x = rng.normal(size=(n, 32))
+    x = rng.normal(size=(n, osg.N_IN))
     dy = rng.normal(size=(n, 9)) * 0.1
     y_ref, cache = osg.forward(th, x, emulate_bf16=True)
     g_ref = osg.backward(th, cache, dy, emulate_bf16=True)
@@ -109,7 +109,7 @@ def _random_ensemble(seed):
     nets = [[osg.init_params(rng) for _ in range(4)] for _ in range(2)]
     norms = []
     for _ in range(2):
-        norms.append({"x_mean": rng.uniform(0, 1, 32), "x_std": rng.uniform(0.5, 2, 32),
+        norms.append({"x_mean": rng.uniform(0, 1, osg.N_IN), "x_std": rng.uniform(0.5, 2, osg.N_IN),
                       "y_mean": rng.normal(0, 0.2, 9), "y_scale": rng.uniform(0.05, 0.2, 9)})
     P = np.stack([np.stack(nets[s]) for s in (0, 1)]).astype(np.float32)
     N = np.stack([np.concatenate([nm["x_mean"], nm["x_std"], nm["y_mean"], nm["y_scale"]]) for nm in norms])
@@ -122,8 +122,7 @@ def test_surrogate_born_matches_oracle_prediction(params):
     # the oracle works on the FP32-rounded weights and normalisation the GPU receives
     nets = [[np.asarray(P[sp, m].cpu().numpy(), dtype=np.float64) for m in range(4)] for sp in (0, 1)]
     Nh = N.cpu().numpy().astype(np.float64)
-    norms = [{"x_mean": Nh[sp, :32], "x_std": Nh[sp, 32:64], "y_mean": Nh[sp, 64:73], "y_scale": Nh[sp, 73:82]}
-             for sp in (0, 1)]
+    norms = [osg.unpack_norm(Nh[sp]) for sp in (0, 1)]
     ctx = cd.context_from_system(params, s)
     ctx.set_scc(1e-12, 300, 0.2)
     ctx.set_surrogate(P.view(-1), N.view(-1), 1e9)
@@ -154,8 +153,7 @@ def test_surrogate_born_full_size_sampled(params):
     _, _, P, N = _random_ensemble(4)
     nets = [[np.asarray(P[sp, m].cpu().numpy(), dtype=np.float64) for m in range(4)] for sp in (0, 1)]
     Nh = N.cpu().numpy().astype(np.float64)
-    norms = [{"x_mean": Nh[sp, :32], "x_std": Nh[sp, 32:64], "y_mean": Nh[sp, 64:73], "y_scale": Nh[sp, 73:82]}
-             for sp in (0, 1)]
+    norms = [osg.unpack_norm(Nh[sp]) for sp in (0, 1)]
     ctx = cd.context_from_system(params, s)
     ctx.set_scc(1e-12, 300, 0.2)
     ctx.set_surrogate(P.view(-1), N.view(-1), 1e9)
@@ -250,8 +248,7 @@ def test_surrogate_md_steps_run_and_stay_finite(params):
 def test_trained_network_beats_the_mulliken_replacement(params):
     # the gain of the learned part: on held-out snapshots (later in time) the
     # trained ensemble is closer to the exact Born charges than the paper's
-    # replacement Z = Q I it corrects (on this synthetic model much of the
-    # charge flux is non-local, which bounds what local descriptors can learn)
+    # replacement Z = Q I it corrects
     data = dsg.build_training_set(params, n_units=48, n_train=5, n_val=2, stride=8, n_sub=2)
     fe, ta = data["train"]
     psg, nsg, losses = dsg.train_ensemble(fe, ta, epochs=12, batch=256)

@@ -27,7 +27,7 @@ def _t(a, dtype=torch.float32):
 def _case(rng, n):
     th = osg.init_params(rng)
     w = _t(th)
-    x = _t(rng.normal(size=(n, 32)))
+    x = _t(rng.normal(size=(n, osg.N_IN)))
     y = torch.empty(n, 9, dtype=torch.float32, device=DEV)
     act = torch.empty(n, 256, dtype=torch.float32, device=DEV)
     B.sg_forward(w, x, n, y, act)
@@ -54,7 +54,7 @@ def test_noalloc_backward_matches_the_oracle_gradient():
     rng = np.random.default_rng(6)
     n = 200
     th = osg.init_params(rng)
-    x = rng.normal(size=(n, 32))
+    x = rng.normal(size=(n, osg.N_IN))
     dy = rng.normal(size=(n, 9)) * 0.1
     _, cache = osg.forward(th, x, emulate_bf16=True)
     g_ref = osg.unpack(osg.backward(th, cache, dy, emulate_bf16=True))
