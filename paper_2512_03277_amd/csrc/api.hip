@@ -111,6 +111,7 @@ struct cavdftb_ctx {
   double* d_f_job = nullptr;      // [6][NA][3] forces of the field jobs
   int32_t* d_f_status = nullptr;  // [U][6] status of the field jobs
   int32_t *d_status = nullptr, *d_cjob_status = nullptr, *d_cjob_iters = nullptr;
+  int32_t* d_unit_fail = nullptr;  // [U] last undisplaced SCC of the unit did not converge
   int32_t *d_fjob_status = nullptr, *d_fjob_iters = nullptr;
   unsigned long long* d_counters = nullptr;
   unsigned int* d_job_counter = nullptr;  // job queues of the SCC launches, one per bucket
@@ -280,6 +281,7 @@ SccArgs base_args(cavdftb_ctx* c, const double* pos) {
   a.jac_factor = c->jac_factor;
   a.eig_mode = c->eig_mode;
   a.counters = c->d_counters;
+  a.unit_fail = c->d_unit_fail;
   a.job_counter = nullptr;  // set per bucket by run_scc
   a.tol = c->tol;
   a.max_iter = c->max_iter;
@@ -813,6 +815,8 @@ int cavdftb_create(const cavdftb_params* params, const cavdftb_layout* L, void* 
   CK(dalloc(c, &c->d_field, U));
   CK(dalloc(c, &c->d_zpol, (size_t)NA * 3));
   CK(dalloc(c, &c->d_status, U));
+  CK(dalloc(c, &c->d_unit_fail, U));
+  CK(hipMemset(c->d_unit_fail, 0, (size_t)U * sizeof(int32_t)));
   CK(dalloc(c, &c->d_cjob_status, U));
   CK(dalloc(c, &c->d_cjob_iters, U));
   CK(dalloc(c, &c->d_sg_params, 2 * (size_t)CAVDFTB_SG_MEMBERS * CAVDFTB_SG_N_PARAM));

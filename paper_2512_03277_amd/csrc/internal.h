@@ -64,6 +64,8 @@ struct SccArgs {
   double* f_job;            // [6][n_atoms][3] or nullptr: forces of the field jobs, by field code
   int32_t* f_status;        // [n_units][6] or nullptr: status of the field jobs, by field code
   int32_t* status;          // [n_units] (undisplaced jobs) or nullptr
+  int32_t* unit_fail;       // [n_units] or nullptr: 1 when the unit's last undisplaced SCC did not
+                            // converge (read by every job of the unit, written by undisplaced jobs)
   int32_t* job_status;      // [n_jobs] or nullptr
   int32_t* job_iters;       // [n_jobs] or nullptr
   unsigned long long* counters;  // [8]: jobs, iterations, algorithmic flops, Jacobi sweeps, surrogate fallback units,

@@ -33,6 +33,7 @@ constexpr int kMaxSweeps = 30;
 constexpr double kJacobiThr = 1.0e-14;  // off-diagonal threshold (hartree)
 constexpr double kGapMin = 1.0e-6;
 constexpr int kStagnation = 20;  // iterations without a new smallest residual before giving up
+constexpr int kStagnationFailed = 5;  // the same for a unit whose last undisplaced SCC did not converge
 // warm orthonormalisation: Newton-Schulz from max|C0^T S C0 - I| <= kNsStart
 constexpr double kNsStart = 0.1;
 constexpr double kNsTol = 1.0e-15;
@@ -1326,6 +1327,11 @@ __global__ __launch_bounds__(NT, NMAX == 32 ? 4 : 2) void scc_kernel(const SccAr
     bool ordered = warm;  // stored bases keep the occupied orbitals first
 
     int it = 0;
+    // a unit that failed its last undisplaced SCC (charge sloshing that does not
+    // settle) gets a shorter stagnation window: it keeps iterating while it finds
+    // new smallest residuals, but does not hold its launch for kStagnation idle
+    // iterations every evaluation
+    const int stag_window = (a.unit_fail && a.unit_fail[u]) ? kStagnationFailed : kStagnation;
     double res_prev = INFINITY;  // no charge residual known before the first iteration
     double res_best = INFINITY;  // smallest residual so far and its iteration (stagnation stop)
     int it_best = 0;
@@ -1681,7 +1687,7 @@ __global__ __launch_bounds__(NT, NMAX == 32 ? 4 : 2) void scc_kernel(const SccAr
         if (res < res_best) {
           res_best = res;
           it_best = it;
-        } else if (it - it_best >= kStagnation) {  // no new best residual for kStagnation iterations
+        } else if (it - it_best >= stag_window) {  // no new best residual for stag_window iterations
           status |= CAVDFTB_ST_NOT_CONVERGED;
           break;
         }
@@ -1910,6 +1916,7 @@ __global__ __launch_bounds__(NT, NMAX == 32 ? 4 : 2) void scc_kernel(const SccAr
     }
     if (tid == 0) {
       if (disp == -1 && a.status) a.status[u] = status;
+      if (disp == -1 && a.unit_fail) a.unit_fail[u] = (status & CAVDFTB_ST_NOT_CONVERGED) ? 1 : 0;
       if (fcode >= 0 && a.f_status) a.f_status[(int64_t)u * 6 + fcode] = status;
       if (a.job_status) a.job_status[job] = status;
       if (a.job_iters) a.job_iters[job] = it;

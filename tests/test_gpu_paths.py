@@ -400,3 +400,29 @@ def test_bucket_streams_leave_results_unchanged(params):
         ctx.close()
     for k in evals[0]:
         assert np.array_equal(evals[0][k], evals[1][k]), k
+
+
+def test_failed_unit_gets_the_short_stagnation_window(params):
+    # the 27-water unit of the uneven workload whose SCC does not converge, with a
+    # unit that does: cold evaluations twice at the same geometry.  The first
+    # stops after the full stagnation window, the second (the unit failed last
+    # time) after the short one; both flag it, and the converging unit's results
+    # are bitwise the same in both
+    full = make_system(4)
+    nw = np.diff(full["unit_off"]) // 3
+    bad = 11611
+    assert nw[bad] == 27
+    s = subsystem(full, [bad, 0])
+    ctx = make_ctx(params, s, tol=1e-8, max_iter=100)
+    ctx.set_warm_start(False)
+    g1 = gpu_eval(ctx, s["pos"])
+    it1 = ctx.read_counters()["scc_iterations"]
+    ctx.reset_counters()
+    g2 = gpu_eval(ctx, s["pos"])
+    it2 = ctx.read_counters()["scc_iterations"]
+    assert g1["status"][0] & cd.binding.ST_NOT_CONVERGED and g2["status"][0] & cd.binding.ST_NOT_CONVERGED
+    assert g1["status"][1] == 0 and g2["status"][1] == 0
+    a0 = s["unit_off"][1]
+    assert g1["energy"][1] == g2["energy"][1] and np.array_equal(g1["charges"][a0:], g2["charges"][a0:])
+    assert it2 <= it1 - 10, (it1, it2)
+    ctx.close()
