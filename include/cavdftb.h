@@ -195,14 +195,16 @@ int cavdftb_load_launch_table(cavdftb_ctx* ctx, const char* path);
  * estimated cost first, to the stream with the least work so far; the side
  * streams wait for the context stream's earlier work and the context stream
  * waits for them before its next work, so callers see one stream.  Results
- * are bit-identical for every count (the buckets hold disjoint units).
- * Returns CAVDFTB_EINVAL for a count outside 1..4. */
+ * are bit-identical for every count (the buckets hold disjoint units).  MD
+ * steps replayed from a graph (cavdftb_set_graph) keep their launches on the
+ * context stream.  Returns CAVDFTB_EINVAL for a count outside 1..4. */
 int cavdftb_set_bucket_streams(cavdftb_ctx* ctx, int32_t n_streams);
 
 /* Warm start: when enabled (default 1) each unit evaluation starts from the
  * charges, the molecular-orbital basis and the mixer history its previous
  * evaluation stored.  cavdftb_reset_warm_start forgets them (the next
- * evaluation starts cold). */
+ * evaluation starts cold), and the charge responses that start the +h / +field
+ * jobs of the Born routes (cavdftb_born_charges). */
 int cavdftb_set_warm_start(cavdftb_ctx* ctx, int32_t enable);
 int cavdftb_reset_warm_start(cavdftb_ctx* ctx);
 
@@ -223,9 +225,10 @@ int cavdftb_eval_units(cavdftb_ctx* ctx, const double* pos, double* energy, doub
  * SCC per unit; CAVDFTB_BORN_FD: central differences with step h (bohr) of the
  * converged SCC dipole, 6 n_atoms displaced SCCs per unit, warm-started from
  * the undisplaced solution, in two launches per orbital bucket: every +h SCC,
- * then every -h SCC started from the +h charges reflected through the
- * undisplaced ones (Results: the Born charges are the bottleneck and are taken
- * by finite differences);
+ * started from the undisplaced charges plus that job's charge response at the
+ * previous evaluation (zero before the first), then every -h SCC started from
+ * the +h charges reflected through the undisplaced ones (Results: the Born
+ * charges are the bottleneck and are taken by finite differences);
  * CAVDFTB_BORN_FIELD: the same tensor from the Maxwell relation
  * d mu_a / d R_Ab = d F_Ab / d field_a, as central differences of the SCC
  * forces in a uniform field +-h e_a (h in atomic units of field, e.g. 1e-4):

@@ -97,7 +97,8 @@ struct cavdftb_ctx {
   double* d_ws_C = nullptr;
   double* d_ws_dq = nullptr;
   double* d_ws_dq_hist = nullptr;
-  double* d_fd_dq = nullptr;        // charges of the +h displaced jobs (3 n_a^2 per unit)
+  double* d_fd_dq = nullptr;        // charge responses of the + jobs (3 n_a^2 + 3 n_a per unit)
+  int64_t fd_dq_count = 0;
   int64_t* d_fd_dq_off = nullptr;   // [U] offsets into d_fd_dq
   int md_hist = 0;  // consecutive MD evaluations whose charges are stored
   int64_t* d_hist_off = nullptr;
@@ -122,6 +123,7 @@ struct cavdftb_ctx {
   hipEvent_t ev_fork = nullptr;
   hipEvent_t ev_join[3] = {nullptr, nullptr, nullptr};
   int n_streams = 4;
+  bool capturing = false;  // inside replay_step's stream capture
   int dynamic_jobs = 1;
   int n_cu = 256;
   // learned Born-charge surrogate
@@ -214,6 +216,7 @@ void drop_graph(cavdftb_ctx* c) {
 
 void release(cavdftb_ctx* c) {
   if (c->stream) hipStreamSynchronize(c->stream);
+  drop_graph(c);  // before the streams and events its capture used
   for (int j = 0; j < 3; ++j)
     if (c->side[j]) {
       hipStreamSynchronize(c->side[j]);
@@ -229,7 +232,6 @@ void release(cavdftb_ctx* c) {
     hipEventDestroy(c->ev_fork);
     c->ev_fork = nullptr;
   }
-  drop_graph(c);
   for (void* p : c->allocs) hipFree(p);
   c->allocs.clear();
   for (auto& pr : c->ev_pending) {
@@ -326,15 +328,18 @@ int32_t center_flags(cavdftb_ctx* c, bool forces) {
 // n_streams streams: buckets by estimated cost, largest first, each to the
 // stream with the least work so far (stream 0 is the context stream).  The
 // side streams wait for the context stream's earlier work (fork) and the
-// context stream waits for theirs (join); captured into a graph, the event
-// edges become graph dependencies.
+// context stream waits for theirs (join).
 struct BucketFan {
   cavdftb_ctx* c;
   int ns;
   double load[4] = {0.0, 0.0, 0.0, 0.0};
   std::vector<int> order;
 
-  explicit BucketFan(cavdftb_ctx* ctx) : c(ctx), ns(std::min(ctx->n_streams, (int)ctx->buckets.size())) {
+  // a step captured into a graph keeps its launches on the context stream: the
+  // graph then holds no cross-stream event dependencies, and a recapture reuses
+  // no event of a destroyed graph
+  explicit BucketFan(cavdftb_ctx* ctx)
+      : c(ctx), ns(ctx->capturing ? 1 : std::min(ctx->n_streams, (int)ctx->buckets.size())) {
     order.resize(c->buckets.size());
     for (size_t k = 0; k < order.size(); ++k) order[k] = (int)k;
     std::stable_sort(order.begin(), order.end(),
@@ -644,7 +649,9 @@ int replay_step(cavdftb_ctx* c, double* r, double* p, double* qm, double* pm, do
     hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(c, e, "graph capture begin");
     const int64_t l0 = c->launches;
+    c->capturing = true;
     const int rc = issue_step(c, r, p, qm, pm, dt, born_mode, h_fd, obs);
+    c->capturing = false;
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(c->stream, &g);
     if (rc) {
@@ -797,10 +804,12 @@ int cavdftb_create(const cavdftb_params* params, const cavdftb_layout* L, void* 
     for (int u = 0; u < U; ++u) {
       const int64_t na = c->h_unit_off[u + 1] - c->h_unit_off[u];
       off[u] = tot;
-      tot += 3 * na * na;
+      tot += 3 * na * na + 3 * na;  // displaced slots, then field slots
     }
     CK(dalloc(c, &c->d_fd_dq_off, (size_t)U));
     CK(dalloc(c, &c->d_fd_dq, (size_t)tot));
+    CK(hipMemset(c->d_fd_dq, 0, (size_t)tot * sizeof(double)));
+    c->fd_dq_count = tot;
     CK(hipMemcpy(c->d_fd_dq_off, off.data(), U * sizeof(int64_t), hipMemcpyHostToDevice));
   }
   CK(dalloc(c, &c->d_hist_off, U));
@@ -1157,6 +1166,9 @@ int cavdftb_reset_warm_start(cavdftb_ctx* ctx) {
   ctx->gen += 1;
   ctx->warm_valid = false;
   ctx->md_hist = 0;
+  // the charge responses of the finite-difference jobs start over too
+  const hipError_t e = hipMemsetAsync(ctx->d_fd_dq, 0, (size_t)ctx->fd_dq_count * sizeof(double), ctx->stream);
+  if (e != hipSuccess) return hip_fail(ctx, e, "reset_warm_start");
   return CAVDFTB_OK;
 }
 

@@ -46,11 +46,13 @@ struct SccArgs {
   double* ws_dq;            // [n_atoms] stored charges (electron excess)
   double* ws_dq_hist;       // [2][n_atoms] charges of the two MD steps before, or nullptr
   int32_t n_extrap;         // stored MD steps usable for extrapolating the start charges (0..3)
-  int32_t fd_pass;          // displaced or field jobs of central differences: 0 all; 1 only +h / +field
-                            // (charges kept in fd_dq); 2 only -h / -field, started from 2 dq_centre - dq(+)
-  double* fd_dq;            // converged charges of the + jobs: fd_dq_off[u] + slot n_a + t, slot 3 atom + dir
-                            // (displaced) or dir (field)
-  const int64_t* fd_dq_off; // [n_units] offsets into fd_dq (3 n_a^2 per unit)
+  int32_t fd_pass;          // displaced or field jobs of central differences: 0 all; 1 only +h / +field,
+                            // 2 only -h / -field
+  double* fd_dq;            // per + job the charge response ddq = dq(+) - dq_centre of its last converged
+                            // run (NaN after a failed one): fd_dq_off[u] + slot n_a + t, slot 3 atom + dir
+                            // (displaced) or 3 n_a + dir (field).  A -h job starts from dq_centre - ddq of
+                            // this pass 1; a +h job from dq_centre + ddq of the previous evaluation.
+  const int64_t* fd_dq_off; // [n_units] offsets into fd_dq (3 n_a^2 + 3 n_a per unit)
   int32_t n_atoms;
   double* hist;             // per-unit Broyden history store (or nullptr)
   const int64_t* hist_off;  // [n_units] offset of each unit's history block

@@ -1131,10 +1131,11 @@ __global__ __launch_bounds__(NT, NMAX == 32 ? 4 : 2) void scc_kernel(const SccAr
     // sign and slot of a perturbed job of a central difference: the +h (+field)
     // job of slot (3 atom + dir) (dir) runs in pass 1, its -h partner in pass 2
     const int pm_sign = disp >= 0 ? (disp & 1) : (fcode >= 0 ? (fcode & 1) : -1);
-    const int64_t pm_slot = disp >= 0 ? (disp >> 1) : (fcode >> 1);
     if (a.fd_pass && pm_sign >= 0 && pm_sign != (a.fd_pass == 2 ? 1 : 0)) continue;  // the other sign's pass
     const int a0 = a.unit_off[u];
     const int na = a.unit_off[u + 1] - a0;
+    // slot of the job's charge response in fd_dq: 3 atom + dir (displaced), 3 n_a + dir (field)
+    const int64_t fd_slot = disp >= 0 ? (disp >> 1) : 3LL * na + (fcode >> 1);
     const int d_atom = disp >= 0 ? (disp >> 1) / 3 : -1;
     const int d_dir = disp >= 0 ? (disp >> 1) % 3 : 0;
     const double d_step = disp >= 0 ? ((disp & 1) ? -a.fd_h : a.fd_h) : 0.0;
@@ -1198,9 +1199,14 @@ __global__ __launch_bounds__(NT, NMAX == 32 ? 4 : 2) void scc_kernel(const SccAr
         const double d1 = a.ws_dq_hist[a0 + t], d2 = a.ws_dq_hist[(int64_t)a.n_atoms + a0 + t];
         dq0 = a.n_extrap >= 3 ? 3.0 * dq0 - 3.0 * d1 + d2 : 2.0 * dq0 - d1;
       }
-      if (a.fd_pass == 2 && pm_sign == 1) {  // -h job: the +h job's charges reflected through the centre
-        const double qp = a.fd_dq[a.fd_dq_off[u] + pm_slot * na + t];
-        if (isfinite(qp)) dq0 = 2.0 * dq0 - qp;
+      if (a.fd_pass && pm_sign >= 0) {
+        // charge response ddq of the + job of this slot: a -h job starts from the
+        // +h charges of this pass reflected through the centre, dq_c - ddq; a +h
+        // job from its response at the previous evaluation, dq_c + ddq (first
+        // order in the change of the response between evaluations; zero before
+        // the first).  Failed + jobs leave NaN: start from the centre.
+        const double d = a.fd_dq[a.fd_dq_off[u] + fd_slot * na + t];
+        if (isfinite(d)) dq0 += (pm_sign == 1) ? -d : d;
       }
       sDqIn[t] = dq0;
     }
@@ -1851,7 +1857,10 @@ __global__ __launch_bounds__(NT, NMAX == 32 ? 4 : 2) void scc_kernel(const SccAr
         if (a.charges) a.charges[a0 + t] = -sDqOut[t];
     }
     if (a.fd_pass == 1 && pm_sign == 0)
-      for (int t = tid; t < na; t += NT) a.fd_dq[a.fd_dq_off[u] + pm_slot * na + t] = sDqOut[t];
+      for (int t = tid; t < na; t += NT) {
+        const double dqc = (a.flags & JF_WARM_DQ) ? a.ws_dq[a0 + t] : 0.0;
+        a.fd_dq[a.fd_dq_off[u] + fd_slot * na + t] = status == 0 ? sDqOut[t] - dqc : NAN;
+      }
     if ((a.flags & JF_FORCES) && disp < 0) {  // undisplaced and field jobs
       // W = 2 C_occ diag(eps_occ) C_occ^T = 1/2 P H P with H of the last iteration
       // (sV still holds its V; X_occ spans the occupied eigenspace, so no
