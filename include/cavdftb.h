@@ -45,7 +45,7 @@ extern "C" {
 #define CAVDFTB_EHIP (-3)
 
 /* unit_status bits */
-#define CAVDFTB_ST_NOT_CONVERGED 1 /* SCC hit max_iter, or set no new smallest residual for 20 iterations, before reaching tol */
+#define CAVDFTB_ST_NOT_CONVERGED 1 /* SCC hit max_iter, or set no new smallest residual for 20 iterations (5 when the unit's last undisplaced SCC was flagged so), before reaching tol */
 #define CAVDFTB_ST_NOT_PD 2        /* overlap matrix not positive definite */
 #define CAVDFTB_ST_DEGENERATE 4    /* HOMO-LUMO gap below 1e-6 hartree */
 #define CAVDFTB_ST_NAN 8           /* non-finite position or charge */
@@ -125,7 +125,10 @@ int cavdftb_destroy(cavdftb_ctx* ctx);
 /* SCC controls (defaults tol 1e-8, max_iter 200, mix_alpha 0.6): Johnson's
  * modified Broyden mixing of the atomic charges with inverse-Jacobian weight
  * w0 = 0.01 and at most 20 stored iterations; converged when
- * max_A |Dq_out - Dq_in| < tol. */
+ * max_A |Dq_out - Dq_in| < tol.  A unit that sets no new smallest residual
+ * for 20 iterations stops and is flagged CAVDFTB_ST_NOT_CONVERGED; while its
+ * last undisplaced SCC was flagged that way, the window is 5 iterations (for
+ * its displaced and field SCCs too). */
 int cavdftb_set_scc(cavdftb_ctx* ctx, double tol, int32_t max_iter, double mix_alpha);
 
 /* Solver tuning (results are unchanged to within the SCC tolerance):
