@@ -109,17 +109,24 @@ def report_from_acf(Ca, Cb, dt, lo, hi, n_samples):
     autocorrelations: the largest peak in [lo, hi] cm^-1 of each, and the first
     moment of each spectrum over that same fixed band (it depends on neither
     run; a peak can jump between neighbouring maxima of a broad noisy band, the
-    centroid cannot); the two strongest lines of each (top_peaks) and the
-    normalised overlap of the two spectra over the band.  The resolution
+    centroid cannot); the two strongest lines of each (top_peaks), the shift
+    of run a's line nearest to run b's largest value, and the normalised
+    overlap of the two spectra over the band.  The resolution
     2 pi / (n_samples dt) is returned beside them; no position is meaningful to
     much better than a fraction of it."""
     fa, Ia = spectrum(Ca, dt)
     fb, Ib = spectrum(Cb, dt)
     pa, pb = peak(fa, Ia, lo, hi), peak(fb, Ib, lo, hi)
     ca, cb = centroid(fa, Ia, lo, hi), centroid(fb, Ib, lo, hi)
+    la, lb = top_peaks(fa, Ia, lo, hi), top_peaks(fb, Ib, lo, hi)
+    # the line of run a nearest to run b's largest value: the same line of the
+    # band followed across the runs, where their largest values can sit on
+    # different lines of a multi-line band
+    near = min(la, key=lambda f: abs(f - pb)) if la else None
     return {"peak_a_cm": pa, "peak_b_cm": pb, "shift_cm": pa - pb,
+            "matched_line_shift_cm": (near - pb) if near is not None else None,
             "centroid_a_cm": ca, "centroid_b_cm": cb, "centroid_shift_cm": ca - cb,
-            "lines_a_cm": top_peaks(fa, Ia, lo, hi), "lines_b_cm": top_peaks(fb, Ib, lo, hi),
+            "lines_a_cm": la, "lines_b_cm": lb,
             "overlap": overlap(fa, Ia, Ib, lo, hi),
             "band_cm": [lo, hi], "resolution_cm": resolution_cm(n_samples, dt)}
 

@@ -204,3 +204,15 @@ def test_overlap_of_spectra():
     assert spectra.overlap(f, Ia, Ia + Ib, 1000.0, 2500.0) == pytest.approx(2 ** -0.5, abs=0.03)
     with pytest.raises(ValueError):
         spectra.overlap(f, Ia, Ib, -2.0, -1.0)
+
+
+def test_matched_line_follows_the_same_line_across_runs():
+    # run b has one line; run a the same line 3 cm^-1 higher plus a stronger second
+    # line: the largest values differ by the line spacing, the matched line by 3
+    t = np.arange(8000) * DT
+    w = 1.0 / spectra.HARTREE_CM
+    xb = np.cos(1400.0 * w * t)
+    xa = np.cos(1403.0 * w * t) + 1.3 * np.cos(1700.0 * w * t)
+    r = spectra.report_from_acf(spectra.autocorrelation(xa), spectra.autocorrelation(xb), DT, 1000.0, 2500.0, len(t))
+    assert r["shift_cm"] == pytest.approx(300.0, abs=5.0)
+    assert r["matched_line_shift_cm"] == pytest.approx(3.0, abs=1.0)
