@@ -367,6 +367,36 @@ def test_md_step_exact_born_parity(params):
     assert _rel(qm, st["q"]) <= 1e-8 and _rel(pm, st["pm"]) <= 1e-8
 
 
+@pytest.mark.parametrize("route", ["fd", "field"])
+def test_md_steps_exact_born_second_order_starts(params, route):
+    # five steps: from the second Born evaluation on, every +h / +field SCC starts
+    # from its charge response at the previous evaluation and every -h / -field
+    # SCC from the reflected + charges; the trajectory still follows the
+    # oracle's within the exact-Born bars
+    s = subsystem(make_system(1), [0, 3, 5])
+    mode, h = (cd.BORN_FD, 1e-3) if route == "fd" else (cd.BORN_FIELD, 1e-4)
+    n = 5
+    ctx = make_ctx(params, s)
+    masses = params["mass"][s["species"]]
+    r = _t(s["pos"])
+    p = _t(s["vel"] * masses[:, None])
+    qm = torch.zeros(ctx.n_modes, dtype=torch.float64, device=DEV)
+    pm = torch.zeros_like(qm)
+    ctx.init_photons(r, qm, pm)
+    ctx.step(r, p, qm, pm, n, s["dt"], mode, h)
+    assert ctx.sync() == 0
+    be = omd.DFTBBackend(params, s["species"], s["unit_off"], born=route, tol=1e-12, h=h)
+    cav = omd.Cavity(s["omega"], s["k"], s["theta"], s["lam"], s["unit_x"], s["pol"])
+    atom_unit = np.repeat(np.arange(len(s["unit_off"]) - 1), np.diff(s["unit_off"]))
+    st = omd.init_state(be, cav, s["pos"], s["vel"] * masses[:, None], masses, atom_unit)
+    for _ in range(n):
+        omd.step(st, be, cav, s["dt"])
+    rn, pn, qn, pmn = (x.cpu().numpy() for x in (r, p, qm, pm))
+    assert _rel(rn, st["r"]) <= 1e-9 and _rel(pn, st["p"]) <= 1e-8
+    assert _rel(qn, st["q"]) <= 1e-8 and _rel(pmn, st["pm"]) <= 1e-8
+    ctx.close()
+
+
 def test_born_fd_forward_parity(params):
     # the paper's forward differences against the undisplaced dipole
     s = subsystem(make_system(5, n_units=6), [0, 1, 5])
