@@ -108,7 +108,7 @@ def exact_born(params, system, pos_list, route="field", tol=1e-10, log=None):
 
 
 def features_and_targets(params, system, pos_list, born, charges, good=None):
-    """Per species: descriptor rows (FP64 [N_s, 32]) and local-frame targets,
+    """Per species: descriptor rows (FP64 [N_s, SG_N_IN]) and local-frame targets,
     the correction R^T Z R - Q I to the Mulliken replacement (FP64 [N_s, 9]),
     over all snapshots; atoms of units without a clean evaluation (good False)
     are left out."""
